@@ -1,0 +1,13 @@
+"""CPU oracle of the lattice tumour / irradiation simulation (float64, NumPy).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, links or
+executes this package; only the tests, the package smoke check and the
+CPU-baseline leg of the benchmark call it.  It shares no code with the HIP
+library: both are written from the method's description and meet only in the
+tests, on the same seeded inputs.
+
+Modules: philox (Philox4x32-10), model (constants), protocol (validation,
+events, LQ thresholds, counting and sampling of protocols), sim (the lattice
+automaton), stats (two-sample tests used by the trajectory comparisons).
+"""
+from . import model, philox, protocol, sim  # noqa: F401

@@ -1,0 +1,161 @@
+"""Benchmark: protocols/s and lattice-site-steps/s of the batched simulator.
+
+One step = gga_simulate over the whole batch: every (protocol, replica)
+instance simulated from its initial state over the horizon, live counts
+reduced and the per-protocol fitness written.  Default workload: 1,024 random
+protocols x 4 replicas on a 128 x 128 lattice over 20 days (480 steps of one
+hour, 10 diffusion sub-steps each), doses {0.5..2.5} Gy, delays {6..60} h,
+total dose <= 20 Gy.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line with the throughput, the roofline of the simulation
+kernel (VALU-bound: its state never leaves the compute unit) and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic VALU work of one site-substep: per field the neighbour sum
+# (3 adds), the centre-and-reaction multiply-add, the lambda multiply-add,
+# plus the non-negativity clamp of O and G: 6 + 6 + 5 operations.
+OPS_PER_SITE_SUBSTEP = 17
+# MI355X: 256 CUs x 4 SIMD x 16 lanes issue one full-rate 32-bit VALU
+# operation per lane per clock at 2.4 GHz (packed FP32 excluded).
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _oracle_instance(args):
+    md, L, horizon, substeps, dose, gap, nfrac, p, r, seed = args
+    from oracle import protocol, sim
+    from oracle.model import Params
+    prm = Params.from_dict(md)
+    ev = protocol.events(dose, gap, nfrac, horizon, prm)
+    t0 = time.perf_counter()
+    _, _, traj = sim.run_instance(prm, L, horizon, substeps, ev, p, r, seed)
+    return int(traj[-1]), time.perf_counter() - t0
+
+
+def cpu_baseline(md, wl, dose, gap, nfrac, n_protocols=2):
+    """The oracle on the first n_protocols protocols x R replicas, one instance
+    per worker process."""
+    R = wl["R"]
+    jobs = [(md, wl["L"], wl["horizon"], wl["substeps"], dose[p], gap[p], int(nfrac[p]), p, r, wl["seed"])
+            for p in range(n_protocols) for r in range(R)]
+    workers = min(len(jobs), os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_instance, jobs)
+    wall = time.perf_counter() - t0
+    cpu_s = sum(t for _, t in res)
+    inst_per_s = len(jobs) / wall
+    return {
+        "value": inst_per_s / R, "unit": "protocols/s", "cores": workers, "kind": "oracle",
+        "sample": f"{n_protocols} protocols x {R} replicas of the same workload, whole horizon, "
+                  f"one instance per process; {wall:.1f} s wall, {cpu_s:.1f} s CPU",
+        "site_steps_per_s": len(jobs) * wl["L"] ** 2 * wl["horizon"] / wall,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batched", choices=["batched", "plain"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the simulator shards by instance with no "
+              "inter-GPU traffic, and this build runs and reports a single MI355X only.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2303_08123_amd as gga
+    from paper_2303_08123_amd import workloads
+
+    md = gga.load_model()
+    if args.workload == "batched":
+        wl = dict(workloads.CONFIG2)
+        dose, gap, nfrac = workloads.config2_protocols(wl["P"], wl["K"], seed=0, cap=wl["dose_cap"])
+    else:
+        wl = dict(workloads.CONFIG1)
+        dose, gap, nfrac = workloads.config1_protocols()
+        wl["P"], wl["K"] = 1, dose.shape[1]
+    P, R, L, N, S = wl["P"], wl["R"], wl["L"], wl["horizon"], wl["substeps"]
+    cfg = gga.make_cfg(L, N, R, seed=wl["seed"], substeps=S, dose_cap=wl["dose_cap"])
+    params = gga.make_params(md)
+    dev = torch.device("cuda:0")
+    d_d = torch.from_numpy(dose).to(dev)
+    g_d = torch.from_numpy(gap).to(dev)
+    n_d = torch.from_numpy(nfrac).to(dev)
+    out = (torch.empty((P, R), dtype=torch.int32, device=dev),
+           torch.empty((P,), dtype=torch.float32, device=dev), None)
+    stream = torch.cuda.current_stream()
+
+    for i in range(args.warmup):
+        gga.simulate(params, cfg, d_d, g_d, n_d, out=out, stream=stream)
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        gga.simulate(params, cfg, d_d, g_d, n_d, out=out, stream=stream)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    log(f"timed {args.steps} steps: wall {wall:.3f} s, per launch {np.mean(launch_ms):.3f} ms")
+
+    live = out[0].cpu().numpy()
+    fit = out[1].cpu().numpy()
+    assert np.all(live >= 0) and np.all(np.isfinite(fit))
+
+    ms_per_step = 1000.0 * wall / args.steps
+    site_steps = P * R * L * L * N
+    kernel_s = float(np.mean(launch_ms)) / 1000.0
+    achieved = OPS_PER_SITE_SUBSTEP * site_steps * S / kernel_s
+    result = {
+        "metric": "protocols/sec (batched simulation: 1024 protocols x 4 replicas, 128x128, 20 days)",
+        "value": P / (ms_per_step / 1000.0),
+        "unit": "protocols/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "protocols": P, "replicas": R, "lattice": L,
+                   "horizon_h": N, "substeps_per_h": S, "fractions": wl["K"], "dose_cap_gy": wl["dose_cap"]},
+        "site_steps_per_s": site_steps / (ms_per_step / 1000.0),
+        "mean_fitness": float(fit.mean()),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "Top/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "kernel": "sim_kernel", "kernel_ms": kernel_s * 1000.0},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(md, wl, dose, gap, nfrac, n_protocols=min(2, P))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * gga.h - C ABI of the MI355X (gfx950) lattice tumour / irradiation simulator.
+ *
+ * The calls follow the paper's statement of the search problem (Results,
+ * "Defining the search problem"): a protocol is a sequence of k (dose, delay)
+ * pairs whose first delay counts from the start of the simulation, the total
+ * dose is capped, and a protocol's fitness comes from the number of occupied
+ * lattice sites at the end of the simulated period, averaged over replicate
+ * simulations (Materials and Methods, "The fitness function", equation
+ * final_fit_fun).  A caller creates a population of protocols, simulates each
+ * one R times and reads back the fitness.
+ *
+ * Conventions for every call:
+ *   - return GGA_OK (0) on success or a negative GGA_E_* code; never abort and
+ *     never throw across the ABI;
+ *   - pointers named *_d are device pointers (hipMalloc'ed or torch tensors);
+ *     the caller owns all memory and no call allocates or frees any;
+ *   - stream-ordered calls enqueue on `stream` and return; outputs are valid
+ *     once the stream has completed the work.  No call synchronises a stream;
+ *   - arrays are dense and row-major, shapes given in brackets;
+ *   - identical inputs give bit-identical outputs on every run.
+ *
+ * Cell words (uint16): bits 0-1 state (0 EMPTY, 1 PROLIF, 2 QUIESC, 3 DEAD),
+ * bits 2-9 age in hours (saturating at 255); EMPTY sites hold 0.
+ * Field state (float32): [instance][3][L][L], planes oxygen, glucose, acidity,
+ * in normalised units.  Instance i = p * R + r (protocol p, replica r).
+ */
+#ifndef GGA_H
+#define GGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GGA_ABI_VERSION 1
+
+/* Error codes. */
+#define GGA_OK 0
+#define GGA_E_ARG (-1)          /* null pointer, negative size, size overflow   */
+#define GGA_E_ABI (-2)          /* struct_size does not match this library      */
+#define GGA_E_UNSUPPORTED (-3)  /* no kernel for this lattice side / sub-steps  */
+#define GGA_E_HIP (-4)          /* HIP runtime error; see gga_last_hip_error()  */
+#define GGA_E_PARAM (-5)        /* model constant out of range (e.g. lambda)    */
+#define GGA_E_ALPHABET (-6)     /* alphabet admits no protocol / too large      */
+
+/* Per-protocol status written by gga_validate (and used by gga_simulate). */
+#define GGA_PROTO_OK 0
+#define GGA_PROTO_NFRAC 1       /* nfrac < 0 or nfrac > K                       */
+#define GGA_PROTO_DOSE 2        /* a used dose is negative or not finite        */
+#define GGA_PROTO_CAP 3         /* total dose > dose_cap + 1e-6 Gy              */
+#define GGA_PROTO_GAP 4         /* delay_1 < 0, or delay_j < 1 h for j >= 2     */
+
+/* Model constants (the paper defers the model's equations to earlier work;
+ * these are the synthetic model's inputs).  Set struct_size =
+ * sizeof(gga_params). */
+typedef struct gga_params {
+    uint32_t struct_size;
+    float lambda[3];        /* FTCS numbers D dtau / h^2 for O, G, H; each in [0, 1/4] */
+    float kappa[3];         /* O and G uptake, H production per sub-step at activity 1;
+                               O uptake must be > 0, the others >= 0                    */
+    float ghost[3];         /* Dirichlet values outside the lattice                      */
+    float init[3];          /* initial uniform field values                              */
+    float activity[4];      /* activity of EMPTY, PROLIF, QUIESC, DEAD sites             */
+    float theta_O_quiesce, theta_G_quiesce;              /* quiescent below these */
+    float theta_O_death, theta_G_death, theta_H_death;   /* necrosis beyond these */
+    int32_t T_min;          /* minimum age (h) before a cell may divide                  */
+    int32_t T_lys;          /* hours from death to lysis                                  */
+    int32_t A0;             /* initial ages uniform on 0 .. A0-1                          */
+    int32_t seed_radius;    /* initial disc (x-c)^2 + (y-c)^2 <= r^2, c = L/2             */
+    int32_t class_age[2];   /* sensitivity classes: age < a0, a0 <= age < a1, age >= a1   */
+    double P_div;           /* hourly division probability once age >= T_min             */
+    double alpha, beta;     /* linear-quadratic survival exp(-alpha x - beta x^2)        */
+    double m[4];            /* x = m[class] * dose; classes young, mid, old, quiescent   */
+} gga_params;
+
+/* One simulation batch.  Set struct_size = sizeof(gga_sim_cfg). */
+typedef struct gga_sim_cfg {
+    uint32_t struct_size;
+    int32_t L;              /* lattice side; 64 and 128 are supported            */
+    int32_t horizon;        /* steps (model hours) simulated by gga_simulate     */
+    int32_t substeps;       /* diffusion sub-steps per step, 1 .. 64             */
+    int32_t R;              /* replicas per protocol, >= 1                       */
+    uint32_t flags;         /* reserved, must be 0                               */
+    uint64_t seed;          /* Philox key (lo, hi words)                         */
+    double dose_cap;        /* total-dose cap in Gy                              */
+} gga_sim_cfg;
+
+/* Alphabet for gga_population_random.  Set struct_size = sizeof(gga_alphabet). */
+#define GGA_ALPHABET_MAX 64
+#define GGA_KMAX 64
+typedef struct gga_alphabet {
+    uint32_t struct_size;
+    int32_t n_dose;                      /* number of allowed doses, 1 .. 64        */
+    int32_t n_gap;                       /* number of allowed delays, 1 .. 64       */
+    int32_t kmin, kmax;                  /* fraction-count range, 0 <= kmin <= kmax */
+    float dose_quantum;                  /* Gy per dose unit                        */
+    float cap;                           /* total-dose cap in Gy                    */
+    int32_t dose_q[GGA_ALPHABET_MAX];    /* allowed doses in quanta, increasing, >0 */
+    int32_t gaps[GGA_ALPHABET_MAX];      /* allowed delays in hours, >= 1           */
+} gga_alphabet;
+
+/* ABI version (GGA_ABI_VERSION). */
+int gga_version(void);
+
+/* Static description of an error code; never NULL. */
+const char* gga_strerror(int code);
+
+/* hipError_t of the last call on this thread that returned GGA_E_HIP. */
+int gga_last_hip_error(void);
+
+/*
+ * Validate protocols on the host.  dose[P][K], gap_h[P][K], nfrac[P] and
+ * status[P] are HOST pointers.  Writes one GGA_PROTO_* code per protocol; the
+ * rules are checked in the order nfrac, then per fraction dose and delay, then
+ * the cap (total summed in double in index order).  Synchronous.
+ * Errors: GGA_E_ARG, GGA_E_ABI.
+ */
+int gga_validate(const gga_sim_cfg* cfg, const float* dose, const int32_t* gap_h,
+                 const int32_t* nfrac, int32_t P, int32_t K, int32_t* status);
+
+/*
+ * Create a population: P random protocols drawn on the device.  For protocol
+ * p the fraction count k is uniform on kmin..kmax; the k doses are uniform
+ * over all length-k sequences from the alphabet whose total is within the cap
+ * (sequential sampling from a counting table, equal in law to rejection
+ * sampling); the k delays are independent and uniform over the allowed delays.
+ * Random words come from Philox4x32-10 blocks (p, i, 0x504F5055, 0) keyed by
+ * `seed`, i = position, i = 0xFFFFFFFF for the fraction count.
+ * Outputs dose_d[P][K] (Gy), gap_h_d[P][K], nfrac_d[P]; entries past nfrac
+ * are 0.  Requires kmax <= K <= GGA_KMAX.
+ * Errors: GGA_E_ARG, GGA_E_ABI, GGA_E_ALPHABET, GGA_E_HIP.
+ */
+int gga_population_random(const gga_alphabet* a, int32_t P, int32_t K, uint64_t seed,
+                          float* dose_d, int32_t* gap_h_d, int32_t* nfrac_d,
+                          hipStream_t stream);
+
+/*
+ * Simulate and score.  Runs every (protocol, replica) instance from the
+ * initial state for cfg->horizon steps on the device: fraction j of protocol
+ * p (dose > 0, time t_j = delay_1 + .. + delay_j < horizon) is applied at the
+ * start of step t_j; each step diffuses the fields cfg->substeps times and then
+ * updates the cells.
+ *   dose_d[P][K], gap_h_d[P][K], nfrac_d[P]  protocols (device)
+ *   live_d[P][R]     live (PROLIF + QUIESC) sites after the last step
+ *   fitness_d[P]     mean of live over replicas (the fitness to minimise; the
+ *                    paper's score is L*L - fitness)
+ *   traj_d[P][R][horizon]  live count after every step, or NULL
+ * A protocol that breaks a GGA_PROTO_* rule is not simulated: its live entries
+ * are -1 and its fitness is NaN.
+ * Errors: GGA_E_ARG, GGA_E_ABI, GGA_E_UNSUPPORTED, GGA_E_PARAM, GGA_E_HIP.
+ */
+int gga_simulate(const gga_params* params, const gga_sim_cfg* cfg,
+                 const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d,
+                 int32_t P, int32_t K, int32_t* live_d, float* fitness_d, int32_t* traj_d,
+                 hipStream_t stream);
+
+/*
+ * Write the initial state of P * cfg->R instances: fields_d[P*R][3][L][L]
+ * (float32) and cells_d[P*R][L][L] (uint16 words).  Same kernel as
+ * gga_simulate, run for zero steps.
+ * Errors: as gga_simulate.
+ */
+int gga_state_init(const gga_params* params, const gga_sim_cfg* cfg, int32_t P,
+                   float* fields_d, uint16_t* cells_d, hipStream_t stream);
+
+/*
+ * Advance the given states of P * cfg->R instances by `nsteps` steps, from
+ * step n0 (events and random words are those of steps n0 .. n0+nsteps-1), in
+ * place.  live_d[P][R] receives the final live counts and traj_d (or NULL)
+ * [P][R][nsteps] the count after every step.  Invalid protocols leave their
+ * states untouched and get live = -1.  Same kernel as gga_simulate; a test
+ * hook for stepping from a known state.
+ * Errors: as gga_simulate.
+ */
+int gga_state_run(const gga_params* params, const gga_sim_cfg* cfg,
+                  const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d,
+                  int32_t P, int32_t K, int32_t n0, int32_t nsteps,
+                  float* fields_d, uint16_t* cells_d, int32_t* live_d, int32_t* traj_d,
+                  hipStream_t stream);
+
+/*
+ * Philox4x32-10 blocks (Salmon et al., SC'11) from the device implementation
+ * the simulator uses: out_d[i][0..3] = Philox(counter ctr_d[i][0..3], key
+ * (seed lo, seed hi)) for i < n.  A test hook.
+ * Errors: GGA_E_ARG, GGA_E_HIP.
+ */
+int gga_philox_fill(const uint32_t* ctr_d, uint64_t seed, uint32_t* out_d, int64_t n,
+                    hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GGA_H */

@@ -139,11 +139,11 @@ def sample_population(alphabet, P, K, seed):
     cap), and the delay is gaps[floor(w2 * len(gaps) / 2**32)].
     Entries past k are zero.
     """
-    q = float(alphabet["dose_quantum"])
+    q = float(np.float32(alphabet["dose_quantum"]))   # single-precision inputs
     dose_q = [int(v) for v in alphabet["dose_q"]]
     gaps = [int(v) for v in alphabet["gaps"]]
     kmin, kmax = int(alphabet["kmin"]), int(alphabet["kmax"])
-    cap_q = int(math.floor(float(alphabet["cap"]) / q + 1e-9))
+    cap_q = int(math.floor(float(np.float32(alphabet["cap"])) / q + 1e-9))
     C = completion_table(dose_q, kmax, cap_q)
     if C[kmax, cap_q] == 0.0:
         raise ValueError("alphabet admits no protocol with kmax fractions under the cap")

@@ -1,0 +1,502 @@
+// Resident simulation kernel: one workgroup advances one (protocol, replica)
+// instance through all of its steps without leaving the compute unit.
+//
+// Layout.  L = 64 * CPL.  Wave w owns lattice rows [w*RPT, (w+1)*RPT); lane l
+// owns columns [l*CPL, (l+1)*CPL).  The three float32 fields of a thread's
+// RPT x CPL sites live in VGPRs for the whole run; the uint16 cell words live
+// in LDS.  One diffusion sub-step needs, per wave, only the row above and the
+// row below its slab from the neighbouring waves (an LDS exchange of 2 rows),
+// while left/right neighbours come from the adjacent lane through DPP lane
+// shifts fused into the VALU adds.  A wave's 64 lanes span a whole lattice row,
+// so the lane shifts' zero fill at lanes 0 and 63 is exactly the missing
+// neighbour outside the lattice; the Dirichlet ghost value enters through a
+// per-site constant added to the reaction term.
+//
+// The method (Materials and Methods: nutrient and waste diffusion, cell
+// cycle, quiescence and death driven by the local environment, irradiation
+// damage; fitness from the final number of occupied sites, equation
+// final_fit_fun) with the synthetic model's rules:
+//   step n:  (1) fraction at n?  live cell of class c survives iff w1 < T_c
+//            (2) activity a = act[state], frozen for the hour
+//            (3) `substeps` FTCS sub-steps
+//                c' = c + lam (N + S + E + W - 4c) - kappa a  (O, G; then max(., 0))
+//                H' = H + lam (N + S + E + W - 4H) + kappa a
+//            (4) synchronous cell update from the snapshot (lysis, environment,
+//                division proposals into free von Neumann neighbours, conflict
+//                resolution by the smallest key)
+//            (5) live count (PROLIF + QUIESC) by wave reduction.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gga_device.h"
+#include "gga_internal.h"
+
+namespace gga {
+namespace {
+
+constexpr uint32_t NONE_KEY = 0xFFFFFFFFu;
+constexpr uint32_t INIT_STEP = 0xFFFFFFFFu;
+constexpr int EMPTY = 0, PROLIF = 1, QUIESC = 2, DEAD = 3;
+
+// 32-bit linear-quadratic survival threshold, evaluated in float64 exactly as
+// written: x = m d, S = exp(-alpha x - beta x x), T = min(floor(S 2^32), 2^32-1).
+#pragma clang fp contract(off)
+__device__ uint32_t lq_threshold(double d, double m, double alpha, double beta) {
+    const double x = m * d;
+    const double e = -(alpha * x) - (beta * x) * x;
+    const double s = exp(e) * 4294967296.0;
+    const double f = floor(s);
+    return f >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)f;
+}
+#pragma clang fp contract(on)
+
+template <int CPL, int RPT>
+struct Geo {
+    static constexpr int L = 64 * CPL;
+    static constexpr int NWAVE = L / RPT;
+    static constexpr int NT = 64 * NWAVE;
+    static constexpr int HALO = NWAVE * 2 * 3 * L;   // one buffer: [wave][top/bottom][field][L]
+    static constexpr int POOL = (2 * HALO > L * L) ? 2 * HALO : L * L;
+    static_assert(L % RPT == 0 && NWAVE <= 16, "workgroup above 1024 threads");
+    static_assert(RPT * CPL <= 32, "per-thread site masks are 32 bits wide");
+};
+
+template <int CPL, int RPT>
+__global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
+    using G = Geo<CPL, RPT>;
+    constexpr int L = G::L;
+    constexpr int NWAVE = G::NWAVE;
+
+    __shared__ uint16_t s_cell[L * L];
+    __shared__ uint32_t s_pool[G::POOL];       // halo double buffer, then division keys
+    __shared__ int s_ev_step[GGA_KMAX];
+    __shared__ float s_ev_dose[GGA_KMAX];
+    __shared__ uint32_t s_ev_thr[GGA_KMAX][4];
+    __shared__ int s_nev, s_valid;
+    __shared__ int s_count[2];
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int inst = blockIdx.x;
+    const int p = inst / a.R;
+    const int r = inst - p * a.R;
+    const int y0 = wave * RPT;
+    const int x0 = lane * CPL;
+    const gga_params& P = a.prm;
+
+    // ---- protocol: validity and irradiation events (thread 0) ----
+    if (tid == 0) {
+        const int k = a.nfrac ? a.nfrac[p] : 0;
+        int valid = (k >= 0 && k <= a.K);
+        int nev = 0;
+        double total = 0.0;
+        long long t = 0;
+        for (int j = 0; valid && j < k; ++j) {
+            const float d = a.dose[(size_t)p * a.K + j];
+            const int g = a.gap[(size_t)p * a.K + j];
+            if (!(d >= 0.0f) || !isfinite(d)) { valid = 0; break; }
+            if (g < (j == 0 ? 0 : 1)) { valid = 0; break; }
+            total += (double)d;
+            t += g;
+            if (d > 0.0f && t >= a.n0 && t < (long long)a.n0 + a.nsteps) {
+                s_ev_step[nev] = (int)t;
+                s_ev_dose[nev] = d;
+                ++nev;
+            }
+        }
+        if (valid && total > a.dose_cap + 1e-6) valid = 0;
+        s_valid = valid;
+        s_nev = nev;
+        s_count[0] = 0;
+        s_count[1] = 0;
+    }
+    __syncthreads();
+    if (!s_valid) {
+        if (tid == 0 && a.live) a.live[inst] = -1;
+        return;                                   // uniform across the workgroup
+    }
+    const int nev = s_nev;
+    for (int e = tid; e < 4 * nev; e += G::NT)
+        s_ev_thr[e >> 2][e & 3] = lq_threshold((double)s_ev_dose[e >> 2], P.m[e & 3], P.alpha, P.beta);
+
+    // ---- state: fields in registers, cells in LDS ----
+    float F[3][RPT][CPL];
+    const size_t plane = (size_t)L * L;
+    if (a.mode & MODE_LOAD) {
+        const float* src = a.fields + (size_t)inst * 3 * plane;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    F[f][i][c] = src[f * plane + (size_t)(y0 + i) * L + x0 + c];
+        const uint16_t* cs = a.cells + (size_t)inst * plane;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+                s_cell[(y0 + i) * L + x0 + c] = cs[(size_t)(y0 + i) * L + x0 + c];
+    } else {
+        const int ctr = L / 2;
+        const int rad2 = P.seed_radius * P.seed_radius;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) F[f][i][c] = P.init[f];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int y = y0 + i, x = x0 + c;
+                uint16_t w = 0;
+                if ((x - ctr) * (x - ctr) + (y - ctr) * (y - ctr) <= rad2) {
+                    const Block4 b = philox10(y * L + x, INIT_STEP, r, p, a.seed_lo, a.seed_hi);
+                    const uint32_t age = (uint32_t)(((uint64_t)b.w0 * (uint32_t)P.A0) >> 32);
+                    w = (uint16_t)(PROLIF | (age << 2));
+                }
+                s_cell[y * L + x] = w;
+            }
+    }
+
+    // Per-field constants.
+    float lam[3], cen[3], kap[3], gst[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        lam[f] = P.lambda[f];
+        cen[f] = 1.0f - 4.0f * P.lambda[f];
+        kap[f] = (f < 2) ? -P.kappa[f] : P.kappa[f];
+        gst[f] = P.ghost[f];
+    }
+    const float actv[4] = {P.activity[0], P.activity[1], P.activity[2], P.activity[3]};
+    const uint32_t T_div = (P.P_div >= 1.0) ? 0xFFFFFFFFu
+                          : (uint32_t)floor(P.P_div * 4294967296.0);
+    const int T_min = P.T_min, T_lys = P.T_lys;
+    const int ca0 = P.class_age[0], ca1 = P.class_age[1];
+    const float thOq = P.theta_O_quiesce, thGq = P.theta_G_quiesce;
+    const float thOd = P.theta_O_death, thGd = P.theta_G_death, thHd = P.theta_H_death;
+    // Ghost flux through the left / right lattice edge, folded into the
+    // reaction constant of the edge columns (the lane shifts deliver 0 there).
+    const bool left_edge = (lane == 0), right_edge = (lane == 63);
+    // R_f = rho_f Ro + e_f:  rho_f = kappa_f' / kappa_O' (signed uptake; the
+    // host requires kappa_O > 0), and e_f = lam_f g_f - rho_f lam_O g_O on an
+    // edge column, 0 elsewhere.
+    float rho[3], eoff[3][CPL];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) rho[f] = kap[f] / kap[0];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const bool edge = (c == 0 && left_edge) || (c == CPL - 1 && right_edge);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+            eoff[f][c] = edge ? lam[f] * gst[f] - rho[f] * (lam[0] * gst[0]) : 0.0f;
+    }
+
+    int ev = 0;
+    int count = 0;
+    __syncthreads();
+
+    for (int n = a.n0; n < a.n0 + a.nsteps; ++n) {
+        // (1) irradiation: every live cell draws w1 against its class threshold
+        if (ev < nev && s_ev_step[ev] == n) {
+            const uint32_t t0 = s_ev_thr[ev][0], t1 = s_ev_thr[ev][1];
+            const uint32_t t2 = s_ev_thr[ev][2], t3 = s_ev_thr[ev][3];
+            uint32_t live_mask = 0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int st = s_cell[(y0 + i) * L + x0 + c] & 3;
+                    if (st == PROLIF || st == QUIESC) live_mask |= 1u << (i * CPL + c);
+                }
+            while (live_mask) {
+                const int idx = __builtin_ctz(live_mask);
+                live_mask &= live_mask - 1;
+                const int site = (y0 + idx / CPL) * L + x0 + idx % CPL;
+                const uint32_t w = s_cell[site];
+                const int st = w & 3, age = w >> 2;
+                const uint32_t thr = (st == QUIESC) ? t3 : (age < ca0 ? t0 : (age < ca1 ? t1 : t2));
+                const Block4 b = philox10(site, n, r, p, a.seed_lo, a.seed_hi);
+                if (b.w1 >= thr) s_cell[site] = DEAD;
+            }
+            ++ev;
+        }
+
+        // (2) reaction constants for the hour.  Only oxygen's term is kept per
+        // site, Ro = -kappa_O a (+ lam_O g_O on an edge column); the glucose and
+        // acid terms are affine in it, R_f = rho_f Ro + e_f with per-lane
+        // constants, which saves two VGPRs per site for one FMA each.
+        float Ro[RPT][CPL];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const bool edge = (c == 0 && left_edge) || (c == CPL - 1 && right_edge);
+                const float act = actv[s_cell[(y0 + i) * L + x0 + c] & 3];
+                Ro[i][c] = fmaf(kap[0], act, edge ? lam[0] * gst[0] : 0.0f);
+            }
+
+        // (3) diffusion sub-steps
+        for (int s = 0; s < a.substeps; ++s) {
+            // Keep the glucose / acid terms from being hoisted out of the loop
+            // (they would cost two live VGPRs per site): Ro is opaque here.
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) asm volatile("" : "+v"(Ro[i][c]));
+            float* hb = reinterpret_cast<float*>(s_pool) + (s & 1) * G::HALO;
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    hb[((wave * 2 + 0) * 3 + f) * L + x0 + c] = F[f][0][c];
+                    hb[((wave * 2 + 1) * 3 + f) * L + x0 + c] = F[f][RPT - 1][c];
+                }
+            __syncthreads();
+            float up[3][CPL], dn[3][CPL];
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    up[f][c] = (wave > 0) ? hb[(((wave - 1) * 2 + 1) * 3 + f) * L + x0 + c] : gst[f];
+                    dn[f][c] = (wave < NWAVE - 1) ? hb[(((wave + 1) * 2 + 0) * 3 + f) * L + x0 + c] : gst[f];
+                }
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                float nw[3][CPL];
+#pragma unroll
+                for (int f = 0; f < 3; ++f)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const float below = (i < RPT - 1) ? F[f][i + 1][c] : dn[f][c];
+                        const float west = (c > 0) ? F[f][i][c - 1] : lane_from_left(F[f][i][CPL - 1]);
+                        const float east = (c < CPL - 1) ? F[f][i][c + 1] : lane_from_right(F[f][i][0]);
+                        const float sum = (up[f][c] + below) + (west + east);
+                        const float rx = (f == 0) ? Ro[i][c] : fmaf(rho[f], Ro[i][c], eoff[f][c]);
+                        float v = fmaf(lam[f], sum, fmaf(F[f][i][c], cen[f], rx));
+                        if (f < 2) v = fmaxf(v, 0.0f);
+                        nw[f][c] = v;
+                    }
+#pragma unroll
+                for (int f = 0; f < 3; ++f)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        up[f][c] = F[f][i][c];
+                        F[f][i][c] = nw[f][c];
+                    }
+            }
+        }
+
+        // (4) cell update.  The key array reuses the halo buffer.
+        __syncthreads();
+        uint32_t* key = s_pool;
+        uint32_t nwd[RPT][CPL];
+        uint32_t empty_mask = 0, cand_mask = 0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int y = y0 + i, x = x0 + c, site = y * L + x, idx = i * CPL + c;
+                const uint32_t w = s_cell[site];
+                const int st = w & 3, age = w >> 2;
+                const int older = age < 255 ? age + 1 : 255;
+                uint32_t out = 0;
+                if (st == EMPTY) {
+                    empty_mask |= 1u << idx;
+                } else if (st == DEAD) {
+                    out = (older >= T_lys) ? 0u : (uint32_t)(DEAD | (older << 2));
+                } else {
+                    const float O = F[0][i][c], Gl = F[1][i][c], H = F[2][i][c];
+                    if (Gl < thGd || O < thOd || H > thHd) {
+                        out = DEAD;
+                    } else if (O < thOq || Gl < thGq) {
+                        out = (uint32_t)(QUIESC | (age << 2));
+                    } else {
+                        out = (uint32_t)(PROLIF | (older << 2));
+                        if (age >= T_min) {
+                            uint32_t fm = 0;
+                            if (y > 0 && (s_cell[site - L] & 3) == EMPTY) fm |= 1u;
+                            if (x < L - 1 && (s_cell[site + 1] & 3) == EMPTY) fm |= 2u;
+                            if (y < L - 1 && (s_cell[site + L] & 3) == EMPTY) fm |= 4u;
+                            if (x > 0 && (s_cell[site - 1] & 3) == EMPTY) fm |= 8u;
+                            if (fm) cand_mask |= 1u << idx;
+                        }
+                    }
+                }
+                nwd[i][c] = out;
+                key[site] = NONE_KEY;
+            }
+        // proposals of this thread's candidates
+        uint32_t prop_mask = 0;
+        {
+            uint32_t m = cand_mask;
+            while (m) {
+                const int idx = __builtin_ctz(m);
+                m &= m - 1;
+                const int y = y0 + idx / CPL, x = x0 + idx % CPL, site = y * L + x;
+                const Block4 b = philox10(site, n, r, p, a.seed_lo, a.seed_hi);
+                if (b.w3 < T_div) {
+                    uint32_t fm = 0;              // free neighbours, bits N E S W
+                    if (y > 0 && (s_cell[site - L] & 3) == EMPTY) fm |= 1u;
+                    if (x < L - 1 && (s_cell[site + 1] & 3) == EMPTY) fm |= 2u;
+                    if (y < L - 1 && (s_cell[site + L] & 3) == EMPTY) fm |= 4u;
+                    if (x > 0 && (s_cell[site - 1] & 3) == EMPTY) fm |= 8u;
+                    const uint32_t kth = (uint32_t)(((uint64_t)b.w0 * __builtin_popcount(fm)) >> 32);
+                    uint32_t rest = fm;
+                    for (uint32_t j = 0; j < kth; ++j) rest &= rest - 1;
+                    const uint32_t dir = __builtin_ctz(rest);              // 0 N, 1 E, 2 S, 3 W
+                    key[site] = ((b.w2 >> 3) << 2) | ((dir + 2) & 3);      // + direction seen from target
+                    prop_mask |= 1u << idx;
+                }
+            }
+        }
+        __syncthreads();
+        // smallest key among the proposers pointing at site t
+        auto best_at = [&](int t) -> uint32_t {
+            const int ty = t / L, tx = t - ty * L;
+            uint32_t best = NONE_KEY, k;
+            if (ty > 0)     { k = key[t - L]; if (k != NONE_KEY && (k & 3) == 0) best = min(best, k); }
+            if (tx < L - 1) { k = key[t + 1]; if (k != NONE_KEY && (k & 3) == 1) best = min(best, k); }
+            if (ty < L - 1) { k = key[t + L]; if (k != NONE_KEY && (k & 3) == 2) best = min(best, k); }
+            if (tx > 0)     { k = key[t - 1]; if (k != NONE_KEY && (k & 3) == 3) best = min(best, k); }
+            return best;
+        };
+        uint32_t won_mask = 0;
+        {
+            uint32_t m = prop_mask;
+            while (m) {
+                const int idx = __builtin_ctz(m);
+                m &= m - 1;
+                const int site = (y0 + idx / CPL) * L + x0 + idx % CPL;
+                const uint32_t k = key[site];
+                const int d = k & 3;                          // this cell as seen from its target
+                const int t = site - (d == 0 ? -L : d == 1 ? 1 : d == 2 ? L : -1);
+                if (best_at(t) == k) won_mask |= 1u << idx;
+            }
+        }
+        int live = 0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int idx = i * CPL + c;
+                const int site = (y0 + i) * L + x0 + c;
+                uint32_t out = nwd[i][c];
+                if ((empty_mask >> idx) & 1u) {
+                    if (best_at(site) != NONE_KEY) out = PROLIF;
+                }
+                if ((won_mask >> idx) & 1u) out = PROLIF;
+                s_cell[site] = (uint16_t)out;
+                const int st = out & 3;
+                live += (st == PROLIF || st == QUIESC);
+            }
+        // (5) live count: wave reduction, one LDS atomic per wave
+        live = wave_sum(live);
+        if (lane == 0) atomicAdd(&s_count[n & 1], live);
+        __syncthreads();
+        if (tid == 0) {
+            count = s_count[n & 1];
+            s_count[(n + 1) & 1] = 0;
+            if (a.traj) a.traj[(size_t)inst * a.nsteps + (n - a.n0)] = count;
+        }
+    }
+
+    if (a.nsteps == 0) {
+        int live = 0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int st = s_cell[(y0 + i) * L + x0 + c] & 3;
+                live += (st == PROLIF || st == QUIESC);
+            }
+        live = wave_sum(live);
+        if (lane == 0) atomicAdd(&s_count[0], live);
+        __syncthreads();
+        if (tid == 0) count = s_count[0];
+    }
+    if (tid == 0 && a.live) a.live[inst] = count;
+
+    if (a.mode & MODE_STORE) {
+        float* dst = a.fields + (size_t)inst * 3 * plane;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    dst[f * plane + (size_t)(y0 + i) * L + x0 + c] = F[f][i][c];
+        __syncthreads();
+        uint16_t* cd = a.cells + (size_t)inst * plane;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+                cd[(size_t)(y0 + i) * L + x0 + c] = s_cell[(y0 + i) * L + x0 + c];
+    }
+}
+
+__global__ void fitness_kernel(const int32_t* live, int P, int R, float* fitness) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    long long sum = 0;
+    bool bad = false;
+    for (int r = 0; r < R; ++r) {
+        const int v = live[(size_t)p * R + r];
+        bad |= v < 0;
+        sum += v;
+    }
+    fitness[p] = bad ? __builtin_nanf("") : (float)((double)sum / (double)R);
+}
+
+__global__ void philox_fill_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
+                                   long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Block4 b = philox10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
+    out[4 * i] = b.w0;
+    out[4 * i + 1] = b.w1;
+    out[4 * i + 2] = b.w2;
+    out[4 * i + 3] = b.w3;
+}
+
+template <int CPL, int RPT>
+hipError_t launch_sim(const SimArgs& a, int n_inst, hipStream_t stream) {
+    using G = Geo<CPL, RPT>;
+    hipLaunchKernelGGL((sim_kernel<CPL, RPT>), dim3(n_inst), dim3(G::NT), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool sim_supported(int L) { return L == 64 || L == 128; }
+
+hipError_t launch_simulation(const SimArgs& a, int L, int n_inst, hipStream_t stream) {
+    if (n_inst <= 0) return hipSuccess;
+    switch (L) {
+        case 64: return launch_sim<1, 4>(a, n_inst, stream);
+        case 128: return launch_sim<2, 16>(a, n_inst, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fitness(const int32_t* live, int P, int R, float* fitness, hipStream_t stream) {
+    if (P <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fitness_kernel, dim3((P + 255) / 256), dim3(256), 0, stream, live, P, R, fitness);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox_fill(const uint32_t* ctr, uint64_t seed, uint32_t* out, long long n,
+                              hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const long long blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(philox_fill_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, ctr,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), out, n);
+    return hipGetLastError();
+}
+
+}  // namespace gga

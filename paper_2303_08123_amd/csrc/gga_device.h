@@ -38,6 +38,13 @@ __device__ __forceinline__ float lane_from_right(float v) {  // lane l <- lane l
         0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
 }
 
+__device__ __forceinline__ uint32_t lane_from_left_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t lane_from_right_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, true);
+}
+
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -51,6 +51,32 @@ __device__ uint32_t lq_threshold(double d, double m, double alpha, double beta) 
 }
 #pragma clang fp contract(on)
 
+// CPL consecutive uint16 cell words of one row, read or written with one
+// LDS access (the address is 2*CPL-byte aligned: x0 = lane * CPL).
+template <int CPL>
+__device__ __forceinline__ void load_words(const uint16_t* p, uint32_t (&w)[CPL]) {
+    if constexpr (CPL == 1) {
+        w[0] = p[0];
+    } else if constexpr (CPL == 2) {
+        const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+        w[0] = v & 0xFFFFu; w[1] = v >> 16;
+    } else {
+        static_assert(CPL == 4, "CPL must be 1, 2 or 4");
+        const uint2 v = *reinterpret_cast<const uint2*>(p);
+        w[0] = v.x & 0xFFFFu; w[1] = v.x >> 16; w[2] = v.y & 0xFFFFu; w[3] = v.y >> 16;
+    }
+}
+template <int CPL>
+__device__ __forceinline__ void store_words(uint16_t* p, const uint32_t (&w)[CPL]) {
+    if constexpr (CPL == 1) {
+        p[0] = (uint16_t)w[0];
+    } else if constexpr (CPL == 2) {
+        *reinterpret_cast<uint32_t*>(p) = w[0] | (w[1] << 16);
+    } else {
+        *reinterpret_cast<uint2*>(p) = make_uint2(w[0] | (w[1] << 16), w[2] | (w[3] << 16));
+    }
+}
+
 template <int CPL, int RPT>
 struct Geo {
     static constexpr int L = 64 * CPL;
@@ -60,6 +86,15 @@ struct Geo {
     static constexpr int POOL = (2 * HALO > L * L) ? 2 * HALO : L * L;
     static_assert(L % RPT == 0 && NWAVE <= 16, "workgroup above 1024 threads");
     static_assert(RPT * CPL <= 32, "per-thread site masks are 32 bits wide");
+    static constexpr uint32_t ALL = (RPT * CPL == 32) ? 0xFFFFFFFFu : ((1u << (RPT * CPL)) - 1u);
+    // mask bits of the first / last column of every row (bit idx = i * CPL + c)
+    static constexpr uint32_t col_bits(int c) {
+        uint32_t m = 0;
+        for (int i = 0; i < RPT; ++i) m |= 1u << (i * CPL + c);
+        return m;
+    }
+    static constexpr uint32_t COL_FIRST = col_bits(0);
+    static constexpr uint32_t COL_LAST = col_bits(CPL - 1);
 };
 
 template <int CPL, int RPT>
@@ -69,7 +104,8 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
     constexpr int NWAVE = G::NWAVE;
 
     __shared__ uint16_t s_cell[L * L];
-    __shared__ uint32_t s_pool[G::POOL];       // halo double buffer, then division keys
+    __shared__ uint32_t s_pool[G::POOL];       // halo double buffer, then claim slots
+    __shared__ uint32_t s_claim[L * L / 32];   // one "has a daughter" bit per site
     __shared__ int s_ev_step[GGA_KMAX];
     __shared__ float s_ev_dose[GGA_KMAX];
     __shared__ uint32_t s_ev_thr[GGA_KMAX][4];
@@ -291,109 +327,115 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
             }
         }
 
-        // (4) cell update.  The key array reuses the halo buffer.
-        __syncthreads();
-        uint32_t* key = s_pool;
-        uint32_t nwd[RPT][CPL];
-        uint32_t empty_mask = 0, cand_mask = 0;
+        // (4) cell update, bit-parallel over the thread's RPT x CPL sites
+        // (bit idx = i * CPL + c of 32-bit masks).  Proposers claim an EMPTY
+        // target with ds_min_u32 on best[t] (one slot per site, sharing the
+        // halo pool) and set the target's bit in s_claim; the smallest key's
+        // low two bits name the winner's direction, so no key is kept.
+        __syncthreads();   // the last sub-step's halo reads are done
+        uint32_t* best = s_pool;
+        uint32_t wd[RPT][CPL];
+        uint32_t empty_m = 0, cyc_m = 0, old_m = 0, alive_m = 0;
 #pragma unroll
-        for (int i = 0; i < RPT; ++i)
+        for (int i = 0; i < RPT; ++i) {
+            uint32_t w[CPL];
+            load_words<CPL>(&s_cell[(y0 + i) * L + x0], w);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                const int y = y0 + i, x = x0 + c, site = y * L + x, idx = i * CPL + c;
-                const uint32_t w = s_cell[site];
-                const int st = w & 3, age = w >> 2;
-                const int older = age < 255 ? age + 1 : 255;
-                uint32_t out = 0;
-                if (st == EMPTY) {
-                    empty_mask |= 1u << idx;
-                } else if (st == DEAD) {
-                    out = (older >= T_lys) ? 0u : (uint32_t)(DEAD | (older << 2));
-                } else {
-                    const float O = F[0][i][c], Gl = F[1][i][c], H = F[2][i][c];
-                    if (Gl < thGd || O < thOd || H > thHd) {
-                        out = DEAD;
-                    } else if (O < thOq || Gl < thGq) {
-                        out = (uint32_t)(QUIESC | (age << 2));
-                    } else {
-                        out = (uint32_t)(PROLIF | (older << 2));
-                        if (age >= T_min) {
-                            uint32_t fm = 0;
-                            if (y > 0 && (s_cell[site - L] & 3) == EMPTY) fm |= 1u;
-                            if (x < L - 1 && (s_cell[site + 1] & 3) == EMPTY) fm |= 2u;
-                            if (y < L - 1 && (s_cell[site + L] & 3) == EMPTY) fm |= 4u;
-                            if (x > 0 && (s_cell[site - 1] & 3) == EMPTY) fm |= 8u;
-                            if (fm) cand_mask |= 1u << idx;
-                        }
-                    }
-                }
-                nwd[i][c] = out;
-                key[site] = NONE_KEY;
-            }
-        // proposals of this thread's candidates
-        uint32_t prop_mask = 0;
-        {
-            uint32_t m = cand_mask;
-            while (m) {
-                const int idx = __builtin_ctz(m);
-                m &= m - 1;
-                const int y = y0 + idx / CPL, x = x0 + idx % CPL, site = y * L + x;
-                const Block4 b = philox10(site, n, r, p, a.seed_lo, a.seed_hi);
-                if (b.w3 < T_div) {
-                    uint32_t fm = 0;              // free neighbours, bits N E S W
-                    if (y > 0 && (s_cell[site - L] & 3) == EMPTY) fm |= 1u;
-                    if (x < L - 1 && (s_cell[site + 1] & 3) == EMPTY) fm |= 2u;
-                    if (y < L - 1 && (s_cell[site + L] & 3) == EMPTY) fm |= 4u;
-                    if (x > 0 && (s_cell[site - 1] & 3) == EMPTY) fm |= 8u;
-                    const uint32_t kth = (uint32_t)(((uint64_t)b.w0 * __builtin_popcount(fm)) >> 32);
-                    uint32_t rest = fm;
-                    for (uint32_t j = 0; j < kth; ++j) rest &= rest - 1;
-                    const uint32_t dir = __builtin_ctz(rest);              // 0 N, 1 E, 2 S, 3 W
-                    key[site] = ((b.w2 >> 3) << 2) | ((dir + 2) & 3);      // + direction seen from target
-                    prop_mask |= 1u << idx;
-                }
+                const int idx = i * CPL + c;
+                const uint32_t st = w[c] & 3u, age = w[c] >> 2;
+                const uint32_t older = age < 255u ? age + 1u : 255u;
+                const float O = F[0][i][c], Gl = F[1][i][c], H = F[2][i][c];
+                const bool nec = (Gl < thGd) | (O < thOd) | (H > thHd);
+                const bool starv = (O < thOq) | (Gl < thGq);
+                const bool live = (st == PROLIF) | (st == QUIESC);
+                uint32_t nw = (st == DEAD && (int)older < T_lys) ? (DEAD | (older << 2)) : 0u;
+                nw = live ? (nec ? (uint32_t)DEAD : (starv ? (QUIESC | (age << 2)) : (PROLIF | (older << 2)))) : nw;
+                wd[i][c] = nw;
+                empty_m |= (uint32_t)(st == EMPTY) << idx;
+                cyc_m |= (uint32_t)(live & !nec & !starv) << idx;
+                old_m |= (uint32_t)((int)age >= T_min) << idx;
+                alive_m |= (uint32_t)(live & !nec) << idx;
+                best[(y0 + i) * L + x0 + c] = NONE_KEY;
             }
         }
-        __syncthreads();
-        // smallest key among the proposers pointing at site t
-        auto best_at = [&](int t) -> uint32_t {
-            const int ty = t / L, tx = t - ty * L;
-            uint32_t best = NONE_KEY, k;
-            if (ty > 0)     { k = key[t - L]; if (k != NONE_KEY && (k & 3) == 0) best = min(best, k); }
-            if (tx < L - 1) { k = key[t + 1]; if (k != NONE_KEY && (k & 3) == 1) best = min(best, k); }
-            if (ty < L - 1) { k = key[t + L]; if (k != NONE_KEY && (k & 3) == 2) best = min(best, k); }
-            if (tx > 0)     { k = key[t - 1]; if (k != NONE_KEY && (k & 3) == 3) best = min(best, k); }
-            return best;
-        };
-        uint32_t won_mask = 0;
+        for (int k = tid; k < L * L / 32; k += G::NT) s_claim[k] = 0u;
+        // EMPTY neighbours of every site, as masks for N, E, S, W
+        uint32_t top = 0, bot = 0;
+        if (wave > 0) {
+            uint32_t w[CPL];
+            load_words<CPL>(&s_cell[(y0 - 1) * L + x0], w);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) top |= (uint32_t)((w[c] & 3u) == EMPTY) << c;
+        }
+        if (wave < NWAVE - 1) {
+            uint32_t w[CPL];
+            load_words<CPL>(&s_cell[(y0 + RPT) * L + x0], w);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) bot |= (uint32_t)((w[c] & 3u) == EMPTY) << c;
+        }
+        constexpr uint32_t ALL = G::ALL;
+        constexpr uint32_t C0 = G::COL_FIRST, CL = G::COL_LAST;
+        const uint32_t fN = ((empty_m << CPL) | top) & ALL;
+        const uint32_t fS = (empty_m >> CPL) | (bot << ((RPT - 1) * CPL));
+        const uint32_t from_left = lane_from_left_u32(empty_m), from_right = lane_from_right_u32(empty_m);
+        const uint32_t fW = (CPL == 1) ? from_left : (((empty_m << 1) & ~C0 & ALL) | ((from_left >> (CPL - 1)) & C0));
+        const uint32_t fE = (CPL == 1) ? from_right : (((empty_m >> 1) & ~CL) | ((from_right << (CPL - 1)) & CL));
+        const uint32_t cand = cyc_m & old_m & (fN | fE | fS | fW);
+        __syncthreads();   // best[] and s_claim are reset
+        uint32_t prop_m = 0;
+        uint64_t dirs = 0;
         {
-            uint32_t m = prop_mask;
+            uint32_t m = cand;
             while (m) {
                 const int idx = __builtin_ctz(m);
                 m &= m - 1;
                 const int site = (y0 + idx / CPL) * L + x0 + idx % CPL;
-                const uint32_t k = key[site];
-                const int d = k & 3;                          // this cell as seen from its target
-                const int t = site - (d == 0 ? -L : d == 1 ? 1 : d == 2 ? L : -1);
-                if (best_at(t) == k) won_mask |= 1u << idx;
+                const Block4 b = philox10(site, n, r, p, a.seed_lo, a.seed_hi);
+                if (b.w3 < T_div) {
+                    const uint32_t fm = ((fN >> idx) & 1u) | (((fE >> idx) & 1u) << 1) |
+                                        (((fS >> idx) & 1u) << 2) | (((fW >> idx) & 1u) << 3);
+                    const uint32_t kth = (uint32_t)(((uint64_t)b.w0 * __builtin_popcount(fm)) >> 32);
+                    uint32_t rest = fm;
+                    for (uint32_t j = 0; j < kth; ++j) rest &= rest - 1;
+                    const uint32_t dir = __builtin_ctz(rest);                 // 0 N, 1 E, 2 S, 3 W
+                    const int t = site + (dir == 0 ? -L : dir == 1 ? 1 : dir == 2 ? L : -1);
+                    atomicMin(&best[t], ((b.w2 >> 3) << 2) | ((dir + 2) & 3u));
+                    atomicOr(&s_claim[t >> 5], 1u << (t & 31));
+                    prop_m |= 1u << idx;
+                    dirs |= (uint64_t)dir << (2 * idx);
+                }
             }
         }
-        int live = 0;
-#pragma unroll
-        for (int i = 0; i < RPT; ++i)
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int idx = i * CPL + c;
-                const int site = (y0 + i) * L + x0 + c;
-                uint32_t out = nwd[i][c];
-                if ((empty_mask >> idx) & 1u) {
-                    if (best_at(site) != NONE_KEY) out = PROLIF;
-                }
-                if ((won_mask >> idx) & 1u) out = PROLIF;
-                s_cell[site] = (uint16_t)out;
-                const int st = out & 3;
-                live += (st == PROLIF || st == QUIESC);
+        __syncthreads();   // all claims are in
+        uint32_t won_m = 0;
+        {
+            uint32_t m = prop_m;
+            while (m) {
+                const int idx = __builtin_ctz(m);
+                m &= m - 1;
+                const uint32_t dir = (uint32_t)(dirs >> (2 * idx)) & 3u;
+                const int site = (y0 + idx / CPL) * L + x0 + idx % CPL;
+                const int t = site + (dir == 0 ? -L : dir == 1 ? 1 : dir == 2 ? L : -1);
+                if ((best[t] & 3u) == ((dir + 2) & 3u)) won_m |= 1u << idx;
             }
+        }
+        uint32_t born_m = 0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int s0 = (y0 + i) * L + x0;
+            born_m |= ((s_claim[s0 >> 5] >> (s0 & 31)) & ((1u << CPL) - 1u)) << (i * CPL);
+        }
+        born_m &= empty_m;
+        const uint32_t restart = born_m | won_m;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            uint32_t w[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) w[c] = ((restart >> (i * CPL + c)) & 1u) ? (uint32_t)PROLIF : wd[i][c];
+            store_words<CPL>(&s_cell[(y0 + i) * L + x0], w);
+        }
+        int live = __builtin_popcount(alive_m | born_m);
         // (5) live count: wave reduction, one LDS atomic per wave
         live = wave_sum(live);
         if (lane == 0) atomicAdd(&s_count[n & 1], live);
@@ -479,7 +521,7 @@ hipError_t launch_simulation(const SimArgs& a, int L, int n_inst, hipStream_t st
     if (n_inst <= 0) return hipSuccess;
     switch (L) {
         case 64: return launch_sim<1, 4>(a, n_inst, stream);
-        case 128: return launch_sim<2, 16>(a, n_inst, stream);
+        case 128: return launch_sim<2, 8>(a, n_inst, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -77,6 +77,26 @@ __device__ __forceinline__ void store_words(uint16_t* p, const uint32_t (&w)[CPL
     }
 }
 
+// Constants of the cell update.  They sit in LDS and are read at their point
+// of use after a barrier, so they do not occupy scalar registers across the
+// diffusion loop.
+struct CellConst {
+    float thOq, thGq, thOd, thGd, thHd;
+    int T_min, T_lys, ca0, ca1;
+    uint32_t T_div;
+};
+
+template <int CPL>
+__device__ __forceinline__ void store_keys(uint32_t* p, const uint32_t (&k)[CPL]) {
+    if constexpr (CPL == 1) {
+        p[0] = k[0];
+    } else if constexpr (CPL == 2) {
+        *reinterpret_cast<uint2*>(p) = make_uint2(k[0], k[1]);
+    } else {
+        *reinterpret_cast<uint4*>(p) = make_uint4(k[0], k[1], k[2], k[3]);
+    }
+}
+
 template <int CPL, int RPT>
 struct Geo {
     static constexpr int L = 64 * CPL;
@@ -102,6 +122,7 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
     using G = Geo<CPL, RPT>;
     constexpr int L = G::L;
     constexpr int NWAVE = G::NWAVE;
+    constexpr uint32_t ALL_SITES = G::ALL;
 
     __shared__ uint16_t s_cell[L * L];
     __shared__ uint32_t s_pool[G::POOL];       // halo double buffer, then claim slots
@@ -111,6 +132,7 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
     __shared__ uint32_t s_ev_thr[GGA_KMAX][4];
     __shared__ int s_nev, s_valid;
     __shared__ int s_count[2];
+    __shared__ CellConst s_k;                  // cell-update constants, read where used
 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -145,6 +167,12 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
         if (valid && total > a.dose_cap + 1e-6) valid = 0;
         s_valid = valid;
         s_nev = nev;
+        const gga_params& Q = a.prm;
+        s_k.thOq = Q.theta_O_quiesce; s_k.thGq = Q.theta_G_quiesce;
+        s_k.thOd = Q.theta_O_death; s_k.thGd = Q.theta_G_death; s_k.thHd = Q.theta_H_death;
+        s_k.T_min = Q.T_min; s_k.T_lys = Q.T_lys;
+        s_k.ca0 = Q.class_age[0]; s_k.ca1 = Q.class_age[1];
+        s_k.T_div = (Q.P_div >= 1.0) ? 0xFFFFFFFFu : (uint32_t)floor(Q.P_div * 4294967296.0);
         s_count[0] = 0;
         s_count[1] = 0;
     }
@@ -209,12 +237,6 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
         gst[f] = P.ghost[f];
     }
     const float actv[4] = {P.activity[0], P.activity[1], P.activity[2], P.activity[3]};
-    const uint32_t T_div = (P.P_div >= 1.0) ? 0xFFFFFFFFu
-                          : (uint32_t)floor(P.P_div * 4294967296.0);
-    const int T_min = P.T_min, T_lys = P.T_lys;
-    const int ca0 = P.class_age[0], ca1 = P.class_age[1];
-    const float thOq = P.theta_O_quiesce, thGq = P.theta_G_quiesce;
-    const float thOd = P.theta_O_death, thGd = P.theta_G_death, thHd = P.theta_H_death;
     // Ghost flux through the left / right lattice edge, folded into the
     // reaction constant of the edge columns (the lane shifts deliver 0 there).
     const bool left_edge = (lane == 0), right_edge = (lane == 63);
@@ -237,22 +259,29 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
     __syncthreads();
 
     for (int n = a.n0; n < a.n0 + a.nsteps; ++n) {
+        // Every LDS access below addresses a row as base + constant offset.  The
+        // base is opaque to the compiler at the top of each step, so per-row
+        // addresses are not hoisted out of the loop into registers.
+        int own = y0 * L + x0;
+        asm volatile("" : "+v"(own));
+        uint16_t* const cellp = s_cell + own;            // row i: cellp + i * L
         // (1) irradiation: every live cell draws w1 against its class threshold
         if (ev < nev && s_ev_step[ev] == n) {
             const uint32_t t0 = s_ev_thr[ev][0], t1 = s_ev_thr[ev][1];
             const uint32_t t2 = s_ev_thr[ev][2], t3 = s_ev_thr[ev][3];
+            const int ca0 = s_k.ca0, ca1 = s_k.ca1;
             uint32_t live_mask = 0;
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
-                    const int st = s_cell[(y0 + i) * L + x0 + c] & 3;
+                    const int st = cellp[i * L + c] & 3;
                     if (st == PROLIF || st == QUIESC) live_mask |= 1u << (i * CPL + c);
                 }
             while (live_mask) {
                 const int idx = __builtin_ctz(live_mask);
                 live_mask &= live_mask - 1;
-                const int site = (y0 + idx / CPL) * L + x0 + idx % CPL;
+                const int site = own + (idx / CPL) * L + idx % CPL;
                 const uint32_t w = s_cell[site];
                 const int st = w & 3, age = w >> 2;
                 const uint32_t thr = (st == QUIESC) ? t3 : (age < ca0 ? t0 : (age < ca1 ? t1 : t2));
@@ -272,7 +301,7 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const bool edge = (c == 0 && left_edge) || (c == CPL - 1 && right_edge);
-                const float act = actv[s_cell[(y0 + i) * L + x0 + c] & 3];
+                const float act = actv[cellp[i * L + c] & 3];
                 Ro[i][c] = fmaf(kap[0], act, edge ? lam[0] * gst[0] : 0.0f);
             }
 
@@ -284,13 +313,14 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
             for (int i = 0; i < RPT; ++i)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) asm volatile("" : "+v"(Ro[i][c]));
-            float* hb = reinterpret_cast<float*>(s_pool) + (s & 1) * G::HALO;
+            // this wave's halo block: [top/bottom][field][L] at wave * 6 L
+            float* const hw = reinterpret_cast<float*>(s_pool) + (s & 1) * G::HALO + wave * 6 * L + x0;
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
-                    hb[((wave * 2 + 0) * 3 + f) * L + x0 + c] = F[f][0][c];
-                    hb[((wave * 2 + 1) * 3 + f) * L + x0 + c] = F[f][RPT - 1][c];
+                    hw[f * L + c] = F[f][0][c];
+                    hw[(3 + f) * L + c] = F[f][RPT - 1][c];
                 }
             __syncthreads();
             float up[3][CPL], dn[3][CPL];
@@ -298,8 +328,8 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
             for (int f = 0; f < 3; ++f)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
-                    up[f][c] = (wave > 0) ? hb[(((wave - 1) * 2 + 1) * 3 + f) * L + x0 + c] : gst[f];
-                    dn[f][c] = (wave < NWAVE - 1) ? hb[(((wave + 1) * 2 + 0) * 3 + f) * L + x0 + c] : gst[f];
+                    up[f][c] = (wave > 0) ? hw[(f - 3) * L + c] : gst[f];            // bottom row of wave-1
+                    dn[f][c] = (wave < NWAVE - 1) ? hw[(6 + f) * L + c] : gst[f];    // top row of wave+1
                 }
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
@@ -327,6 +357,25 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
             }
         }
 
+        // Environment flags of every site, taken from the fields right after the
+        // sub-steps (x < th  <=>  sign bit of x - th: the difference of two finite
+        // floats is zero only when they are equal and otherwise keeps the sign of
+        // the exact difference).  The cell update below reads only these masks.
+        uint32_t nec_m = 0, starv_m = 0;
+        {
+            const float thOq = s_k.thOq, thGq = s_k.thGq, thOd = s_k.thOd, thGd = s_k.thGd, thHd = s_k.thHd;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int idx = i * CPL + c;
+                    const float O = F[0][i][c], Gl = F[1][i][c], H = F[2][i][c];
+                    nec_m |= ((__float_as_uint(Gl - thGd) | __float_as_uint(O - thOd) |
+                               __float_as_uint(thHd - H)) >> 31) << idx;
+                    starv_m |= ((__float_as_uint(O - thOq) | __float_as_uint(Gl - thGq)) >> 31) << idx;
+                }
+        }
+
         // (4) cell update, bit-parallel over the thread's RPT x CPL sites
         // (bit idx = i * CPL + c of 32-bit masks).  Proposers claim an EMPTY
         // target with ds_min_u32 on best[t] (one slot per site, sharing the
@@ -334,55 +383,76 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
         // low two bits name the winner's direction, so no key is kept.
         __syncthreads();   // the last sub-step's halo reads are done
         uint32_t* best = s_pool;
+        uint32_t* const bestp = best + own;              // row i: bestp + i * L
+        const CellConst K = s_k;
         uint32_t wd[RPT][CPL];
-        uint32_t empty_m = 0, cyc_m = 0, old_m = 0, alive_m = 0;
+        uint32_t occupied = 0;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            uint32_t w[CPL];
-            load_words<CPL>(&s_cell[(y0 + i) * L + x0], w);
+            load_words<CPL>(cellp + i * L, wd[i]);
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int idx = i * CPL + c;
-                const uint32_t st = w[c] & 3u, age = w[c] >> 2;
-                const uint32_t older = age < 255u ? age + 1u : 255u;
-                const float O = F[0][i][c], Gl = F[1][i][c], H = F[2][i][c];
-                const bool nec = (Gl < thGd) | (O < thOd) | (H > thHd);
-                const bool starv = (O < thOq) | (Gl < thGq);
-                const bool live = (st == PROLIF) | (st == QUIESC);
-                uint32_t nw = (st == DEAD && (int)older < T_lys) ? (DEAD | (older << 2)) : 0u;
-                nw = live ? (nec ? (uint32_t)DEAD : (starv ? (QUIESC | (age << 2)) : (PROLIF | (older << 2)))) : nw;
-                wd[i][c] = nw;
-                empty_m |= (uint32_t)(st == EMPTY) << idx;
-                cyc_m |= (uint32_t)(live & !nec & !starv) << idx;
-                old_m |= (uint32_t)((int)age >= T_min) << idx;
-                alive_m |= (uint32_t)(live & !nec) << idx;
-                best[(y0 + i) * L + x0 + c] = NONE_KEY;
-            }
+            for (int c = 0; c < CPL; ++c) occupied |= wd[i][c];
+        }
+        uint32_t empty_m = ALL_SITES, cyc_m = 0, old_m = 0, alive_m = 0;
+        if (__builtin_amdgcn_ballot_w64(occupied != 0u) != 0) {   // wave-uniform
+            empty_m = 0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int idx = i * CPL + c;
+                    const uint32_t w = wd[i][c], st = w & 3u, age = w >> 2;
+                    const uint32_t older = age < 255u ? age + 1u : 255u;
+                    const uint32_t nec = (nec_m >> idx) & 1u, starv = (starv_m >> idx) & 1u;
+                    const uint32_t live = (0x6u >> st) & 1u;
+                    const uint32_t cyc = live & ~(nec | starv) & 1u;
+                    uint32_t nw = (st == DEAD && (int)older < K.T_lys) ? (DEAD | (older << 2)) : 0u;
+                    nw = live ? (nec ? (uint32_t)DEAD : (starv ? (QUIESC | (age << 2)) : (PROLIF | (older << 2)))) : nw;
+                    wd[i][c] = nw;
+                    empty_m |= (uint32_t)(st == EMPTY) << idx;
+                    cyc_m |= cyc << idx;
+                    old_m |= (uint32_t)((int)age >= K.T_min) << idx;
+                    alive_m |= (live & ~nec & 1u) << idx;
+                    if (c == CPL - 1) __builtin_amdgcn_sched_barrier(0);   // one row at a time
+                }
+        } else {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) wd[i][c] = 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            uint32_t none[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) none[c] = NONE_KEY;
+            store_keys<CPL>(bestp + i * L, none);
         }
         for (int k = tid; k < L * L / 32; k += G::NT) s_claim[k] = 0u;
         // EMPTY neighbours of every site, as masks for N, E, S, W
         uint32_t top = 0, bot = 0;
         if (wave > 0) {
             uint32_t w[CPL];
-            load_words<CPL>(&s_cell[(y0 - 1) * L + x0], w);
+            load_words<CPL>(cellp - L, w);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) top |= (uint32_t)((w[c] & 3u) == EMPTY) << c;
         }
         if (wave < NWAVE - 1) {
             uint32_t w[CPL];
-            load_words<CPL>(&s_cell[(y0 + RPT) * L + x0], w);
+            load_words<CPL>(cellp + RPT * L, w);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) bot |= (uint32_t)((w[c] & 3u) == EMPTY) << c;
         }
-        constexpr uint32_t ALL = G::ALL;
         constexpr uint32_t C0 = G::COL_FIRST, CL = G::COL_LAST;
-        const uint32_t fN = ((empty_m << CPL) | top) & ALL;
+        const uint32_t fN = ((empty_m << CPL) | top) & ALL_SITES;
         const uint32_t fS = (empty_m >> CPL) | (bot << ((RPT - 1) * CPL));
         const uint32_t from_left = lane_from_left_u32(empty_m), from_right = lane_from_right_u32(empty_m);
-        const uint32_t fW = (CPL == 1) ? from_left : (((empty_m << 1) & ~C0 & ALL) | ((from_left >> (CPL - 1)) & C0));
+        const uint32_t fW = (CPL == 1) ? from_left : (((empty_m << 1) & ~C0 & ALL_SITES) | ((from_left >> (CPL - 1)) & C0));
         const uint32_t fE = (CPL == 1) ? from_right : (((empty_m >> 1) & ~CL) | ((from_right << (CPL - 1)) & CL));
         const uint32_t cand = cyc_m & old_m & (fN | fE | fS | fW);
-        __syncthreads();   // best[] and s_claim are reset
+        __syncthreads();   // best[] and s_claim are reset; the snapshot is no longer read
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) store_words<CPL>(cellp + i * L, wd[i]);
         uint32_t prop_m = 0;
         uint64_t dirs = 0;
         {
@@ -390,9 +460,9 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
             while (m) {
                 const int idx = __builtin_ctz(m);
                 m &= m - 1;
-                const int site = (y0 + idx / CPL) * L + x0 + idx % CPL;
+                const int site = own + (idx / CPL) * L + idx % CPL;
                 const Block4 b = philox10(site, n, r, p, a.seed_lo, a.seed_hi);
-                if (b.w3 < T_div) {
+                if (b.w3 < K.T_div) {
                     const uint32_t fm = ((fN >> idx) & 1u) | (((fE >> idx) & 1u) << 1) |
                                         (((fS >> idx) & 1u) << 2) | (((fW >> idx) & 1u) << 3);
                     const uint32_t kth = (uint32_t)(((uint64_t)b.w0 * __builtin_popcount(fm)) >> 32);
@@ -415,7 +485,7 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
                 const int idx = __builtin_ctz(m);
                 m &= m - 1;
                 const uint32_t dir = (uint32_t)(dirs >> (2 * idx)) & 3u;
-                const int site = (y0 + idx / CPL) * L + x0 + idx % CPL;
+                const int site = own + (idx / CPL) * L + idx % CPL;
                 const int t = site + (dir == 0 ? -L : dir == 1 ? 1 : dir == 2 ? L : -1);
                 if ((best[t] & 3u) == ((dir + 2) & 3u)) won_m |= 1u << idx;
             }
@@ -423,17 +493,16 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
         uint32_t born_m = 0;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            const int s0 = (y0 + i) * L + x0;
-            born_m |= ((s_claim[s0 >> 5] >> (s0 & 31)) & ((1u << CPL) - 1u)) << (i * CPL);
+            born_m |= ((s_claim[(own >> 5) + i * (L / 32)] >> (x0 & 31)) & ((1u << CPL) - 1u)) << (i * CPL);
         }
         born_m &= empty_m;
-        const uint32_t restart = born_m | won_m;
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            uint32_t w[CPL];
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) w[c] = ((restart >> (i * CPL + c)) & 1u) ? (uint32_t)PROLIF : wd[i][c];
-            store_words<CPL>(&s_cell[(y0 + i) * L + x0], w);
+        {
+            uint32_t m = born_m | won_m;             // daughters and winning parents restart at age 0
+            while (m) {
+                const int idx = __builtin_ctz(m);
+                m &= m - 1;
+                cellp[(idx / CPL) * L + idx % CPL] = (uint16_t)PROLIF;
+            }
         }
         int live = __builtin_popcount(alive_m | born_m);
         // (5) live count: wave reduction, one LDS atomic per wave

@@ -373,6 +373,7 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
                     nec_m |= ((__float_as_uint(Gl - thGd) | __float_as_uint(O - thOd) |
                                __float_as_uint(thHd - H)) >> 31) << idx;
                     starv_m |= ((__float_as_uint(O - thOq) | __float_as_uint(Gl - thGq)) >> 31) << idx;
+                    asm volatile("" : "+v"(nec_m), "+v"(starv_m));   // fold each site in now
                 }
         }
 
@@ -384,53 +385,10 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
         __syncthreads();   // the last sub-step's halo reads are done
         uint32_t* best = s_pool;
         uint32_t* const bestp = best + own;              // row i: bestp + i * L
-        const CellConst K = s_k;
-        uint32_t wd[RPT][CPL];
-        uint32_t occupied = 0;
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            load_words<CPL>(cellp + i * L, wd[i]);
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) occupied |= wd[i][c];
-        }
-        uint32_t empty_m = ALL_SITES, cyc_m = 0, old_m = 0, alive_m = 0;
-        if (__builtin_amdgcn_ballot_w64(occupied != 0u) != 0) {   // wave-uniform
-            empty_m = 0;
-#pragma unroll
-            for (int i = 0; i < RPT; ++i)
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const int idx = i * CPL + c;
-                    const uint32_t w = wd[i][c], st = w & 3u, age = w >> 2;
-                    const uint32_t older = age < 255u ? age + 1u : 255u;
-                    const uint32_t nec = (nec_m >> idx) & 1u, starv = (starv_m >> idx) & 1u;
-                    const uint32_t live = (0x6u >> st) & 1u;
-                    const uint32_t cyc = live & ~(nec | starv) & 1u;
-                    uint32_t nw = (st == DEAD && (int)older < K.T_lys) ? (DEAD | (older << 2)) : 0u;
-                    nw = live ? (nec ? (uint32_t)DEAD : (starv ? (QUIESC | (age << 2)) : (PROLIF | (older << 2)))) : nw;
-                    wd[i][c] = nw;
-                    empty_m |= (uint32_t)(st == EMPTY) << idx;
-                    cyc_m |= cyc << idx;
-                    old_m |= (uint32_t)((int)age >= K.T_min) << idx;
-                    alive_m |= (live & ~nec & 1u) << idx;
-                    if (c == CPL - 1) __builtin_amdgcn_sched_barrier(0);   // one row at a time
-                }
-        } else {
-#pragma unroll
-            for (int i = 0; i < RPT; ++i)
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) wd[i][c] = 0u;
-        }
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            uint32_t none[CPL];
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) none[c] = NONE_KEY;
-            store_keys<CPL>(bestp + i * L, none);
-        }
-        for (int k = tid; k < L * L / 32; k += G::NT) s_claim[k] = 0u;
-        // EMPTY neighbours of every site, as masks for N, E, S, W
-        uint32_t top = 0, bot = 0;
+        // From the snapshot: the EMPTY state of the rows just above and below
+        // this slab (owned by the neighbouring waves) and whether any of this
+        // wave's sites holds a cell.
+        uint32_t top = 0, bot = 0, occupied = 0;
         if (wave > 0) {
             uint32_t w[CPL];
             load_words<CPL>(cellp - L, w);
@@ -443,6 +401,54 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) bot |= (uint32_t)((w[c] & 3u) == EMPTY) << c;
         }
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            uint32_t w[CPL];
+            load_words<CPL>(cellp + i * L, w);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) occupied |= w[c];
+        }
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            uint32_t none[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) none[c] = NONE_KEY;
+            store_keys<CPL>(bestp + i * L, none);
+        }
+        for (int k = tid; k < L * L / 32; k += G::NT) s_claim[k] = 0u;
+        __syncthreads();   // boundary rows read, claims reset: own rows may now be rewritten
+        // Per site: lysis and environment transitions, written back row by row.
+        uint32_t empty_m = ALL_SITES, cyc_m = 0, old_m = 0, alive_m = 0;
+        if (__builtin_amdgcn_ballot_w64(occupied != 0u) != 0) {   // wave-uniform; else all EMPTY
+            const int T_lys = s_k.T_lys, T_min = s_k.T_min;
+            empty_m = 0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                uint32_t w[CPL];
+                load_words<CPL>(cellp + i * L, w);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int idx = i * CPL + c;
+                    const uint32_t st = w[c] & 3u, age = w[c] >> 2;
+                    const uint32_t older = age < 255u ? age + 1u : 255u;
+                    const uint32_t nec = (nec_m >> idx) & 1u, starv = (starv_m >> idx) & 1u;
+                    const uint32_t live = (0x6u >> st) & 1u;
+                    // branch-free selects: x ^ ((y ^ x) & -flag) picks y when flag is 1
+                    const uint32_t kept = (uint32_t)QUIESC | (w[c] & ~3u), grown = (uint32_t)PROLIF | (older << 2);
+                    uint32_t nl = grown ^ ((kept ^ grown) & (0u - starv));          // live outcome
+                    nl ^= (nl ^ (uint32_t)DEAD) & (0u - nec);
+                    const uint32_t decay = (uint32_t)((st == DEAD) & ((int)older < T_lys));
+                    const uint32_t nd = ((uint32_t)DEAD | (older << 2)) & (0u - decay);  // DEAD ages or lyses
+                    w[c] = nd ^ ((nl ^ nd) & (0u - live));
+                    empty_m |= (uint32_t)(st == EMPTY) << idx;
+                    cyc_m |= (live & ~(nec | starv) & 1u) << idx;
+                    old_m |= (uint32_t)((int)age >= T_min) << idx;
+                    alive_m |= (live & ~nec & 1u) << idx;
+                    asm volatile("" : "+v"(empty_m), "+v"(cyc_m), "+v"(old_m), "+v"(alive_m));
+                }
+                store_words<CPL>(cellp + i * L, w);
+            }
+        }
         constexpr uint32_t C0 = G::COL_FIRST, CL = G::COL_LAST;
         const uint32_t fN = ((empty_m << CPL) | top) & ALL_SITES;
         const uint32_t fS = (empty_m >> CPL) | (bot << ((RPT - 1) * CPL));
@@ -450,9 +456,6 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
         const uint32_t fW = (CPL == 1) ? from_left : (((empty_m << 1) & ~C0 & ALL_SITES) | ((from_left >> (CPL - 1)) & C0));
         const uint32_t fE = (CPL == 1) ? from_right : (((empty_m >> 1) & ~CL) | ((from_right << (CPL - 1)) & CL));
         const uint32_t cand = cyc_m & old_m & (fN | fE | fS | fW);
-        __syncthreads();   // best[] and s_claim are reset; the snapshot is no longer read
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) store_words<CPL>(cellp + i * L, wd[i]);
         uint32_t prop_m = 0;
         uint64_t dirs = 0;
         {
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
                 m &= m - 1;
                 const int site = own + (idx / CPL) * L + idx % CPL;
                 const Block4 b = philox10(site, n, r, p, a.seed_lo, a.seed_hi);
-                if (b.w3 < K.T_div) {
+                if (b.w3 < s_k.T_div) {
                     const uint32_t fm = ((fN >> idx) & 1u) | (((fE >> idx) & 1u) << 1) |
                                         (((fS >> idx) & 1u) << 2) | (((fW >> idx) & 1u) << 3);
                     const uint32_t kth = (uint32_t)(((uint64_t)b.w0 * __builtin_popcount(fm)) >> 32);

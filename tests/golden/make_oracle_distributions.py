@@ -1,0 +1,77 @@
+"""Write tests/golden/oracle_distributions.json: final live counts of many
+independent oracle replicas for a few protocols.
+
+Calls only the oracle and the seeded input generators.  Run from the
+repository root:  python tests/golden/make_oracle_distributions.py
+"""
+import copy
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from oracle import protocol, sim  # noqa: E402
+from oracle.model import Params  # noqa: E402
+from paper_2303_08123_amd import workloads  # noqa: E402
+
+ORACLE_SEED = 1000
+
+
+def model(name):
+    with open(os.path.join(ROOT, "paper_2303_08123_amd", "data", "model_default.json")) as fh:
+        md = json.load(fh)
+    if name == "high_uptake":
+        md = copy.deepcopy(md)
+        md["kappa"] = [4.0e-3, 2.0e-3, 2.0e-3]
+    return md
+
+
+def cases():
+    d1, g1, n1 = workloads.config1_protocols()
+    d2, g2, n2 = workloads.config2_protocols(1024, 10, seed=0, cap=20.0)
+    return {
+        "plain_bmii_64": dict(model="default", L=64, horizon=240, R=256,
+                              dose=d1[0].tolist(), gap=g1[0].tolist(), nfrac=int(n1[0])),
+        "high_uptake_bmii_64": dict(model="high_uptake", L=64, horizon=240, R=256,
+                                    dose=d1[0].tolist(), gap=g1[0].tolist(), nfrac=int(n1[0])),
+        "batched_p0_128": dict(model="default", L=128, horizon=480, R=200,
+                               dose=d2[0].tolist(), gap=g2[0].tolist(), nfrac=int(n2[0])),
+    }
+
+
+def one(args):
+    name, c, r = args
+    prm = Params.from_dict(model(c["model"]))
+    ev = protocol.events(np.array(c["dose"], np.float32), np.array(c["gap"]), c["nfrac"], c["horizon"], prm)
+    # protocol index 0 of the batch, replica r, under the oracle's own run seed
+    return name, r, int(sim.run_instance(prm, c["L"], c["horizon"], 10, ev, 0, r, ORACLE_SEED)[2][-1])
+
+
+def main():
+    cs = cases()
+    jobs = [(name, c, r) for name, c in cs.items() for r in range(c["R"])]
+    t0 = time.time()
+    with mp.Pool(os.cpu_count()) as pool:
+        res = pool.map(one, jobs, chunksize=4)
+    out = {"_about": "final live counts of independent oracle replicas (protocol index 0, replica r = 0..R-1, "
+                     f"run seed {ORACLE_SEED}); written by tests/golden/make_oracle_distributions.py",
+           "seed": ORACLE_SEED}
+    for name, c in cs.items():
+        live = [0] * c["R"]
+        for n, r, v in res:
+            if n == name:
+                live[r] = v
+        out[name] = dict(c, live=live)
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_distributions.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"done in {time.time() - t0:.0f} s")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,105 @@
+"""Whole-trajectory parity (needs an MI355X).
+
+Distribution level, as the paper compared its GPU and CPU codes (Results,
+"Establishing the fidelity of the GPU model": t-test of means and
+Kolmogorov-Smirnov tests over replicate runs): final live counts of the HIP
+path under one run seed against stored oracle replicas under another seed;
+the 95 % confidence interval of the mean difference must contain 0 (Welch)
+and the two-sample KS p-value must exceed 0.05.  Three cases at level 0.05
+each (multiplicity stated: three tests).  Same seeds: the share of replicas
+whose final counts agree exactly is reported.
+
+Full size: the batched workload (1,024 protocols x 4 replicas, 128 x 128,
+480 steps) in bench.py's launch configuration, with sampled instances checked
+step by step against the oracle over their certain prefix.
+"""
+import copy
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+from scipy import stats
+
+from oracle import protocol
+from oracle.model import Params
+from paper_2303_08123_amd import workloads
+from parity_helpers import oracle_certain_prefix
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+GPU_SEED = 2000
+
+
+@pytest.fixture(scope="module")
+def gga():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2303_08123_amd as g
+    return g
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(os.path.join(HERE, "golden", "oracle_distributions.json")) as fh:
+        return json.load(fh)
+
+
+def _model(md, name):
+    if name == "high_uptake":
+        md = copy.deepcopy(md)
+        md["kappa"] = [4.0e-3, 2.0e-3, 2.0e-3]
+    return md
+
+
+def _run(gga, md, case, seed):
+    dose = torch.tensor([case["dose"]], dtype=torch.float32, device="cuda")
+    gap = torch.tensor([case["gap"]], dtype=torch.int32, device="cuda")
+    nfrac = torch.tensor([case["nfrac"]], dtype=torch.int32, device="cuda")
+    cfg = gga.make_cfg(case["L"], case["horizon"], case["R"], seed=seed, substeps=10, dose_cap=100.0)
+    live, fit, _ = gga.simulate(md, cfg, dose, gap, nfrac)
+    return live.cpu().numpy()[0], float(fit.cpu().numpy()[0])
+
+
+@pytest.mark.parametrize("name", ["plain_bmii_64", "high_uptake_bmii_64", "batched_p0_128"])
+def test_final_count_distribution_matches_oracle(gga, model_dict, golden, name):
+    case = golden[name]
+    md = _model(model_dict, case["model"])
+    ref = np.array(case["live"], dtype=np.float64)
+    got, fit = _run(gga, md, case, GPU_SEED)
+    assert np.isclose(fit, got.mean(), rtol=1e-6)
+    t = stats.ttest_ind(got, ref, equal_var=False)
+    ks = stats.ks_2samp(got, ref)
+    same, _ = _run(gga, md, case, golden["seed"])
+    match = float(np.mean(same == np.array(case["live"])))
+    print(f"{name}: gpu mean {got.mean():.1f} sd {got.std():.1f} | oracle mean {ref.mean():.1f} sd {ref.std():.1f} | "
+          f"Welch p {t.pvalue:.3f} KS p {ks.pvalue:.3f} | same-seed exact match {match:.3f}")
+    assert t.pvalue > 0.05 and ks.pvalue > 0.05
+    if name == "plain_bmii_64":
+        assert match == 1.0     # no site ever comes near a threshold in this case
+    assert match >= 0.25
+
+
+def test_full_size_batched_workload(gga, model_dict):
+    """Bench configuration: sampled instances equal the oracle step by step
+    until their first near-threshold site; properties of every output."""
+    wl = workloads.CONFIG2
+    dose, gap, nfrac = workloads.config2_protocols(wl["P"], wl["K"], seed=0, cap=wl["dose_cap"])
+    cfg = gga.make_cfg(wl["L"], wl["horizon"], wl["R"], seed=wl["seed"], substeps=wl["substeps"],
+                       dose_cap=wl["dose_cap"])
+    dd = [torch.from_numpy(x).cuda() for x in (dose, gap, nfrac)]
+    live, fit, traj = gga.simulate(model_dict, cfg, *dd, traj=True)
+    live, fit, traj = live.cpu().numpy(), fit.cpu().numpy(), traj.cpu().numpy()
+    L2 = wl["L"] ** 2
+    assert live.shape == (wl["P"], wl["R"]) and traj.shape == (wl["P"], wl["R"], wl["horizon"])
+    assert np.all(live >= 0) and np.all(live <= L2) and np.array_equal(live, traj[:, :, -1])
+    np.testing.assert_allclose(fit, live.mean(axis=1), rtol=1e-6)
+    prm = Params.from_dict(model_dict)
+    certain = []
+    for p, r in ((0, 0), (517, 2), (1023, 3)):
+        ev = protocol.events(dose[p], gap[p], nfrac[p], wl["horizon"], prm)
+        ref, c = oracle_certain_prefix(prm, wl["L"], wl["horizon"], wl["substeps"], ev, p, r, wl["seed"])
+        assert np.array_equal(traj[p, r, :c], ref[:c]), (p, r, c)
+        certain.append(c)
+    print("certain prefixes", certain)
+    assert min(certain) >= 100

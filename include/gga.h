@@ -182,6 +182,81 @@ int gga_state_run(const gga_params* params, const gga_sim_cfg* cfg,
                   float* fields_d, uint16_t* cells_d, int32_t* live_d, int32_t* traj_d,
                   hipStream_t stream);
 
+/* GA settings.  Set struct_size = sizeof(gga_ga_cfg). */
+typedef struct gga_ga_cfg {
+    uint32_t struct_size;
+    int32_t n_elite;        /* best protocols copied unchanged, 0 .. N            */
+    int32_t tournament_k;   /* tournament size, 1 .. 64                            */
+    double p_cross;         /* one-point crossover probability, [0, 1]             */
+    double p_mut;           /* per-gene mutation probability (dose, delay), [0, 1] */
+    uint64_t seed;          /* key of the GA's Philox blocks                        */
+} gga_ga_cfg;
+
+/*
+ * One GA breeding step over fixed-length protocols (K genes of dose and delay;
+ * the paper's loop, Materials and Methods, "The Main GA Loop", and its
+ * appendix on the operators): rank by (fitness, index) with NaN last, copy the
+ * n_elite best, and fill the other slots pairwise: tournament selection of two
+ * parents, one-point crossover with probability p_cross, per-gene mutation
+ * over the alphabet, and a guard that lowers the largest dose one alphabet
+ * step until the total is within the cap.  Lower fitness is better.  Random
+ * words: Philox blocks (pair, generation, 0x47414741, sub) keyed by
+ * cfg->seed, generation read from *generation_d.
+ *   fitness_d[N], dose_d[N][K], gap_h_d[N][K]   current population (device)
+ *   order_d[N], position_d[N]                   rank outputs (device)
+ *   next_dose_d[N][K], next_gap_h_d[N][K]       next population (device)
+ * Requires 2 <= N, 1 <= K <= GGA_KMAX, doses on the alphabet's quantum grid.
+ * Errors: GGA_E_ARG, GGA_E_ABI, GGA_E_ALPHABET, GGA_E_HIP.
+ */
+int gga_ga_breed(const gga_ga_cfg* ga, const gga_alphabet* a, const float* fitness_d,
+                 const float* dose_d, const int32_t* gap_h_d, int32_t N, int32_t K,
+                 const int32_t* generation_d, int32_t* order_d, int32_t* position_d,
+                 float* next_dose_d, int32_t* next_gap_h_d, hipStream_t stream);
+
+/* Device workspace of gga_ga_generation / gga_ga_run for N protocols x R replicas. */
+size_t gga_ga_workspace_bytes(int32_t N, int32_t R);
+
+/* Stream-ordered: store g in the workspace's generation counter.
+ * Errors: GGA_E_ARG, GGA_E_HIP. */
+int gga_ga_set_generation(void* ws_d, int32_t g, hipStream_t stream);
+
+/*
+ * One whole GA generation, stream-ordered: simulate every protocol of the
+ * current population R times (Philox key cfg->seed + g * 0x9E3779B97F4A7C15,
+ * g the generation counter held in the workspace), reduce the fitness, record
+ * hist_d[g] = (best, mean fitness) when g < hist_cap, and breed the next
+ * population.  With advance != 0 the counter is then incremented, so the same
+ * enqueued work can be captured once in a hipGraph and replayed.  nfrac_d[N]
+ * must hold K for every protocol.  Set the counter with gga_ga_set_generation.
+ * Errors: as gga_simulate and gga_ga_breed; GGA_E_ARG for a small workspace.
+ */
+int gga_ga_generation(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga,
+                      const gga_alphabet* a, const float* dose_d, const int32_t* gap_h_d,
+                      const int32_t* nfrac_d, int32_t N, int32_t K, float* next_dose_d,
+                      int32_t* next_gap_h_d, void* ws_d, size_t ws_bytes, float* hist_d,
+                      int32_t hist_cap, int32_t advance, hipStream_t stream);
+
+/*
+ * Run generations g0 .. g0 + n_gen - 1 from population A (dose_a_d, gap_a_d),
+ * alternating A -> B and B -> A; the last bred population is in A when n_gen
+ * is even and in B otherwise.  A run continued with g0 = previous g0 + n_gen
+ * from the previous result reproduces one longer run exactly.  use_graph = 0: each generation is enqueued and the host
+ * waits for it before the next one (host-driven loop); use_graph = 1: the two
+ * alternating generations are captured once into hipGraphs and replayed with
+ * no host wait in between.  gen_ms_h[g] (HOST, or NULL) receives the time from
+ * the start of the run to the end of generation g0 + g, from HIP events on
+ * `stream`.  hist_d[g0 + n_gen][2] receives (best, mean) fitness at row g for
+ * generation g.
+ * Synchronous: returns after the stream has finished.  Creates and destroys
+ * HIP graphs and events (host-side objects); allocates no device memory.
+ * Errors: as gga_ga_generation.
+ */
+int gga_ga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga,
+               const gga_alphabet* a, float* dose_a_d, int32_t* gap_a_d, float* dose_b_d,
+               int32_t* gap_b_d, const int32_t* nfrac_d, int32_t N, int32_t K, int32_t g0,
+               int32_t n_gen, int32_t use_graph, void* ws_d, size_t ws_bytes, float* hist_d,
+               float* gen_ms_h, hipStream_t stream);
+
 /*
  * Philox4x32-10 blocks (Salmon et al., SC'11) from the device implementation
  * the simulator uses: out_d[i][0..3] = Philox(counter ctr_d[i][0..3], key

@@ -57,6 +57,13 @@ class Alphabet(ctypes.Structure):
     ]
 
 
+class GaCfg(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("n_elite", ctypes.c_int32), ("tournament_k", ctypes.c_int32),
+        ("p_cross", ctypes.c_double), ("p_mut", ctypes.c_double), ("seed", ctypes.c_uint64),
+    ]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -73,6 +80,13 @@ def _load():
         "gga_state_init": ([vp, vp, i32, vp, vp, vp], ctypes.c_int),
         "gga_state_run": ([vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "gga_philox_fill": ([vp, u64, vp, i64, vp], ctypes.c_int),
+        "gga_ga_breed": ([vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "gga_ga_workspace_bytes": ([i32, i32], ctypes.c_size_t),
+        "gga_ga_set_generation": ([vp, i32, vp], ctypes.c_int),
+        "gga_ga_generation": ([vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, ctypes.c_size_t, vp, i32,
+                               i32, vp], ctypes.c_int),
+        "gga_ga_run": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, ctypes.c_size_t, vp,
+                        vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -84,7 +98,8 @@ def _load():
 LIB = _load()
 EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
            "gga_population_random", "gga_simulate", "gga_state_init", "gga_state_run",
-           "gga_philox_fill")
+           "gga_philox_fill", "gga_ga_breed", "gga_ga_workspace_bytes", "gga_ga_set_generation",
+           "gga_ga_generation", "gga_ga_run")
 
 
 class GGAError(RuntimeError):
@@ -250,3 +265,72 @@ def philox_fill(ctr, seed, stream=None):
     out = torch.empty_like(ctr)
     _check(LIB.gga_philox_fill(_ptr(ctr), int(seed), _ptr(out), ctr.shape[0], _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------- GA
+
+def make_ga(n_elite=2, tournament_k=4, p_cross=0.8, p_mut=0.05, seed=0):
+    g = GaCfg()
+    g.struct_size = ctypes.sizeof(GaCfg)
+    g.n_elite, g.tournament_k = int(n_elite), int(tournament_k)
+    g.p_cross, g.p_mut, g.seed = float(p_cross), float(p_mut), int(seed)
+    return g
+
+
+def ga_breed(ga, alphabet, fitness, dose, gap, generation, stream=None):
+    """One breeding step; generation is an int32 CUDA tensor of one element.
+    Returns (order, position, next_dose, next_gap)."""
+    N, K = dose.shape
+    order = torch.empty(N, dtype=torch.int32, device=dose.device)
+    pos = torch.empty(N, dtype=torch.int32, device=dose.device)
+    nd, ng = torch.empty_like(dose), torch.empty_like(gap)
+    _check(LIB.gga_ga_breed(ctypes.byref(ga), ctypes.byref(alphabet), _ptr(fitness), _ptr(dose), _ptr(gap),
+                            N, K, _ptr(generation), _ptr(order), _ptr(pos), _ptr(nd), _ptr(ng), _stream(stream)))
+    return order, pos, nd, ng
+
+
+def ga_workspace(N, R, device="cuda"):
+    return torch.empty(int(LIB.gga_ga_workspace_bytes(N, R)), dtype=torch.uint8, device=device)
+
+
+def ga_set_generation(ws, g, stream=None):
+    _check(LIB.gga_ga_set_generation(_ptr(ws), int(g), _stream(stream)))
+
+
+def ga_generation(params, cfg, ga, alphabet, dose, gap, nfrac, ws, hist=None, advance=True, stream=None):
+    """Enqueue one GA generation; returns (next_dose, next_gap)."""
+    N, K = _protocols(dose, gap, nfrac)
+    nd, ng = torch.empty_like(dose), torch.empty_like(gap)
+    cap = hist.shape[0] if hist is not None else 0
+    _check(LIB.gga_ga_generation(ctypes.byref(_as_params(params)), ctypes.byref(cfg), ctypes.byref(ga),
+                                 ctypes.byref(alphabet), _ptr(dose), _ptr(gap), _ptr(nfrac), N, K, _ptr(nd),
+                                 _ptr(ng), _ptr(ws), ws.numel(), _ptr(hist), cap, int(bool(advance)),
+                                 _stream(stream)))
+    return nd, ng
+
+
+def ga_run(params, cfg, ga, alphabet, dose, gap, n_gen, use_graph, g0=0, hist=None):
+    """Run generations g0 .. g0+n_gen-1 from (dose, gap) (not modified).
+    Returns (final dose, final gap, hist[g0+n_gen, 2] (best, mean), gen_ms[n_gen]).
+    Pass the previous hist to keep filling it when continuing a run."""
+    N, K = dose.shape
+    nfrac = torch.full((N,), K, dtype=torch.int32, device=dose.device)
+    da, ga_ = dose.clone(), gap.clone()
+    db, gb = torch.empty_like(dose), torch.empty_like(gap)
+    ws = ga_workspace(N, cfg.R, dose.device)
+    rows = max(g0 + n_gen, 1)
+    h = torch.full((rows, 2), float("nan"), dtype=torch.float32, device=dose.device)
+    if hist is not None:
+        h[:min(rows, hist.shape[0])] = hist[:rows]
+    gen_ms = np.zeros(max(n_gen, 1), dtype=np.float32)
+    # a captured stream must not be the legacy default stream
+    side = torch.cuda.Stream(device=dose.device)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        _check(LIB.gga_ga_run(ctypes.byref(_as_params(params)), ctypes.byref(cfg), ctypes.byref(ga),
+                              ctypes.byref(alphabet), _ptr(da), _ptr(ga_), _ptr(db), _ptr(gb), _ptr(nfrac), N, K,
+                              int(g0), int(n_gen), int(bool(use_graph)), _ptr(ws), ws.numel(), _ptr(h),
+                              gen_ms.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(side.cuda_stream)))
+    torch.cuda.current_stream().wait_stream(side)
+    final = (da, ga_) if n_gen % 2 == 0 else (db, gb)
+    return final[0], final[1], h[:g0 + n_gen], gen_ms[:n_gen]

@@ -1,0 +1,196 @@
+// Device GA over fixed-length protocols (K genes of dose and delay).
+//
+// The paper's loop (Materials and Methods, "The Main GA Loop"; appendix "GA
+// Operators: additional details"): the best protocols are copied unchanged,
+// parents are selected (here a k-way tournament), recombined by crossover (one
+// point), mutated, and repaired by a guard that lowers the largest dose while
+// the total exceeds the cap.  Lower fitness (mean live count) is better.
+//
+// Kernels: rank (position of each protocol in (fitness, index) order, NaN
+// last), history (best and mean fitness of the generation), offspring (one
+// thread per child pair), and the generation counter used by replayed graphs.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gga_device.h"
+#include "gga_internal.h"
+
+namespace gga {
+namespace {
+
+constexpr uint32_t GA_TAG = 0x47414741u;
+
+__device__ __forceinline__ float rank_key(float f) { return isnan(f) ? INFINITY : f; }
+
+__global__ __launch_bounds__(256) void rank_kernel(const float* fitness, int N, int32_t* order,
+                                                   int32_t* position) {
+    __shared__ float tile[256];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const float ki = (i < N) ? rank_key(fitness[i]) : 0.0f;
+    int pos = 0;
+    for (int base = 0; base < N; base += 256) {
+        const int j = base + threadIdx.x;
+        tile[threadIdx.x] = (j < N) ? rank_key(fitness[j]) : 0.0f;
+        __syncthreads();
+        const int n = min(256, N - base);
+        for (int t = 0; t < n; ++t) {
+            const float kj = tile[t];
+            pos += (kj < ki) || (kj == ki && base + t < i);
+        }
+        __syncthreads();
+    }
+    if (i < N) {
+        position[i] = pos;
+        order[pos] = i;
+    }
+}
+
+// hist[g] = (best fitness, mean fitness over finite entries) of this generation.
+__global__ __launch_bounds__(256) void history_kernel(const float* fitness, int N, const int32_t* order,
+                                                      const int32_t* generation, float* hist, int hist_cap) {
+    __shared__ double s_sum[256];
+    __shared__ int s_cnt[256];
+    double sum = 0.0;
+    int cnt = 0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float f = fitness[i];
+        if (!isnan(f)) { sum += f; ++cnt; }
+    }
+    s_sum[threadIdx.x] = sum;
+    s_cnt[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            s_sum[threadIdx.x] += s_sum[threadIdx.x + s];
+            s_cnt[threadIdx.x] += s_cnt[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int g = *generation;
+        if (g >= 0 && g < hist_cap) {
+            hist[2 * g] = fitness[order[0]];
+            hist[2 * g + 1] = s_cnt[0] ? (float)(s_sum[0] / s_cnt[0]) : __builtin_nanf("");
+        }
+    }
+}
+
+__device__ __forceinline__ Block4 ga_words(int c, uint32_t g, uint32_t sub, uint32_t k0, uint32_t k1) {
+    return philox10((uint32_t)c, g, GA_TAG, sub, k0, k1);
+}
+
+__device__ __forceinline__ uint32_t word_of(const Block4& b, int i) {
+    return i == 0 ? b.w0 : i == 1 ? b.w1 : i == 2 ? b.w2 : b.w3;
+}
+
+__global__ __launch_bounds__(128) void offspring_kernel(GaArgs a) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = a.N, K = a.K;
+    const uint32_t g = (uint32_t)*a.generation;
+    if (t < a.n_elite) {                                   // elites: copied unchanged
+        const int src = a.order[t];
+        for (int j = 0; j < K; ++j) {
+            a.next_dose[(size_t)t * K + j] = a.dose[(size_t)src * K + j];
+            a.next_gap[(size_t)t * K + j] = a.gap[(size_t)src * K + j];
+        }
+        return;
+    }
+    const int c = t - a.n_elite;                           // child pair
+    const int n_pairs = (N - a.n_elite + 1) / 2;
+    if (c < 0 || c >= n_pairs) return;
+    const int nb = (a.k + 3) / 4;
+    int parent[2];
+    for (int side = 0; side < 2; ++side) {
+        int best = -1, best_pos = 0x7FFFFFFF;
+        for (int i = 0; i < a.k; ++i) {
+            const Block4 b = ga_words(c, g, (uint32_t)(side * nb + i / 4), a.seed_lo, a.seed_hi);
+            const int pick = (int)(((uint64_t)word_of(b, i & 3) * (uint32_t)N) >> 32);
+            const int pos = a.position[pick];
+            if (pos < best_pos) { best_pos = pos; best = pick; }
+        }
+        parent[side] = best;
+    }
+    const Block4 bc = ga_words(c, g, (uint32_t)(2 * nb), a.seed_lo, a.seed_hi);
+    int cut = K;                                           // no crossover: children copy the parents
+    if (bc.w0 < a.t_cross && K > 1) cut = 1 + (int)(((uint64_t)bc.w1 * (uint32_t)(K - 1)) >> 32);
+    for (int ch = 0; ch < 2; ++ch) {
+        const int slot = a.n_elite + 2 * c + ch;
+        if (slot >= N) break;
+        int q[GGA_KMAX], gp[GGA_KMAX];
+        int total = 0;
+        for (int j = 0; j < K; ++j) {
+            const int src = (j < cut) == (ch == 0) ? parent[0] : parent[1];
+            int qd = (int)rintf(a.dose[(size_t)src * K + j] / a.quantum);
+            int gg = a.gap[(size_t)src * K + j];
+            const Block4 bm = ga_words(c, g, (uint32_t)(2 * nb + 1 + ch * K + j), a.seed_lo, a.seed_hi);
+            if (bm.w0 < a.t_mut) qd = a.dose_q[(int)(((uint64_t)bm.w1 * (uint32_t)a.n_dose) >> 32)];
+            if (bm.w2 < a.t_mut) gg = a.gaps[(int)(((uint64_t)bm.w3 * (uint32_t)a.n_gap) >> 32)];
+            q[j] = qd;
+            gp[j] = gg;
+            total += qd;
+        }
+        // guard: the largest dose (first among equals) steps down the alphabet
+        while (total > a.cap_q) {
+            bool moved = false;
+            int skip_above = 0x7FFFFFFF, skip_from = -1;     // doses that cannot move
+            while (!moved) {
+                int jm = -1;
+                for (int j = 0; j < K; ++j) {
+                    const bool eligible = q[j] < skip_above || (q[j] == skip_above && j > skip_from);
+                    if (eligible && (jm < 0 || q[j] > q[jm])) jm = j;
+                }
+                if (jm < 0) break;                          // nothing can move (host rejects such alphabets)
+                int lower = -1;
+                for (int v = 0; v < a.n_dose; ++v)
+                    if (a.dose_q[v] < q[jm]) lower = a.dose_q[v];
+                if (lower >= 0) {
+                    total -= q[jm] - lower;
+                    q[jm] = lower;
+                    moved = true;
+                } else {
+                    skip_above = q[jm];
+                    skip_from = jm;
+                }
+            }
+            if (!moved) break;
+        }
+        for (int j = 0; j < K; ++j) {
+            a.next_dose[(size_t)slot * K + j] = (float)((double)q[j] * (double)a.quantum);
+            a.next_gap[(size_t)slot * K + j] = gp[j];
+        }
+    }
+}
+
+__global__ void counter_kernel(int32_t* generation, int32_t value, int32_t add) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *generation = add ? *generation + value : value;
+}
+
+}  // namespace
+
+hipError_t launch_rank(const float* fitness, int N, int32_t* order, int32_t* position, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rank_kernel, dim3((N + 255) / 256), dim3(256), 0, s, fitness, N, order, position);
+    return hipGetLastError();
+}
+
+hipError_t launch_history(const float* fitness, int N, const int32_t* order, const int32_t* generation,
+                          float* hist, int hist_cap, hipStream_t s) {
+    if (N <= 0 || !hist) return hipSuccess;
+    hipLaunchKernelGGL(history_kernel, dim3(1), dim3(256), 0, s, fitness, N, order, generation, hist, hist_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_offspring(const GaArgs& a, hipStream_t s) {
+    const int threads = a.n_elite + (a.N - a.n_elite + 1) / 2;
+    if (threads <= 0) return hipSuccess;
+    hipLaunchKernelGGL(offspring_kernel, dim3((threads + 127) / 128), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_counter(int32_t* generation, int32_t value, int32_t add, hipStream_t s) {
+    hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, s, generation, value, add);
+    return hipGetLastError();
+}
+
+}  // namespace gga

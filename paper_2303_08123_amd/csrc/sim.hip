@@ -143,6 +143,11 @@ __global__ __launch_bounds__(64 * 64 * CPL / RPT) void sim_kernel(SimArgs a) {
     const int y0 = wave * RPT;
     const int x0 = lane * CPL;
     const gga_params& P = a.prm;
+    if (a.generation) {             // per-generation key of a replayed GA generation
+        const uint64_t key = a.seed + (uint64_t)(uint32_t)*a.generation * 0x9E3779B97F4A7C15ull;
+        a.seed_lo = (uint32_t)key;
+        a.seed_hi = (uint32_t)(key >> 32);
+    }
 
     // ---- protocol: validity and irradiation events (thread 0) ----
     if (tid == 0) {

@@ -28,7 +28,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(gga):
     names = declared_functions()
-    assert len(names) == 9
+    assert len(names) == 14
     for n in names:
         assert hasattr(gga.LIB, n), n
     assert set(names) == set(gga.EXPORTS)
@@ -43,9 +43,9 @@ STRUCT_PROBE = r"""
 #include <stddef.h>
 #include "gga.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(gga_params), sizeof(gga_sim_cfg), sizeof(gga_alphabet),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(gga_params), sizeof(gga_sim_cfg), sizeof(gga_alphabet),
          offsetof(gga_params, P_div), offsetof(gga_params, m), offsetof(gga_sim_cfg, seed),
-         offsetof(gga_alphabet, gaps));
+         offsetof(gga_alphabet, gaps), sizeof(gga_ga_cfg), offsetof(gga_ga_cfg, seed));
   return 0;
 }
 """
@@ -61,7 +61,7 @@ def test_struct_layout_matches_python_mirror(gga, tmp_path):
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert vals == [ctypes.sizeof(gga.Params), ctypes.sizeof(gga.SimCfg), ctypes.sizeof(gga.Alphabet),
                     gga.Params.P_div.offset, gga.Params.m.offset, gga.SimCfg.seed.offset,
-                    gga.Alphabet.gaps.offset]
+                    gga.Alphabet.gaps.offset, ctypes.sizeof(gga.GaCfg), gga.GaCfg.seed.offset]
 
 
 def test_version_and_errors(gga):

@@ -1,0 +1,127 @@
+"""Pins of the GA operators: ranking against a library sort, tournament
+selection against its exact order-statistic law, crossover and mutation
+statistics, the dose guard, and elitism."""
+import math
+
+import numpy as np
+import pytest
+from scipy.stats import chisquare
+
+from oracle import ga
+
+ALPHA = dict(dose_quantum=0.5, dose_q=[1, 2, 3, 4, 5], gaps=list(range(6, 61, 6)), cap=20.0)
+
+
+def _pop(N, K, seed):
+    rng = np.random.default_rng(seed)
+    dose = rng.choice([0.5, 1.0, 1.5, 2.0], size=(N, K)).astype(np.float32)
+    gap = rng.choice(ALPHA["gaps"], size=(N, K)).astype(np.int32)
+    return dose, gap
+
+
+def test_rank_matches_stable_library_sort(rng):
+    f = rng.integers(0, 20, size=300).astype(np.float64)
+    f[rng.uniform(size=300) < 0.05] = np.nan
+    order, pos = ga.rank_order(f)
+    key = np.where(np.isnan(f), np.inf, f)
+    assert np.array_equal(order, np.argsort(key, kind="stable"))
+    assert np.array_equal(pos[order], np.arange(300))
+
+
+def test_tournament_follows_order_statistic_law():
+    """k picks with replacement, the best rank wins:
+    P(rank r) = ((N - r)^k - (N - r - 1)^k) / N^k."""
+    N, K, k = 40, 4, 4
+    dose, gap = _pop(N, K, 0)
+    fitness = np.arange(N, dtype=np.float64)[::-1].copy()   # protocol N-1 is best
+    order, pos = ga.rank_order(fitness)
+    counts = np.zeros(N)
+    nb = 1
+    for c in range(6000):
+        words = ga._words(c, 3, 0, 99)
+        picks = [(w * N) >> 32 for w in words[:k]]
+        counts[pos[min(picks, key=lambda i: pos[i])]] += 1
+    expect = np.array([((N - r) ** k - (N - r - 1) ** k) / N ** k for r in range(N)]) * counts.sum()
+    keep = expect > 5
+    obs = np.append(counts[keep], counts[~keep].sum())
+    exp = np.append(expect[keep], expect[~keep].sum())
+    assert chisquare(obs, exp).pvalue > 1e-3
+
+
+def test_crossover_exchanges_tails_at_uniform_cut():
+    N, K = 64, 10
+    dose, gap = _pop(N, K, 1)
+    fitness = np.arange(N, dtype=np.float64)
+    big = dict(ALPHA, cap=1e6)
+    nd, ng = ga.next_generation(dose, gap, fitness, 0, 5, big, n_elite=0, k=1, p_cross=1.0, p_mut=0.0)
+    cuts = []
+    for c in range(N // 2):
+        words = ga._words(c, 0, 0, 5)
+        a = (words[0] * N) >> 32
+        b = (ga._words(c, 0, 1, 5)[0] * N) >> 32
+        wc = ga._words(c, 0, 2, 5)
+        cut = 1 + ((wc[1] * (K - 1)) >> 32)
+        cuts.append(cut)
+        c1, c2 = 2 * c, 2 * c + 1
+        assert np.array_equal(nd[c1], np.concatenate([dose[a, :cut], dose[b, cut:]]))
+        assert np.array_equal(nd[c2], np.concatenate([dose[b, :cut], dose[a, cut:]]))
+        assert np.array_equal(ng[c1], np.concatenate([gap[a, :cut], gap[b, cut:]]))
+    assert min(cuts) >= 1 and max(cuts) <= K - 1
+
+
+def test_mutation_rate():
+    N, K, p = 400, 10, 0.05
+    dose, gap = _pop(N, K, 2)
+    fitness = np.zeros(N)
+    big = dict(ALPHA, cap=1e6)
+    nd, ng = ga.next_generation(dose, gap, fitness, 1, 7, big, n_elite=0, k=1, p_cross=0.0, p_mut=p)
+    # with k = 1 and no crossover each child copies its single pick
+    changed_d = changed_g = total = 0
+    for c in range(N // 2):
+        for t, ch in ((0, 2 * c), (1, 2 * c + 1)):
+            src = (ga._words(c, 1, t, 7)[0] * N) >> 32
+            changed_d += np.sum(nd[ch] != dose[src])
+            changed_g += np.sum(ng[ch] != gap[src])
+            total += K
+    for changed, n_alpha in ((changed_d, 5), (changed_g, 10)):
+        rate = p * (1 - 1.0 / n_alpha) if n_alpha == 10 else None
+        if rate is None:   # parent doses are in {0.5..2.0}: redraw hits the old value 1 time in 5
+            rate = p * (1 - 1.0 / 5)
+        assert abs(changed / total - rate) < 5 * math.sqrt(rate * (1 - rate) / total)
+
+
+def test_guard_lowers_largest_dose_first():
+    assert ga.guard([5, 5, 3], [1, 2, 3, 4, 5], 12) == [4, 5, 3]
+    assert ga.guard([5, 5, 3], [1, 2, 3, 4, 5], 11) == [4, 4, 3]
+    assert ga.guard([5, 4, 3], [1, 3, 5], 9) == [3, 3, 3]
+    assert ga.guard([5, 1, 1], [1, 2, 3, 4, 5], 5) == [3, 1, 1]
+    assert ga.guard([2, 2], [1, 2, 3], 10) == [2, 2]
+    with pytest.raises(ValueError):
+        ga.guard([3, 3], [3], 5)
+
+
+def test_children_respect_cap_and_elites_are_kept():
+    N, K = 64, 10
+    rng = np.random.default_rng(3)
+    dose = rng.choice([2.0, 2.5], size=(N, K)).astype(np.float32)   # totals 20..25 Gy
+    gap = rng.choice(ALPHA["gaps"], size=(N, K)).astype(np.int32)
+    fitness = rng.uniform(size=N)
+    nd, ng = ga.next_generation(dose, gap, fitness, 4, 11, ALPHA, n_elite=4, k=4, p_cross=0.8, p_mut=0.05)
+    order, _ = ga.rank_order(fitness)
+    assert np.array_equal(nd[:4], dose[order[:4]]) and np.array_equal(ng[:4], gap[order[:4]])
+    assert np.all(nd[4:].astype(np.float64).sum(1) <= 20.0 + 1e-6)
+    assert set(np.unique(nd[4:])) <= {0.5, 1.0, 1.5, 2.0, 2.5}
+
+
+def test_elitism_keeps_best_fitness_monotone():
+    """With a deterministic fitness of the protocol, the best never worsens."""
+    N, K = 40, 10
+    dose, gap = _pop(N, K, 4)
+    w = np.linspace(1, 2, K)
+    best = []
+    for g in range(15):
+        f = (dose.astype(np.float64) * w).sum(1) - 0.01 * gap.sum(1)
+        best.append(f.min())
+        dose, gap = ga.next_generation(dose, gap, f, g, 13, ALPHA, n_elite=2, k=4, p_cross=0.8, p_mut=0.05)
+    assert all(b2 <= b1 + 1e-12 for b1, b2 in zip(best, best[1:]))
+    assert best[-1] < best[0]

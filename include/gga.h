@@ -258,6 +258,112 @@ int gga_ga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cf
                float* gen_ms_h, hipStream_t stream);
 
 /*
+ * Surrogate of the simulation for pre-screening GA offspring (not part of the
+ * paper's method): an MLP from an encoded protocol (40 fractions x (dose / 5
+ * Gy, delay / 60 h, present), zero-padded to 128 features) through three
+ * hidden layers of 512 with GELU(x) = x Phi(x) to one output, the normalised
+ * fitness.  BF16 weights and activations on MFMA with FP32 accumulation; FP32
+ * master weights and Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
+ *
+ * Net buffer (device, caller-owned, gga_mlp_net_bytes() bytes), 256-byte
+ * aligned blocks in this order: norm f32[2] (mu, sigma of the training
+ * targets), params f32[591873], Adam m, Adam v, gradients (same size), then
+ * bf16 copies W1 [128][512], W1^T, W2 [512][512], W2^T, W3, W3^T.  Parameter
+ * order: W1 [128][512], b1[512], W2 [512][512], b2, W3 [512][512], b3,
+ * w4[512], b4[1].  Work buffer: gga_mlp_work_bytes(B) bytes for batch B.
+ */
+size_t gga_mlp_net_bytes(void);
+size_t gga_mlp_work_bytes(int32_t B);
+
+/* Initialise: weights uniform on +-1/sqrt(fan_in) from Philox keyed by seed,
+ * biases and Adam state 0, norm (0, 1).  Synchronous.  Errors: GGA_E_ARG,
+ * GGA_E_HIP. */
+int gga_mlp_init(void* net_d, uint64_t seed, hipStream_t stream);
+
+/* Set the target normalisation (mean, standard deviation) from n fitness
+ * values (device).  Errors: GGA_E_ARG, GGA_E_HIP. */
+int gga_mlp_set_norm(void* net_d, const float* target_d, int32_t n, hipStream_t stream);
+
+/* Predicted fitness pred_d[B] (de-normalised) of protocols dose_d[B][K],
+ * gap_h_d[B][K], nfrac_d[B] (K <= GGA_KMAX; fractions past 40 are ignored).
+ * Errors: GGA_E_ARG, GGA_E_HIP. */
+int gga_mlp_predict(const void* net_d, const float* dose_d, const int32_t* gap_h_d,
+                    const int32_t* nfrac_d, int32_t B, int32_t K, void* work_d, size_t work_bytes,
+                    float* pred_d, hipStream_t stream);
+
+/* Forward and backward pass of the loss mean((y - (t - mu)/sigma)^2) over a
+ * batch with targets target_d[B]; gradients land in the net buffer's gradient
+ * block, the loss in loss_d[0] (or NULL).  Errors: GGA_E_ARG, GGA_E_HIP. */
+int gga_mlp_grad(void* net_d, const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d,
+                 const float* target_d, int32_t B, int32_t K, void* work_d, size_t work_bytes,
+                 float* loss_d, hipStream_t stream);
+
+/* gga_mlp_grad, then one Adam step (step counts from 1) with learning rate lr
+ * and a refresh of the bf16 copies.  Errors: GGA_E_ARG, GGA_E_HIP. */
+int gga_mlp_train_step(void* net_d, const float* dose_d, const int32_t* gap_h_d,
+                       const int32_t* nfrac_d, const float* target_d, int32_t B, int32_t K,
+                       int32_t step, float lr, void* work_d, size_t work_bytes, float* loss_d,
+                       hipStream_t stream);
+
+/* Test hook of the MLP's MFMA GEMM: C_d[M][N] (f32) = A * B with bf16 inputs
+ * A stored [M][K] (or [K][M] if a_trans) and B stored [K][N] (or [N][K] if
+ * b_trans).  Errors: GGA_E_ARG, GGA_E_HIP. */
+int gga_mlp_gemm(int32_t M, int32_t N, int32_t K, const void* A_d, int32_t a_trans, const void* B_d,
+                 int32_t b_trans, float* C_d, hipStream_t stream);
+
+/* Surrogate-screened GA settings.  Set struct_size = sizeof(gga_sga_cfg). */
+typedef struct gga_sga_cfg {
+    uint32_t struct_size;
+    int32_t n_candidates;   /* C: offspring bred and screened per generation, >= 2      */
+    int32_t n_simulated;    /* S: screened offspring fully simulated, 1 .. C            */
+    int32_t screen;         /* 1: the S best predicted by the surrogate; 0: S random     */
+} gga_sga_cfg;
+
+/* Device workspace of the surrogate-screened GA. */
+size_t gga_sga_workspace_bytes(int32_t N, int32_t K, int32_t R, int32_t C, int32_t S);
+
+/*
+ * Prepare a surrogate-screened GA: simulate the initial population
+ * pop_dose_d[N][K], pop_gap_d[N][K] (R replicas, Philox key cfg->seed) into
+ * pop_fit_d[0 .. N-1] and set the generation counter to 0.  The population
+ * arrays have N + S rows; rows N .. N+S-1 are working space.
+ * Errors: as gga_simulate; GGA_E_ARG for a small workspace.
+ */
+int gga_sga_init(const gga_params* params, const gga_sim_cfg* cfg, const gga_sga_cfg* sga,
+                 float* pop_dose_d, int32_t* pop_gap_d, float* pop_fit_d, int32_t N, int32_t K,
+                 void* ws_d, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * One surrogate-screened generation, stream-ordered: rank the population by
+ * its simulated fitness, breed C candidates with the GA operators (as
+ * gga_ga_breed, no elites), predict their fitness with the surrogate net_d
+ * (gga_mlp_*), fully simulate the S best-predicted candidates as members of
+ * population g + 1 (Philox key cfg->seed + (g + 1) * 0x9E3779B97F4A7C15, the
+ * initial population being population 0), and keep the best N of the N + S
+ * evaluated protocols, sorted, in rows 0 .. N-1.  hist_d[g] = (best, mean)
+ * fitness of the kept population.  With screen = 0 the S candidates are
+ * picked at random instead (the same loop without the surrogate).
+ * Errors: as gga_ga_generation.
+ */
+int gga_sga_generation(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga,
+                       const gga_alphabet* a, const gga_sga_cfg* sga, const void* net_d,
+                       float* pop_dose_d, int32_t* pop_gap_d, float* pop_fit_d, int32_t N, int32_t K,
+                       void* ws_d, size_t ws_bytes, float* hist_d, int32_t hist_cap,
+                       hipStream_t stream);
+
+/*
+ * Generations g0 .. g0+n_gen-1 of gga_sga_generation, host-driven
+ * (use_graph = 0) or as a captured hipGraph replayed (use_graph = 1); timing
+ * and history as gga_ga_run.  Synchronous; creates and destroys HIP graphs
+ * and events; allocates no device memory.  Errors: as gga_sga_generation.
+ */
+int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga,
+                const gga_alphabet* a, const gga_sga_cfg* sga, const void* net_d, float* pop_dose_d,
+                int32_t* pop_gap_d, float* pop_fit_d, int32_t N, int32_t K, int32_t g0, int32_t n_gen,
+                int32_t use_graph, void* ws_d, size_t ws_bytes, float* hist_d, float* gen_ms_h,
+                hipStream_t stream);
+
+/*
  * Philox4x32-10 blocks (Salmon et al., SC'11) from the device implementation
  * the simulator uses: out_d[i][0..3] = Philox(counter ctr_d[i][0..3], key
  * (seed lo, seed hi)) for i < n.  A test hook.

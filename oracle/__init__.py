@@ -8,6 +8,7 @@ tests, on the same seeded inputs.
 
 Modules: philox (Philox4x32-10), model (constants), protocol (validation,
 events, LQ thresholds, counting and sampling of protocols), sim (the lattice
-automaton), stats (two-sample tests used by the trajectory comparisons).
+automaton), ga (GA operators), mlp (float64 surrogate network), sga (one
+generation of the surrogate-screened GA with a random screen).
 """
-from . import model, philox, protocol, sim  # noqa: F401
+from . import ga, mlp, model, philox, protocol, sga, sim  # noqa: F401

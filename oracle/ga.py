@@ -73,23 +73,25 @@ def guard(q, dose_q, cap_q):
     return q
 
 
-def next_generation(dose, gap, fitness, generation, seed, alphabet, n_elite, k, p_cross, p_mut):
-    """Return (next_dose, next_gap) of the same shape."""
+def next_generation(dose, gap, fitness, generation, seed, alphabet, n_elite, k, p_cross, p_mut, n_out=None):
+    """Return (next_dose, next_gap) with n_out rows (default: as many as the
+    population); slots n_elite .. n_out-1 hold children."""
     dose = np.asarray(dose, np.float32)
     gap = np.asarray(gap, np.int32)
     N, K = dose.shape
+    n_out = N if n_out is None else int(n_out)
     quantum = float(np.float32(alphabet["dose_quantum"]))
     dose_q = [int(v) for v in alphabet["dose_q"]]
     gaps = [int(v) for v in alphabet["gaps"]]
     cap_q = int(math.floor(float(np.float32(alphabet["cap"])) / quantum + 1e-9))
     order, position = rank_order(fitness)
-    out_d = np.zeros_like(dose)
-    out_g = np.zeros_like(gap)
+    out_d = np.zeros((n_out, K), np.float32)
+    out_g = np.zeros((n_out, K), np.int32)
     out_d[:n_elite] = dose[order[:n_elite]]
     out_g[:n_elite] = gap[order[:n_elite]]
     nb = (k + 3) // 4
     t_cross, t_mut = _threshold(p_cross), _threshold(p_mut)
-    n_pairs = (N - n_elite + 1) // 2
+    n_pairs = (n_out - n_elite + 1) // 2
     for c in range(n_pairs):
         parents = []
         for t in range(2):
@@ -109,7 +111,7 @@ def next_generation(dose, gap, fitness, generation, seed, alphabet, n_elite, k, 
             kids = [list(ga), list(gb)]
         for ch in range(2):
             slot = n_elite + 2 * c + ch
-            if slot >= N:
+            if slot >= n_out:
                 break
             genes = kids[ch]
             for j in range(K):

@@ -57,6 +57,11 @@ class Alphabet(ctypes.Structure):
     ]
 
 
+class SgaCfg(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n_candidates", ctypes.c_int32),
+                ("n_simulated", ctypes.c_int32), ("screen", ctypes.c_int32)]
+
+
 class GaCfg(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32), ("n_elite", ctypes.c_int32), ("tournament_k", ctypes.c_int32),
@@ -87,6 +92,21 @@ def _load():
                                i32, vp], ctypes.c_int),
         "gga_ga_run": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, ctypes.c_size_t, vp,
                         vp, vp], ctypes.c_int),
+        "gga_mlp_net_bytes": ([], ctypes.c_size_t),
+        "gga_mlp_work_bytes": ([i32], ctypes.c_size_t),
+        "gga_mlp_init": ([vp, u64, vp], ctypes.c_int),
+        "gga_mlp_set_norm": ([vp, vp, i32, vp], ctypes.c_int),
+        "gga_mlp_predict": ([vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
+        "gga_mlp_grad": ([vp, vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
+        "gga_mlp_train_step": ([vp, vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, ctypes.c_size_t, vp, vp],
+                               ctypes.c_int),
+        "gga_mlp_gemm": ([i32, i32, i32, vp, i32, vp, i32, vp, vp], ctypes.c_int),
+        "gga_sga_workspace_bytes": ([i32, i32, i32, i32, i32], ctypes.c_size_t),
+        "gga_sga_init": ([vp, vp, vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "gga_sga_generation": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, i32, vp],
+                               ctypes.c_int),
+        "gga_sga_run": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, ctypes.c_size_t, vp, vp,
+                         vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -99,7 +119,9 @@ LIB = _load()
 EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
            "gga_population_random", "gga_simulate", "gga_state_init", "gga_state_run",
            "gga_philox_fill", "gga_ga_breed", "gga_ga_workspace_bytes", "gga_ga_set_generation",
-           "gga_ga_generation", "gga_ga_run")
+           "gga_ga_generation", "gga_ga_run", "gga_mlp_net_bytes", "gga_mlp_work_bytes", "gga_mlp_init",
+           "gga_mlp_set_norm", "gga_mlp_predict", "gga_mlp_grad", "gga_mlp_train_step", "gga_mlp_gemm",
+           "gga_sga_workspace_bytes", "gga_sga_init", "gga_sga_generation", "gga_sga_run")
 
 
 class GGAError(RuntimeError):
@@ -334,3 +356,156 @@ def ga_run(params, cfg, ga, alphabet, dose, gap, n_gen, use_graph, g0=0, hist=No
     torch.cuda.current_stream().wait_stream(side)
     final = (da, ga_) if n_gen % 2 == 0 else (db, gb)
     return final[0], final[1], h[:g0 + n_gen], gen_ms[:n_gen]
+
+
+# ---------------------------------------------------------------- surrogate MLP
+
+MLP_IN, MLP_HID = 128, 512
+MLP_SHAPES = [(MLP_IN, MLP_HID), (MLP_HID,), (MLP_HID, MLP_HID), (MLP_HID,), (MLP_HID, MLP_HID), (MLP_HID,),
+              (MLP_HID,), (1,)]
+MLP_PARAMS = sum(int(np.prod(s)) for s in MLP_SHAPES)
+
+
+def _align256(x):
+    return (x + 255) & ~255
+
+
+def mlp_layout():
+    """Byte offsets of the net buffer's blocks (norm, params, m, v, grads)."""
+    off, out = 0, {}
+    for name, size in (("norm", 8), ("p", 4 * MLP_PARAMS), ("m", 4 * MLP_PARAMS), ("v", 4 * MLP_PARAMS),
+                       ("g", 4 * MLP_PARAMS)):
+        out[name] = off
+        off += _align256(size)
+    return out
+
+
+def mlp_net(seed=0, device="cuda", stream=None):
+    net = torch.empty(int(LIB.gga_mlp_net_bytes()), dtype=torch.uint8, device=device)
+    _check(LIB.gga_mlp_init(_ptr(net), int(seed), _stream(stream)))
+    return net
+
+
+def mlp_block(net, name):
+    """float32 view of a block of the net buffer (norm, p, m, v or g)."""
+    off = mlp_layout()[name]
+    n = 2 if name == "norm" else MLP_PARAMS
+    return net[off:off + 4 * n].view(torch.float32)
+
+
+def mlp_split(flat):
+    """Split a flat parameter-ordered vector into the per-tensor shapes."""
+    out, i = [], 0
+    for s in MLP_SHAPES:
+        n = int(np.prod(s))
+        out.append(flat[i:i + n].reshape(s))
+        i += n
+    return out
+
+
+def mlp_work(B, device="cuda"):
+    return torch.empty(max(int(LIB.gga_mlp_work_bytes(B)), 1), dtype=torch.uint8, device=device)
+
+
+def mlp_set_norm(net, target, stream=None):
+    _check(LIB.gga_mlp_set_norm(_ptr(net), _ptr(target), target.numel(), _stream(stream)))
+
+
+def mlp_predict(net, dose, gap, nfrac, work=None, out=None, stream=None):
+    B, K = _protocols(dose, gap, nfrac)
+    work = work if work is not None else mlp_work(B, dose.device)
+    pred = out if out is not None else torch.empty(B, dtype=torch.float32, device=dose.device)
+    _check(LIB.gga_mlp_predict(_ptr(net), _ptr(dose), _ptr(gap), _ptr(nfrac), B, K, _ptr(work), work.numel(),
+                               _ptr(pred), _stream(stream)))
+    return pred
+
+
+def mlp_grad(net, dose, gap, nfrac, target, work=None, stream=None):
+    B, K = _protocols(dose, gap, nfrac)
+    work = work if work is not None else mlp_work(B, dose.device)
+    loss = torch.empty(1, dtype=torch.float32, device=dose.device)
+    _check(LIB.gga_mlp_grad(_ptr(net), _ptr(dose), _ptr(gap), _ptr(nfrac), _ptr(target), B, K, _ptr(work),
+                            work.numel(), _ptr(loss), _stream(stream)))
+    return loss
+
+
+def mlp_train_step(net, dose, gap, nfrac, target, step, lr, work=None, loss=None, stream=None):
+    B, K = _protocols(dose, gap, nfrac)
+    work = work if work is not None else mlp_work(B, dose.device)
+    loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=dose.device)
+    _check(LIB.gga_mlp_train_step(_ptr(net), _ptr(dose), _ptr(gap), _ptr(nfrac), _ptr(target), B, K, int(step),
+                                  float(lr), _ptr(work), work.numel(), _ptr(loss), _stream(stream)))
+    return loss
+
+
+def mlp_gemm(A, B, a_trans=False, b_trans=False, stream=None):
+    """C = op(A) op(B) with the MLP's MFMA kernel (bf16 in, f32 out)."""
+    if A.dtype != torch.bfloat16 or B.dtype != torch.bfloat16:
+        raise ValueError("A and B must be bfloat16")
+    M, K = (A.shape[1], A.shape[0]) if a_trans else A.shape
+    K2, N = (B.shape[1], B.shape[0]) if b_trans else B.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _check(LIB.gga_mlp_gemm(M, N, K, _ptr(A.contiguous()), int(a_trans), _ptr(B.contiguous()), int(b_trans),
+                            _ptr(C), _stream(stream)))
+    return C
+
+
+# ---------------------------------------------------------------- surrogate-screened GA
+
+def make_sga(n_candidates, n_simulated, screen=True):
+    c = SgaCfg()
+    c.struct_size = ctypes.sizeof(SgaCfg)
+    c.n_candidates, c.n_simulated, c.screen = int(n_candidates), int(n_simulated), int(bool(screen))
+    return c
+
+
+class SurrogateGA:
+    """Population (N + S rows) and workspace of a surrogate-screened GA run.
+
+    init() simulates the initial population; run() advances generations (in
+    chunks if wanted: continuing with g0 reproduces one longer run)."""
+
+    def __init__(self, params, cfg, ga, alphabet, sga, net, dose, gap):
+        self.params, self.cfg, self.ga, self.alphabet, self.sga, self.net = _as_params(params), cfg, ga, alphabet, sga, net
+        N, K = dose.shape
+        S = sga.n_simulated
+        self.N, self.K = N, K
+        dev = dose.device
+        self.dose = torch.zeros((N + S, K), dtype=torch.float32, device=dev)
+        self.gap = torch.zeros((N + S, K), dtype=torch.int32, device=dev)
+        self.fit = torch.full((N + S,), float("nan"), dtype=torch.float32, device=dev)
+        self.dose[:N] = dose
+        self.gap[:N] = gap
+        self.ws = torch.empty(int(LIB.gga_sga_workspace_bytes(N, K, cfg.R, sga.n_candidates, S)),
+                              dtype=torch.uint8, device=dev)
+        self.hist = None
+        self.g = 0
+        self.stream = torch.cuda.Stream(device=dev)     # capturable (not the legacy default stream)
+
+    def init(self):
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.stream):
+            _check(LIB.gga_sga_init(ctypes.byref(self.params), ctypes.byref(self.cfg), ctypes.byref(self.sga),
+                                    _ptr(self.dose), _ptr(self.gap), _ptr(self.fit), self.N, self.K, _ptr(self.ws),
+                                    self.ws.numel(), ctypes.c_void_p(self.stream.cuda_stream)))
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def run(self, n_gen, use_graph=True):
+        rows = self.g + n_gen
+        h = torch.full((max(rows, 1), 2), float("nan"), dtype=torch.float32, device=self.dose.device)
+        if self.hist is not None:
+            h[:self.hist.shape[0]] = self.hist
+        gen_ms = np.zeros(max(n_gen, 1), dtype=np.float32)
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.stream):
+            _check(LIB.gga_sga_run(ctypes.byref(self.params), ctypes.byref(self.cfg), ctypes.byref(self.ga),
+                                   ctypes.byref(self.alphabet), ctypes.byref(self.sga), _ptr(self.net),
+                                   _ptr(self.dose), _ptr(self.gap), _ptr(self.fit), self.N, self.K, self.g, n_gen,
+                                   int(bool(use_graph)), _ptr(self.ws), self.ws.numel(), _ptr(h),
+                                   gen_ms.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(self.stream.cuda_stream)))
+        torch.cuda.current_stream().wait_stream(self.stream)
+        self.hist = h[:rows]
+        self.g = rows
+        return gen_ms[:n_gen]

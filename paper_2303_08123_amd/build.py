@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgga.so")
-SOURCES = ["gga_host.cpp", "sim.hip", "population.hip", "ga.hip"]
+SOURCES = ["gga_host.cpp", "sim.hip", "population.hip", "ga.hip", "mlp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

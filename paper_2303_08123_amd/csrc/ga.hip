@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void history_kernel(const float* fitness, int 
     if (threadIdx.x == 0) {
         const int g = *generation;
         if (g >= 0 && g < hist_cap) {
-            hist[2 * g] = fitness[order[0]];
+            hist[2 * g] = fitness[order ? order[0] : 0];
             hist[2 * g + 1] = s_cnt[0] ? (float)(s_sum[0] / s_cnt[0]) : __builtin_nanf("");
         }
     }
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(128) void offspring_kernel(GaArgs a) {
         return;
     }
     const int c = t - a.n_elite;                           // child pair
-    const int n_pairs = (N - a.n_elite + 1) / 2;
+    const int n_pairs = (a.n_out - a.n_elite + 1) / 2;
     if (c < 0 || c >= n_pairs) return;
     const int nb = (a.k + 3) / 4;
     int parent[2];
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(128) void offspring_kernel(GaArgs a) {
     if (bc.w0 < a.t_cross && K > 1) cut = 1 + (int)(((uint64_t)bc.w1 * (uint32_t)(K - 1)) >> 32);
     for (int ch = 0; ch < 2; ++ch) {
         const int slot = a.n_elite + 2 * c + ch;
-        if (slot >= N) break;
+        if (slot >= a.n_out) break;
         int q[GGA_KMAX], gp[GGA_KMAX];
         int total = 0;
         for (int j = 0; j < K; ++j) {
@@ -162,8 +162,41 @@ __global__ __launch_bounds__(128) void offspring_kernel(GaArgs a) {
     }
 }
 
+// dst rows i < n = src rows idx[i] (or row i when idx is null), K genes each,
+// plus an optional float per row.
+__global__ void gather_kernel(const float* sd, const int32_t* sg, const float* sf, const int32_t* idx, int n, int K,
+                              float* dd, int32_t* dg, float* df) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int src = idx ? idx[i] : i;
+    for (int j = 0; j < K; ++j) {
+        dd[(size_t)i * K + j] = sd[(size_t)src * K + j];
+        dg[(size_t)i * K + j] = sg[(size_t)src * K + j];
+    }
+    if (sf && df) df[i] = sf[src];
+}
+
+// Uniform random keys (Philox blocks (i, generation, 0x53435245, 0)): the
+// screening ablation that picks candidates without the surrogate.
+__global__ void random_key_kernel(int n, const int32_t* generation, uint32_t k0, uint32_t k1, float* key) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Block4 b = philox10((uint32_t)i, (uint32_t)*generation, 0x53435245u, 0u, k0, k1);
+    key[i] = (float)(b.w0 >> 8);
+}
+
+// fill an int32 array with a value
+__global__ void fill_kernel(int32_t* p, int n, int32_t v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void counter_kernel(int32_t* generation, int32_t value, int32_t add) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *generation = add ? *generation + value : value;
+}
+
+__global__ void counter_copy_kernel(int32_t* dst, const int32_t* src, int32_t add) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src + add;
 }
 
 }  // namespace
@@ -182,14 +215,39 @@ hipError_t launch_history(const float* fitness, int N, const int32_t* order, con
 }
 
 hipError_t launch_offspring(const GaArgs& a, hipStream_t s) {
-    const int threads = a.n_elite + (a.N - a.n_elite + 1) / 2;
+    const int threads = a.n_elite + (a.n_out - a.n_elite + 1) / 2;
     if (threads <= 0) return hipSuccess;
     hipLaunchKernelGGL(offspring_kernel, dim3((threads + 127) / 128), dim3(128), 0, s, a);
     return hipGetLastError();
 }
 
+hipError_t launch_gather(const float* sd, const int32_t* sg, const float* sf, const int32_t* idx, int n, int K,
+                         float* dd, int32_t* dg, float* df, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_kernel, dim3((n + 127) / 128), dim3(128), 0, s, sd, sg, sf, idx, n, K, dd, dg, df);
+    return hipGetLastError();
+}
+
+hipError_t launch_random_keys(int n, const int32_t* generation, uint64_t seed, float* key, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(random_key_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, generation, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), key);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int32_t* p, int n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_counter(int32_t* generation, int32_t value, int32_t add, hipStream_t s) {
     hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, s, generation, value, add);
+    return hipGetLastError();
+}
+
+hipError_t launch_counter_copy(int32_t* dst, const int32_t* src, int32_t add, hipStream_t s) {
+    hipLaunchKernelGGL(counter_copy_kernel, dim3(1), dim3(64), 0, s, dst, src, add);
     return hipGetLastError();
 }
 

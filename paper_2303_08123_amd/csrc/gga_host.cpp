@@ -3,6 +3,7 @@
 // marshals arguments.
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <limits>
 #include <vector>
 
@@ -290,6 +291,7 @@ int check_ga(const gga_ga_cfg* ga, const gga_alphabet* a, int32_t N, int32_t K, 
     if (capq > 1e6 || (long long)K * a->dose_q[0] > capq) return GGA_E_ALPHABET;   // guard must succeed
     std::memset(out, 0, sizeof(*out));
     out->N = N;
+    out->n_out = N;
     out->K = K;
     out->n_elite = ga->n_elite;
     out->k = ga->tournament_k;
@@ -331,6 +333,46 @@ hipError_t enqueue_generation(const gga_params* params, const gga_sim_cfg* cfg, 
     ga_args.next_gap = next_gap;
     if (e == hipSuccess) e = gga::launch_offspring(ga_args, stream);
     if (e == hipSuccess && advance) e = gga::launch_counter(w.generation, 1, 1, stream);
+    return e;
+}
+
+// Run generations g0 .. g0+n_gen-1 of enqueue(d) (d = generation parity):
+// host-driven (enqueue, wait) or as two captured hipGraphs replayed back to
+// back.  gen_ms[g] = time from the start to the end of generation g0 + g.
+template <class F>
+hipError_t run_generations(F enqueue, int32_t* counter, int32_t g0, int32_t n_gen, int32_t use_graph,
+                           float* gen_ms, hipStream_t stream) {
+    std::vector<hipEvent_t> ev(static_cast<size_t>(n_gen) + 1, nullptr);
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (auto& x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    if (e == hipSuccess && use_graph) {
+        for (int d = 0; d < 2 && e == hipSuccess; ++d) {
+            e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) break;
+            const hipError_t ee = enqueue(d);
+            e = hipStreamEndCapture(stream, &graph[d]);
+            if (ee != hipSuccess) e = ee;
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec[d], graph[d], nullptr, nullptr, 0);
+        }
+    }
+    if (e == hipSuccess) e = gga::launch_counter(counter, g0, 0, stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+    for (int g = 0; g < n_gen && e == hipSuccess; ++g) {
+        e = use_graph ? hipGraphLaunch(exec[g & 1], stream) : enqueue(g & 1);
+        if (e == hipSuccess) e = hipEventRecord(ev[g + 1], stream);
+        if (e == hipSuccess && !use_graph) e = hipStreamSynchronize(stream);   // host-driven loop
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    for (int g = 0; g < n_gen && e == hipSuccess && gen_ms; ++g) e = hipEventElapsedTime(&gen_ms[g], ev[0], ev[g + 1]);
+    for (int d = 0; d < 2; ++d) {
+        if (exec[d]) (void)hipGraphExecDestroy(exec[d]);
+        if (graph[d]) (void)hipGraphDestroy(graph[d]);
+    }
+    for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
     return e;
 }
 
@@ -406,44 +448,378 @@ int gga_ga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cf
     const GaWorkspace w = ga_ws(ws_d, N, cfg->R);
     float* pd[2] = {dose_a_d, dose_b_d};
     int32_t* pg[2] = {gap_a_d, gap_b_d};
-    std::vector<hipEvent_t> ev(static_cast<size_t>(n_gen) + 1, nullptr);
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    hipError_t e = hipSuccess;
-    for (auto& x : ev)
-        if (e == hipSuccess) e = hipEventCreate(&x);
-    if (e == hipSuccess && use_graph) {
-        for (int d = 0; d < 2 && e == hipSuccess; ++d) {
-            e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) break;
-            const hipError_t ee = enqueue_generation(params, cfg, ga_args, pd[d], pg[d], nfrac_d, N, K, pd[1 - d],
-                                                     pg[1 - d], w, hist_d, hist_cap, 1, stream);
-            e = hipStreamEndCapture(stream, &graph[d]);
-            if (ee != hipSuccess) e = ee;
-            if (e == hipSuccess) e = hipGraphInstantiate(&exec[d], graph[d], nullptr, nullptr, 0);
-        }
+    auto enqueue = [&](int d) {
+        return enqueue_generation(params, cfg, ga_args, pd[d], pg[d], nfrac_d, N, K, pd[1 - d], pg[1 - d], w,
+                                  hist_d, hist_cap, 1, stream);
+    };
+    const hipError_t e = run_generations(enqueue, w.generation, g0, n_gen, use_graph, gen_ms_h, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ surrogate MLP
+
+namespace gga {
+
+namespace {
+struct Layout {
+    size_t norm, p, m, v, g, wb[3], wtb[3], total;
+};
+Layout net_layout() {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t at = off; off += align256(bytes); return at; };
+    L.norm = take(2 * sizeof(float));
+    L.p = take(sizeof(float) * MLP_PARAMS);
+    L.m = take(sizeof(float) * MLP_PARAMS);
+    L.v = take(sizeof(float) * MLP_PARAMS);
+    L.g = take(sizeof(float) * MLP_PARAMS);
+    for (int l = 0; l < 3; ++l) {
+        const size_t k = l == 0 ? MLP_IN : MLP_HID;
+        L.wb[l] = take(sizeof(uint16_t) * k * MLP_HID);
+        L.wtb[l] = take(sizeof(uint16_t) * k * MLP_HID);
     }
-    if (e == hipSuccess) e = gga::launch_counter(w.generation, g0, 0, stream);
-    if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
-    for (int g = 0; g < n_gen && e == hipSuccess; ++g) {
-        const int d = g & 1;
-        if (use_graph) {
-            e = hipGraphLaunch(exec[d], stream);
-        } else {
-            e = enqueue_generation(params, cfg, ga_args, pd[d], pg[d], nfrac_d, N, K, pd[1 - d], pg[1 - d], w,
-                                   hist_d, hist_cap, 1, stream);
-        }
-        if (e == hipSuccess) e = hipEventRecord(ev[g + 1], stream);
-        if (e == hipSuccess && !use_graph) e = hipStreamSynchronize(stream);   // host-driven loop
+    L.total = off;
+    return L;
+}
+}  // namespace
+
+size_t mlp_net_bytes() { return net_layout().total; }
+
+MlpNet mlp_net(void* base) {
+    const Layout L = net_layout();
+    char* c = static_cast<char*>(base);
+    MlpNet n{};
+    n.norm = reinterpret_cast<float*>(c + L.norm);
+    n.p = reinterpret_cast<float*>(c + L.p);
+    n.m = reinterpret_cast<float*>(c + L.m);
+    n.v = reinterpret_cast<float*>(c + L.v);
+    n.g = reinterpret_cast<float*>(c + L.g);
+    float* p = n.p;
+    float* g = n.g;
+    for (int l = 0; l < 3; ++l) {
+        const long k = l == 0 ? MLP_IN : MLP_HID;
+        n.Wf[l] = p;
+        n.gW[l] = g;
+        p += k * MLP_HID;
+        g += k * MLP_HID;
+        n.b[l] = p;
+        n.gb[l] = g;
+        p += MLP_HID;
+        g += MLP_HID;
+        n.W[l] = reinterpret_cast<__bf16*>(c + L.wb[l]);
+        n.WT[l] = reinterpret_cast<__bf16*>(c + L.wtb[l]);
     }
+    n.w4 = p;
+    n.gw4 = g;
+    n.b4 = p + MLP_HID;
+    n.gb4 = g + MLP_HID;
+    return n;
+}
+
+size_t mlp_work_bytes(int B) {
+    const size_t b = static_cast<size_t>(B);
+    return align256(2 * b * MLP_IN) + 3 * align256(4 * b * MLP_HID) + 3 * align256(2 * b * MLP_HID) +
+           2 * align256(4 * b) + 2 * align256(2 * b * MLP_HID);
+}
+
+MlpWork mlp_work(void* base, int B) {
+    const size_t b = static_cast<size_t>(B);
+    char* c = static_cast<char*>(base);
+    MlpWork w{};
+    w.X = reinterpret_cast<__bf16*>(c);
+    c += align256(2 * b * MLP_IN);
+    for (int l = 0; l < 3; ++l) { w.Z[l] = reinterpret_cast<float*>(c); c += align256(4 * b * MLP_HID); }
+    for (int l = 0; l < 3; ++l) { w.H[l] = reinterpret_cast<__bf16*>(c); c += align256(2 * b * MLP_HID); }
+    w.y = reinterpret_cast<float*>(c);
+    c += align256(4 * b);
+    w.dy = reinterpret_cast<float*>(c);
+    c += align256(4 * b);
+    for (int l = 0; l < 2; ++l) { w.dZ[l] = reinterpret_cast<__bf16*>(c); c += align256(2 * b * MLP_HID); }
+    return w;
+}
+
+}  // namespace gga
+
+namespace {
+int mlp_check(const void* net, int32_t B, int32_t K, const float* dose, const int32_t* gap, const int32_t* nfrac,
+              const void* work, size_t work_bytes) {
+    if (!net || B < 0 || K < 0 || K > GGA_KMAX) return GGA_E_ARG;
+    if (B > 0 && (!nfrac || !work || (K > 0 && (!dose || !gap)))) return GGA_E_ARG;
+    if ((long long)B * gga::MLP_HID > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
+    if (B > 0 && work_bytes < gga::mlp_work_bytes(B)) return GGA_E_ARG;
+    return GGA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t gga_mlp_net_bytes(void) { return gga::mlp_net_bytes(); }
+
+size_t gga_mlp_work_bytes(int32_t B) { return B < 0 ? 0 : gga::mlp_work_bytes(B); }
+
+int gga_mlp_init(void* net_d, uint64_t seed, hipStream_t stream) {
+    if (!net_d) return GGA_E_ARG;
+    const gga::MlpNet net = gga::mlp_net(net_d);
+    hipError_t e = gga::mlp_init(net, seed, stream);
+    // normalisation defaults to (0, 1) until gga_mlp_set_norm
+    static const float unit[2] = {0.0f, 1.0f};
+    if (e == hipSuccess) e = hipMemcpyAsync(net.norm, unit, sizeof(unit), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    for (int g = 0; g < n_gen && e == hipSuccess && gen_ms_h; ++g) e = hipEventElapsedTime(&gen_ms_h[g], ev[0], ev[g + 1]);
-    for (int d = 0; d < 2; ++d) {
-        if (exec[d]) (void)hipGraphExecDestroy(exec[d]);
-        if (graph[d]) (void)hipGraphDestroy(graph[d]);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_mlp_set_norm(void* net_d, const float* target_d, int32_t n, hipStream_t stream) {
+    if (!net_d || n < 1 || !target_d) return GGA_E_ARG;
+    const hipError_t e = gga::mlp_set_norm(gga::mlp_net(net_d), target_d, n, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_mlp_predict(const void* net_d, const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d,
+                    int32_t B, int32_t K, void* work_d, size_t work_bytes, float* pred_d, hipStream_t stream) {
+    const int rc = mlp_check(net_d, B, K, dose_d, gap_h_d, nfrac_d, work_d, work_bytes);
+    if (rc) return rc;
+    if (B == 0) return GGA_OK;
+    if (!pred_d) return GGA_E_ARG;
+    const hipError_t e = gga::mlp_forward(gga::mlp_net(const_cast<void*>(net_d)), dose_d, gap_h_d, nfrac_d, B, K,
+                                          gga::mlp_work(work_d, B), pred_d, true, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_mlp_grad(void* net_d, const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d,
+                 const float* target_d, int32_t B, int32_t K, void* work_d, size_t work_bytes, float* loss_d,
+                 hipStream_t stream) {
+    const int rc = mlp_check(net_d, B, K, dose_d, gap_h_d, nfrac_d, work_d, work_bytes);
+    if (rc) return rc;
+    if (B < 1 || !target_d) return GGA_E_ARG;
+    const gga::MlpNet net = gga::mlp_net(net_d);
+    const gga::MlpWork w = gga::mlp_work(work_d, B);
+    hipError_t e = gga::mlp_forward(net, dose_d, gap_h_d, nfrac_d, B, K, w, w.y, false, stream);
+    if (e == hipSuccess) e = gga::mlp_backward(net, B, target_d, w, loss_d, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_mlp_train_step(void* net_d, const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d,
+                       const float* target_d, int32_t B, int32_t K, int32_t step, float lr, void* work_d,
+                       size_t work_bytes, float* loss_d, hipStream_t stream) {
+    if (step < 1 || !(lr > 0.0f) || !std::isfinite(lr)) return GGA_E_ARG;
+    int rc = gga_mlp_grad(net_d, dose_d, gap_h_d, nfrac_d, target_d, B, K, work_d, work_bytes, loss_d, stream);
+    if (rc) return rc;
+    const hipError_t e = gga::mlp_adam_refresh(gga::mlp_net(net_d), step, lr, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_mlp_gemm(int32_t M, int32_t N, int32_t K, const void* A_d, int32_t a_trans, const void* B_d,
+                 int32_t b_trans, float* C_d, hipStream_t stream) {
+    if (M < 0 || N < 0 || K < 0 || (M > 0 && N > 0 && (!C_d || (K > 0 && (!A_d || !B_d))))) return GGA_E_ARG;
+    gga::MlpGemm g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = static_cast<const __bf16*>(A_d);
+    g.sa_m = a_trans ? 1 : K;        // A stored [M][K], or [K][M] when transposed
+    g.sa_k = a_trans ? M : 1;
+    g.B = static_cast<const __bf16*>(B_d);
+    g.sb_k = b_trans ? 1 : N;        // B stored [K][N], or [N][K] when transposed
+    g.sb_n = b_trans ? K : 1;
+    g.mode = gga::MLP_PLAIN;
+    g.C = C_d;
+    g.ldc = N;
+    const hipError_t e = gga::launch_gemm(g, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ surrogate-screened GA
+
+namespace {
+
+struct SgaWorkspace {
+    int32_t* generation;
+    int32_t* sim_key;       // generation + 1: offspring of generation g join population g + 1
+    float* cand_dose;
+    int32_t* cand_gap;
+    float* pred;
+    int32_t *order_c, *pos_c, *order_p, *pos_p;
+    int32_t* live;
+    int32_t* nfrac;
+    float* tmp_dose;
+    int32_t* tmp_gap;
+    float* tmp_fit;
+    void* mlp_work;
+    size_t mlp_work_bytes;
+};
+
+struct SgaDims {
+    int32_t N, K, R, C, S;
+};
+
+size_t sga_layout(const SgaDims& d, SgaWorkspace* w, void* base) {
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t at = off; off += align256(bytes); return p ? p + at : nullptr; };
+    const size_t C = d.C, K = d.K, NS = (size_t)d.N + d.S, MX = std::max<size_t>(C, NS);
+    SgaWorkspace s{};
+    s.generation = reinterpret_cast<int32_t*>(take(sizeof(int32_t)));
+    s.sim_key = reinterpret_cast<int32_t*>(take(sizeof(int32_t)));
+    s.cand_dose = reinterpret_cast<float*>(take(4 * C * K));
+    s.cand_gap = reinterpret_cast<int32_t*>(take(4 * C * K));
+    s.pred = reinterpret_cast<float*>(take(4 * C));
+    s.order_c = reinterpret_cast<int32_t*>(take(4 * C));
+    s.pos_c = reinterpret_cast<int32_t*>(take(4 * C));
+    s.order_p = reinterpret_cast<int32_t*>(take(4 * NS));
+    s.pos_p = reinterpret_cast<int32_t*>(take(4 * NS));
+    s.live = reinterpret_cast<int32_t*>(take(4 * (size_t)std::max(d.N, d.S) * d.R));
+    s.nfrac = reinterpret_cast<int32_t*>(take(4 * MX));
+    s.tmp_dose = reinterpret_cast<float*>(take(4 * (size_t)d.N * K));
+    s.tmp_gap = reinterpret_cast<int32_t*>(take(4 * (size_t)d.N * K));
+    s.tmp_fit = reinterpret_cast<float*>(take(4 * (size_t)d.N));
+    s.mlp_work_bytes = gga::mlp_work_bytes(d.C);
+    s.mlp_work = take(s.mlp_work_bytes);
+    if (w) *w = s;
+    return off;
+}
+
+int check_sga(const gga_sga_cfg* sga, int32_t N, int32_t K, int32_t R, SgaDims* d) {
+    if (!sga) return GGA_E_ARG;
+    if (sga->struct_size != sizeof(gga_sga_cfg)) return GGA_E_ABI;
+    if (sga->n_candidates < 2 || sga->n_simulated < 1 || sga->n_simulated > sga->n_candidates) return GGA_E_ARG;
+    if (sga->screen != 0 && sga->screen != 1) return GGA_E_ARG;
+    if (N < 2 || K < 1 || K > GGA_KMAX || R < 1) return GGA_E_ARG;
+    if ((long long)sga->n_candidates * gga::MLP_HID > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
+    if ((long long)(N + sga->n_simulated) * R > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
+    *d = SgaDims{N, K, R, sga->n_candidates, sga->n_simulated};
+    return GGA_OK;
+}
+
+hipError_t sim_rows(const gga_params* params, const gga_sim_cfg* cfg, const float* dose, const int32_t* gap,
+                    const int32_t* nfrac, int32_t P, int32_t K, const int32_t* generation, int32_t* live, float* fit,
+                    hipStream_t stream) {
+    gga::SimArgs sa = make_args(params, cfg, dose, gap, nfrac, K);
+    sa.n0 = 0;
+    sa.nsteps = cfg->horizon;
+    sa.mode = 0;
+    sa.live = live;
+    sa.generation = generation;
+    sa.seed = cfg->seed;
+    hipError_t e = gga::launch_simulation(sa, cfg->L, P * cfg->R, stream);
+    if (e == hipSuccess) e = gga::launch_fitness(live, P, cfg->R, fit, stream);
+    return e;
+}
+
+hipError_t enqueue_sga(const gga_params* params, const gga_sim_cfg* cfg, gga::GaArgs ga_args, const gga_sga_cfg* sga,
+                       const void* net, float* pop_dose, int32_t* pop_gap, float* pop_fit, const SgaDims& d,
+                       const SgaWorkspace& w, float* hist, int32_t hist_cap, hipStream_t stream) {
+    const int N = d.N, K = d.K, C = d.C, S = d.S;
+    // breed C candidates from the ranked population
+    hipError_t e = gga::launch_rank(pop_fit, N, w.order_p, w.pos_p, stream);
+    ga_args.n_elite = 0;
+    ga_args.n_out = C;
+    ga_args.dose = pop_dose;
+    ga_args.gap = pop_gap;
+    ga_args.order = w.order_p;
+    ga_args.position = w.pos_p;
+    ga_args.generation = w.generation;
+    ga_args.next_dose = w.cand_dose;
+    ga_args.next_gap = w.cand_gap;
+    if (e == hipSuccess) e = gga::launch_offspring(ga_args, stream);
+    // screen: surrogate prediction (or random keys for the ablation), keep the best S
+    if (e == hipSuccess) {
+        e = sga->screen ? gga::mlp_forward(gga::mlp_net(const_cast<void*>(net)), w.cand_dose, w.cand_gap, w.nfrac, C, K,
+                                           gga::mlp_work(w.mlp_work, C), w.pred, true, stream)
+                        : gga::launch_random_keys(C, w.generation, ((uint64_t)ga_args.seed_hi << 32) | ga_args.seed_lo,
+                                                  w.pred, stream);
     }
-    for (auto& x : ev)
-        if (x) (void)hipEventDestroy(x);
+    if (e == hipSuccess) e = gga::launch_rank(w.pred, C, w.order_c, w.pos_c, stream);
+    if (e == hipSuccess)
+        e = gga::launch_gather(w.cand_dose, w.cand_gap, nullptr, w.order_c, S, K, pop_dose + (size_t)N * K,
+                               pop_gap + (size_t)N * K, nullptr, stream);
+    // simulate the S survivors of the screen, keyed as members of population g + 1
+    if (e == hipSuccess) e = gga::launch_counter_copy(w.sim_key, w.generation, 1, stream);
+    if (e == hipSuccess)
+        e = sim_rows(params, cfg, pop_dose + (size_t)N * K, pop_gap + (size_t)N * K, w.nfrac, S, K, w.sim_key,
+                     w.live, pop_fit + N, stream);
+    // keep the best N of the N + S evaluated protocols
+    if (e == hipSuccess) e = gga::launch_rank(pop_fit, N + S, w.order_p, w.pos_p, stream);
+    if (e == hipSuccess)
+        e = gga::launch_gather(pop_dose, pop_gap, pop_fit, w.order_p, N, K, w.tmp_dose, w.tmp_gap, w.tmp_fit, stream);
+    if (e == hipSuccess)
+        e = gga::launch_gather(w.tmp_dose, w.tmp_gap, w.tmp_fit, nullptr, N, K, pop_dose, pop_gap, pop_fit, stream);
+    if (e == hipSuccess) e = gga::launch_history(pop_fit, N, nullptr, w.generation, hist, hist_cap, stream);
+    if (e == hipSuccess) e = gga::launch_counter(w.generation, 1, 1, stream);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gga_sga_workspace_bytes(int32_t N, int32_t K, int32_t R, int32_t C, int32_t S) {
+    if (N < 1 || K < 1 || R < 1 || C < 1 || S < 1) return 0;
+    return sga_layout(SgaDims{N, K, R, C, S}, nullptr, nullptr);
+}
+
+int gga_sga_init(const gga_params* params, const gga_sim_cfg* cfg, const gga_sga_cfg* sga, float* pop_dose_d,
+                 int32_t* pop_gap_d, float* pop_fit_d, int32_t N, int32_t K, void* ws_d, size_t ws_bytes,
+                 hipStream_t stream) {
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((rc = check_cfg(cfg))) return rc;
+    SgaDims d;
+    if ((rc = check_sga(sga, N, K, cfg->R, &d))) return rc;
+    if (!pop_dose_d || !pop_gap_d || !pop_fit_d || !ws_d || ws_bytes < sga_layout(d, nullptr, nullptr))
+        return GGA_E_ARG;
+    SgaWorkspace w;
+    sga_layout(d, &w, ws_d);
+    hipError_t e = gga::launch_fill(w.nfrac, std::max(d.C, d.N + d.S), K, stream);
+    if (e == hipSuccess) e = gga::launch_counter(w.generation, 0, 0, stream);
+    if (e == hipSuccess) e = sim_rows(params, cfg, pop_dose_d, pop_gap_d, w.nfrac, N, K, w.generation, w.live, pop_fit_d, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_sga_generation(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga,
+                       const gga_alphabet* a, const gga_sga_cfg* sga, const void* net_d, float* pop_dose_d,
+                       int32_t* pop_gap_d, float* pop_fit_d, int32_t N, int32_t K, void* ws_d, size_t ws_bytes,
+                       float* hist_d, int32_t hist_cap, hipStream_t stream) {
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((rc = check_cfg(cfg))) return rc;
+    SgaDims d;
+    if ((rc = check_sga(sga, N, K, cfg->R, &d))) return rc;
+    gga::GaArgs ga_args;
+    if ((rc = check_ga(ga, a, N, K, &ga_args))) return rc;
+    if (!pop_dose_d || !pop_gap_d || !pop_fit_d || !ws_d || (sga->screen && !net_d)) return GGA_E_ARG;
+    if (ws_bytes < sga_layout(d, nullptr, nullptr) || hist_cap < 0 || (hist_cap > 0 && !hist_d)) return GGA_E_ARG;
+    SgaWorkspace w;
+    sga_layout(d, &w, ws_d);
+    const hipError_t e = enqueue_sga(params, cfg, ga_args, sga, net_d, pop_dose_d, pop_gap_d, pop_fit_d, d, w, hist_d,
+                                     hist_cap, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga, const gga_alphabet* a,
+                const gga_sga_cfg* sga, const void* net_d, float* pop_dose_d, int32_t* pop_gap_d, float* pop_fit_d,
+                int32_t N, int32_t K, int32_t g0, int32_t n_gen, int32_t use_graph, void* ws_d, size_t ws_bytes,
+                float* hist_d, float* gen_ms_h, hipStream_t stream) {
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((rc = check_cfg(cfg))) return rc;
+    SgaDims d;
+    if ((rc = check_sga(sga, N, K, cfg->R, &d))) return rc;
+    gga::GaArgs ga_args;
+    if ((rc = check_ga(ga, a, N, K, &ga_args))) return rc;
+    if (!pop_dose_d || !pop_gap_d || !pop_fit_d || !ws_d || (sga->screen && !net_d) || n_gen < 0 || g0 < 0)
+        return GGA_E_ARG;
+    if ((long long)g0 + n_gen > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
+    if (ws_bytes < sga_layout(d, nullptr, nullptr) || (n_gen > 0 && !hist_d)) return GGA_E_ARG;
+    SgaWorkspace w;
+    sga_layout(d, &w, ws_d);
+    const int32_t hist_cap = g0 + n_gen;
+    auto enqueue = [&](int) {
+        return enqueue_sga(params, cfg, ga_args, sga, net_d, pop_dose_d, pop_gap_d, pop_fit_d, d, w, hist_d, hist_cap,
+                           stream);
+    };
+    const hipError_t e = run_generations(enqueue, w.generation, g0, n_gen, use_graph, gen_ms_h, stream);
     return e == hipSuccess ? GGA_OK : hip_fail(e);
 }
 

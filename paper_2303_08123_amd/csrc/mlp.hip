@@ -1,0 +1,363 @@
+// Surrogate MLP (protocol -> predicted fitness) with hand-written BF16 MFMA
+// kernels: 128 -> 512 -> 512 -> 512 -> 1, GELU(x) = x Phi(x) on the hidden
+// layers, BF16 weights and activations into v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation, FP32 master weights and Adam.  The surrogate only pre-screens
+// GA offspring; the full simulation evaluates whatever it lets through.
+//
+// Net buffer (caller-owned, gga_mlp_net_bytes()):
+//   header (normalisation mu, sigma) | params f32 | adam m | adam v | grads |
+//   bf16 copies W_l [K][N] and W_l^T [N][K] for the three MFMA layers.
+// Parameter order: W1 [128][512], b1, W2 [512][512], b2, W3 [512][512], b3,
+// w4 [512], b4 [1].
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gga_device.h"
+#include "gga_internal.h"
+
+namespace gga {
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 32, PADK = 8;   // LDS rows of BK + PADK bf16
+
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// C = A (M x K) * B (K x N) with element A(m,k) = A[m*sa_m + k*sa_k] and
+// B(k,n) = B[k*sb_k + n*sb_n]; 256 threads compute a 64 x 64 tile, each wave a
+// 32 x 32 quarter as 2 x 2 MFMA 16x16x32 blocks.
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(MlpGemm g) {
+    __shared__ bf16 As[BM][BK + PADK];
+    __shared__ bf16 Bs[BN][BK + PADK];      // stored as [n][k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int lr = tid >> 2, lk = (tid & 3) * 8;   // loader: row 0..63, k offset 0..24
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        {   // A tile
+            const int m = m0 + lr;
+            bf16x8 v;
+            if (g.sa_k == 1 && m < g.M && k0 + lk + 8 <= g.K && ((g.sa_m & 7) == 0)) {
+                v = *reinterpret_cast<const bf16x8*>(g.A + (size_t)m * g.sa_m + k0 + lk);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = k0 + lk + e;
+                    v[e] = (m < g.M && k < g.K) ? g.A[(size_t)m * g.sa_m + (size_t)k * g.sa_k] : (bf16)0.0f;
+                }
+            }
+            *reinterpret_cast<bf16x8*>(&As[lr][lk]) = v;
+        }
+        {   // B tile, transposed into [n][k]
+            const int n = n0 + lr;
+            bf16x8 v;
+            if (g.sb_k == 1 && n < g.N && k0 + lk + 8 <= g.K && ((g.sb_n & 7) == 0)) {
+                v = *reinterpret_cast<const bf16x8*>(g.B + (size_t)n * g.sb_n + k0 + lk);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = k0 + lk + e;
+                    v[e] = (n < g.N && k < g.K) ? g.B[(size_t)k * g.sb_k + (size_t)n * g.sb_n] : (bf16)0.0f;
+                }
+            }
+            *reinterpret_cast<bf16x8*>(&Bs[lr][lk]) = v;
+        }
+        __syncthreads();
+        const int fr = lane & 15, fk = (lane >> 4) * 8;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + fr][fk]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + fr][fk]);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D[4*(lane/16) + r][lane%16] of every 16x16 block
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+                const int col = n0 + wn + j * 16 + (lane & 15);
+                if (row >= g.M || col >= g.N) continue;
+                float v = acc[i][j][r] + (g.bias ? g.bias[col] : 0.0f);
+                if (g.mode == MLP_FWD) {
+                    g.Z[(size_t)row * g.ldz + col] = v;
+                    g.H[(size_t)row * g.ldh + col] = (bf16)gelu_f(v);
+                } else if (g.mode == MLP_BWD) {
+                    g.H[(size_t)row * g.ldh + col] = (bf16)(v * gelu_grad_f(g.Z[(size_t)row * g.ldz + col]));
+                } else {
+                    g.C[(size_t)row * g.ldc + col] = v;
+                }
+            }
+}
+
+// Features of protocol b: for fraction j < 40, (dose/5, gap/60, 1) if present.
+__global__ void encode_kernel(const float* dose, const int32_t* gap, const int32_t* nfrac, int B, int K,
+                              bf16* X) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * MLP_IN) return;
+    const int b = idx / MLP_IN, f = idx - b * MLP_IN;
+    const int j = f / 3, part = f - 3 * j;
+    float v = 0.0f;
+    if (j < MLP_FRAC && j < K && j < nfrac[b]) {
+        v = part == 0 ? dose[(size_t)b * K + j] * (1.0f / 5.0f)
+                      : part == 1 ? (float)gap[(size_t)b * K + j] * (1.0f / 60.0f) : 1.0f;
+    }
+    X[idx] = (bf16)v;
+}
+
+// y[b] = H3[b] . w4 + b4 (one wave per sample); optionally de-normalised.
+__global__ void out_fwd_kernel(const bf16* H3, const float* w4, const float* b4, int B, float* y,
+                               const float* norm) {
+    const int b = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (b >= B) return;
+    float s = 0.0f;
+    for (int k = lane; k < MLP_HID; k += 64) s += (float)H3[(size_t)b * MLP_HID + k] * w4[k];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) y[b] = norm ? (s + b4[0]) * norm[1] + norm[0] : s + b4[0];
+}
+
+// dy = 2 (y - t') / B with t' = (t - mu) / sigma; loss = mean (y - t')^2.
+__global__ __launch_bounds__(256) void loss_kernel(const float* y, const float* t, const float* norm, int B,
+                                                   float* dy, float* loss) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+        const float e = y[b] - (t[b] - norm[0]) / norm[1];
+        dy[b] = 2.0f * e / (float)B;
+        s += e * e;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss) loss[0] = red[0] / (float)B;
+}
+
+// dZ3[b][k] = dy[b] w4[k] gelu'(Z3[b][k])
+__global__ void out_bwd_kernel(const float* dy, const float* w4, const float* Z3, int B, bf16* dZ3) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * MLP_HID) return;
+    const int b = idx / MLP_HID, k = idx - b * MLP_HID;
+    dZ3[idx] = (bf16)(dy[b] * w4[k] * gelu_grad_f(Z3[idx]));
+}
+
+// Column sums of a [B][N] bf16 matrix (bias gradients), and dw4 / db4.
+__global__ void colsum_kernel(const bf16* D, int B, int N, float* out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int b = 0; b < B; ++b) s += (float)D[(size_t)b * N + n];
+    out[n] = s;
+}
+__global__ void out_wgrad_kernel(const bf16* H3, const float* dy, int B, float* dw4, float* db4) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < MLP_HID) {
+        float s = 0.0f;
+        for (int b = 0; b < B; ++b) s += (float)H3[(size_t)b * MLP_HID + k] * dy[b];
+        dw4[k] = s;
+    }
+    if (k == MLP_HID) {
+        float s = 0.0f;
+        for (int b = 0; b < B; ++b) s += dy[b];
+        db4[0] = s;
+    }
+}
+
+// Adam with bias correction over the flat parameter vector.
+__global__ void adam_kernel(float* p, float* m, float* v, const float* g, long n, float lr, float c1, float c2) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// bf16 copies W [K][N] and W^T [N][K] of a K x N layer.
+__global__ void refresh_kernel(const float* W, int K, int N, bf16* Wb, bf16* WTb) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= K * N) return;
+    const int k = idx / N, n = idx - k * N;
+    const bf16 v = (bf16)W[idx];
+    Wb[idx] = v;
+    WTb[(size_t)n * K + k] = v;
+}
+
+// Weights uniform on +-1/sqrt(fan_in) from Philox blocks (i, 0x4D4C5000, layer, 0);
+// biases and Adam state zero.
+__global__ void init_kernel(float* p, float* m, float* v, float* g, long n, uint32_t k0, uint32_t k1) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    long off = i;
+    int layer = -1;
+    float fan_in = 1.0f;
+    const long sizes[8] = {(long)MLP_IN * MLP_HID, MLP_HID, (long)MLP_HID * MLP_HID, MLP_HID,
+                           (long)MLP_HID * MLP_HID, MLP_HID, MLP_HID, 1};
+    const float fans[8] = {(float)MLP_IN, 0.f, (float)MLP_HID, 0.f, (float)MLP_HID, 0.f, (float)MLP_HID, 0.f};
+    for (int t = 0; t < 8; ++t) {
+        if (off < sizes[t]) { layer = t; fan_in = fans[t]; break; }
+        off -= sizes[t];
+    }
+    float w = 0.0f;
+    if (fan_in > 0.0f) {
+        const Block4 b = philox10((uint32_t)i, 0x4D4C5000u, (uint32_t)layer, 0u, k0, k1);
+        const float u = ((float)(b.w0 >> 8) + 0.5f) * (1.0f / 16777216.0f);
+        w = (2.0f * u - 1.0f) / sqrtf(fan_in);
+    }
+    p[i] = w;
+    m[i] = 0.0f;
+    v[i] = 0.0f;
+    g[i] = 0.0f;
+}
+
+// mu, sigma of n targets (one block, float64 accumulation).
+__global__ __launch_bounds__(256) void norm_kernel(const float* t, int n, float* norm) {
+    __shared__ double s1[256], s2[256];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) { a += t[i]; b += (double)t[i] * t[i]; }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) { s1[threadIdx.x] += s1[threadIdx.x + w]; s2[threadIdx.x] += s2[threadIdx.x + w]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mu = n ? s1[0] / n : 0.0;
+        const double var = n ? s2[0] / n - mu * mu : 1.0;
+        norm[0] = (float)mu;
+        norm[1] = (float)(var > 1e-12 ? sqrt(var) : 1.0);
+    }
+}
+
+unsigned blocks_for(long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_gemm(const MlpGemm& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gemm_bf16_kernel, dim3(blocks_for(g.N, BN), blocks_for(g.M, BM)), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t mlp_forward(const MlpNet& net, const float* dose, const int32_t* gap, const int32_t* nfrac, int B,
+                       int K, const MlpWork& w, float* pred, bool denorm, hipStream_t s) {
+    hipLaunchKernelGGL(encode_kernel, dim3(blocks_for((long)B * MLP_IN, 256)), dim3(256), 0, s, dose, gap, nfrac,
+                       B, K, w.X);
+    hipError_t e = hipGetLastError();
+    const bf16* in = w.X;
+    int kin = MLP_IN;
+    for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+        MlpGemm g{};
+        g.M = B; g.N = MLP_HID; g.K = kin;
+        g.A = in; g.sa_m = kin; g.sa_k = 1;
+        g.B = net.WT[l]; g.sb_k = 1; g.sb_n = kin;           // B(k, n) = W^T[n][k]
+        g.bias = net.b[l];
+        g.mode = MLP_FWD;
+        g.Z = w.Z[l]; g.ldz = MLP_HID;
+        g.H = w.H[l]; g.ldh = MLP_HID;
+        e = launch_gemm(g, s);
+        in = w.H[l];
+        kin = MLP_HID;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(out_fwd_kernel, dim3(blocks_for(B, 4)), dim3(256), 0, s, w.H[2], net.w4, net.b4, B, pred,
+                       denorm ? net.norm : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t mlp_backward(const MlpNet& net, int B, const float* target, const MlpWork& w, float* loss,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, s, w.y, target, net.norm, B, w.dy, loss);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(out_wgrad_kernel, dim3(blocks_for(MLP_HID + 1, 256)), dim3(256), 0, s, w.H[2], w.dy, B,
+                       net.gw4, net.gb4);
+    hipLaunchKernelGGL(out_bwd_kernel, dim3(blocks_for((long)B * MLP_HID, 256)), dim3(256), 0, s, w.dy, net.w4,
+                       w.Z[2], B, w.dZ[0]);
+    e = hipGetLastError();
+    // layer l = 2, 1, 0: dZ_l in dZ[cur]; weight and bias gradients, then dZ_{l-1}
+    int cur = 0;
+    for (int l = 2; l >= 0 && e == hipSuccess; --l) {
+        const bf16* hin = l == 0 ? w.X : w.H[l - 1];
+        const int kin = l == 0 ? MLP_IN : MLP_HID;
+        MlpGemm g{};
+        g.M = kin; g.N = MLP_HID; g.K = B;                    // dW_l = H_in^T dZ_l
+        g.A = hin; g.sa_m = 1; g.sa_k = kin;
+        g.B = w.dZ[cur]; g.sb_k = MLP_HID; g.sb_n = 1;
+        g.mode = MLP_PLAIN;
+        g.C = net.gW[l]; g.ldc = MLP_HID;
+        e = launch_gemm(g, s);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(colsum_kernel, dim3(blocks_for(MLP_HID, 256)), dim3(256), 0, s, w.dZ[cur], B, MLP_HID,
+                           net.gb[l]);
+        e = hipGetLastError();
+        if (l == 0 || e != hipSuccess) break;
+        MlpGemm d{};
+        d.M = B; d.N = MLP_HID; d.K = MLP_HID;                // dZ_{l-1} = (dZ_l W_l^T) . gelu'(Z_{l-1})
+        d.A = w.dZ[cur]; d.sa_m = MLP_HID; d.sa_k = 1;
+        d.B = net.W[l]; d.sb_k = 1; d.sb_n = MLP_HID;         // B(k, n) = W_l[n][k]
+        d.mode = MLP_BWD;
+        d.Z = w.Z[l - 1]; d.ldz = MLP_HID;
+        d.H = w.dZ[1 - cur]; d.ldh = MLP_HID;
+        e = launch_gemm(d, s);
+        cur = 1 - cur;
+    }
+    return e;
+}
+
+hipError_t mlp_adam_refresh(const MlpNet& net, int step, float lr, hipStream_t s) {
+    const long n = MLP_PARAMS;
+    const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, net.p, net.m, net.v, net.g, n, lr,
+                       c1, c2);
+    hipError_t e = hipGetLastError();
+    for (int l = 0; l < 3 && e == hipSuccess; ++l) e = mlp_refresh_layer(net, l, s);
+    return e;
+}
+
+hipError_t mlp_refresh_layer(const MlpNet& net, int l, hipStream_t s) {
+    const int K = l == 0 ? MLP_IN : MLP_HID;
+    hipLaunchKernelGGL(refresh_kernel, dim3(blocks_for((long)K * MLP_HID, 256)), dim3(256), 0, s, net.Wf[l], K,
+                       MLP_HID, net.W[l], net.WT[l]);
+    return hipGetLastError();
+}
+
+hipError_t mlp_init(const MlpNet& net, uint64_t seed, hipStream_t s) {
+    const long n = MLP_PARAMS;
+    hipLaunchKernelGGL(init_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, net.p, net.m, net.v, net.g, n,
+                       (uint32_t)seed, (uint32_t)(seed >> 32));
+    hipError_t e = hipGetLastError();
+    for (int l = 0; l < 3 && e == hipSuccess; ++l) e = mlp_refresh_layer(net, l, s);
+    return e;
+}
+
+hipError_t mlp_set_norm(const MlpNet& net, const float* t, int n, hipStream_t s) {
+    hipLaunchKernelGGL(norm_kernel, dim3(1), dim3(256), 0, s, t, n, net.norm);
+    return hipGetLastError();
+}
+
+}  // namespace gga

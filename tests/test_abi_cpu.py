@@ -28,7 +28,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(gga):
     names = declared_functions()
-    assert len(names) == 14
+    assert len(names) == 26
     for n in names:
         assert hasattr(gga.LIB, n), n
     assert set(names) == set(gga.EXPORTS)
@@ -106,3 +106,13 @@ def test_abi_argument_errors(gga):
     ab = gga.make_alphabet(0.5, [1, 2], [6], 5, 5, 2.0)   # 5 fractions of >= 0.5 Gy exceed 2 Gy
     assert gga.LIB.gga_population_random(ctypes.byref(ab), 0, 5, 0, n, n, n, n) == -6
     assert gga.LIB.gga_population_random(ctypes.byref(ab), 1, 5, 0, n, n, n, n) == -1
+
+
+def test_mlp_layout_matches_library(gga):
+    lay = gga.mlp_layout()
+    assert lay["p"] == 256 and lay["g"] > lay["v"] > lay["m"] > lay["p"]
+    assert gga.MLP_PARAMS == 591873
+    total = lay["g"] + gga._align256(4 * gga.MLP_PARAMS)
+    for k in (128, 512, 512):
+        total += 2 * gga._align256(2 * k * 512)
+    assert gga.LIB.gga_mlp_net_bytes() == total

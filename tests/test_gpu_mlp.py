@@ -1,0 +1,115 @@
+"""Surrogate MLP kernels against float64 references (needs an MI355X).
+
+Tolerances come from the arithmetic: the GEMM multiplies bf16 values exactly
+and accumulates in fp32, so its error is a few fp32 roundings of the sum of
+|products|; the network also rounds every hidden activation (and, backwards,
+every dZ) to bf16, a relative error of 2^-9 per value, so forward outputs are
+compared at 2 % of their spread and gradients per tensor at 5 % relative
+Frobenius error with cosine similarity above 0.998.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+ALPHA_DOSES = [0.5, 1.0, 1.5, 2.0, 2.5]
+GAPS = list(range(6, 61, 6))
+
+
+@pytest.fixture(scope="module")
+def gga():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2303_08123_amd as g
+    return g
+
+
+def bf16(x):
+    return torch.as_tensor(np.asarray(x, np.float32)).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+
+
+def protocols(B, K, seed):
+    rng = np.random.default_rng(seed)
+    dose = rng.choice(ALPHA_DOSES, size=(B, K)).astype(np.float32)
+    gap = rng.choice(GAPS, size=(B, K)).astype(np.int32)
+    nfrac = rng.integers(1, K + 1, size=B).astype(np.int32)
+    return dose, gap, nfrac
+
+
+@pytest.mark.parametrize("M,N,K", [(64, 64, 32), (100, 70, 45), (128, 512, 512), (513, 512, 1000)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+def test_gemm_matches_float64(gga, M, N, K, ta, tb):
+    g = torch.Generator().manual_seed(M * 7 + N + K)
+    A = torch.randn(M, K, generator=g).to(torch.bfloat16)
+    B = torch.randn(K, N, generator=g).to(torch.bfloat16)
+    Ad = (A.t().contiguous() if ta else A).cuda()
+    Bd = (B.t().contiguous() if tb else B).cuda()
+    C = gga.mlp_gemm(Ad, Bd, a_trans=ta, b_trans=tb).cpu().numpy().astype(np.float64)
+    A64, B64 = A.double().numpy(), B.double().numpy()
+    ref = A64 @ B64
+    bound = 1e-5 * (np.abs(A64) @ np.abs(B64)) + 1e-30
+    assert np.all(np.abs(C - ref) <= bound)
+
+
+def _oracle_params(gga, net):
+    p = gga.mlp_split(gga.mlp_block(net, "p").cpu().numpy().astype(np.float64))
+    for i in (0, 2, 4):                      # the MFMA layers run on bf16 weights
+        p[i] = bf16(p[i])
+    return p
+
+
+def test_forward_matches_oracle(gga):
+    net = gga.mlp_net(seed=3)
+    dose, gap, nfrac = protocols(300, 10, 1)
+    dd = [torch.from_numpy(x).cuda() for x in (dose, gap, nfrac)]
+    pred = gga.mlp_predict(net, *dd).cpu().numpy().astype(np.float64)
+    params = _oracle_params(gga, net)
+    X = bf16(omlp.encode(dose, gap, nfrac))
+    y, _ = omlp.forward(params, X)
+    spread = max(np.std(y), 1e-3)
+    assert np.max(np.abs(pred - y)) <= 0.02 * spread + 1e-6 * np.max(np.abs(y)), (np.max(np.abs(pred - y)), spread)
+
+
+def test_gradients_match_oracle(gga):
+    net = gga.mlp_net(seed=5)
+    B = 256
+    dose, gap, nfrac = protocols(B, 10, 2)
+    rng = np.random.default_rng(9)
+    target = rng.normal(0.0, 1.0, size=B).astype(np.float32)
+    dd = [torch.from_numpy(x).cuda() for x in (dose, gap, nfrac)]
+    loss = gga.mlp_grad(net, *dd, torch.from_numpy(target).cuda()).item()
+    grads = gga.mlp_split(gga.mlp_block(net, "g").cpu().numpy().astype(np.float64))
+    params = _oracle_params(gga, net)
+    X = bf16(omlp.encode(dose, gap, nfrac))
+    ref_loss, ref = omlp.loss_and_grads(params, X, target.astype(np.float64))
+    assert abs(loss - ref_loss) <= 0.02 * ref_loss
+    for i, (g, r) in enumerate(zip(grads, ref)):
+        if i == 0:                           # inputs 120..127 are always 0: their rows get no gradient
+            assert np.all(g[120:] == 0) and np.all(r[120:] == 0)
+        rel = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
+        cos = float(np.dot(g.ravel(), r.ravel()) / max(np.linalg.norm(g) * np.linalg.norm(r), 1e-30))
+        assert rel < 0.05 and cos > 0.998, (i, rel, cos)
+
+
+def test_adam_first_step_and_training(gga):
+    net = gga.mlp_net(seed=7)
+    B = 512
+    dose, gap, nfrac = protocols(B, 10, 4)
+    target = torch.from_numpy((dose.astype(np.float64) * np.linspace(1, 2, 10)).sum(1).astype(np.float32)).cuda()
+    gga.mlp_set_norm(net, target)
+    dd = [torch.from_numpy(x).cuda() for x in (dose, gap, nfrac)]
+    work = gga.mlp_work(B)
+    p0 = gga.mlp_block(net, "p").clone()
+    gga.mlp_train_step(net, *dd, target, step=1, lr=1e-3, work=work)
+    g = gga.mlp_block(net, "g").double()
+    step = (gga.mlp_block(net, "p").double() - p0.double())
+    expect = -1e-3 * g / (g.abs() + 1e-8)
+    assert torch.allclose(step, expect, rtol=1e-3, atol=1e-9)
+    losses = []
+    for s in range(2, 201):
+        losses.append(gga.mlp_train_step(net, *dd, target, step=s, lr=1e-3, work=work).item())
+    assert losses[-1] < 0.1 * losses[0], (losses[0], losses[-1])
+    pred = gga.mlp_predict(net, *dd).cpu().numpy()
+    t = target.cpu().numpy()
+    assert np.corrcoef(pred, t)[0, 1] > 0.95

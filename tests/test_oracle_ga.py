@@ -125,3 +125,28 @@ def test_elitism_keeps_best_fitness_monotone():
         dose, gap = ga.next_generation(dose, gap, f, g, 13, ALPHA, n_elite=2, k=4, p_cross=0.8, p_mut=0.05)
     assert all(b2 <= b1 + 1e-12 for b1, b2 in zip(best, best[1:]))
     assert best[-1] < best[0]
+
+
+def test_random_screen_generation_invariants(params):
+    """The screened generation keeps N rows sorted by fitness, each row either
+    an old member with its old fitness or one of the S candidates picked by
+    the smallest random keys."""
+    from oracle import sga
+    rng = np.random.default_rng(5)
+    N, K, C, S = 6, 4, 12, 3
+    alphabet = dict(dose_quantum=0.5, dose_q=[1, 2, 3, 4], gaps=[6, 12, 24], kmin=K, kmax=K, cap=8.0)
+    dose = rng.choice([0.5, 1.0, 1.5], size=(N, K)).astype(np.float32)
+    gap = rng.choice([6, 12, 24], size=(N, K)).astype(np.int32)
+    fit = sga.simulate_fitness(params, 16, 12, 2, 1, 3, dose, gap)
+    d, g, f = sga.generation_random_screen(params, 16, 12, 2, 1, 3, dose, gap, fit, 0, 9, alphabet,
+                                           2, 0.8, 0.2, C, S)
+    assert d.shape == (N, K) and np.all(np.diff(f) >= 0)
+    cd, cg = ga.next_generation(dose, gap, fit, 0, 9, alphabet, 0, 2, 0.8, 0.2, n_out=C)
+    keys = sga.random_keys(C, 0, 9)
+    assert len(np.unique(keys)) == C and np.all(keys < 2 ** 24)
+    picked = np.argsort(keys, kind="stable")[:S]
+    new_f = sga.simulate_fitness(params, 16, 12, 2, 1, 3 + sga.W64, cd[picked], cg[picked])
+    pool = [(dose[i], gap[i], fit[i]) for i in range(N)] + [(cd[j], cg[j], new_f[n]) for n, j in enumerate(picked)]
+    expect = sorted(range(N + S), key=lambda i: (pool[i][2], i))[:N]
+    for row, i in enumerate(expect):
+        assert np.array_equal(d[row], pool[i][0]) and np.array_equal(g[row], pool[i][1]) and f[row] == pool[i][2]

@@ -121,14 +121,147 @@ def ga_bench(gga, workloads, md, args):
     }
 
 
+def _reevaluate(gga, params, wl, best_dose, best_gap, R, seed):
+    """Fitness of archived protocols re-simulated with R fresh replicas."""
+    import torch
+    P, K = best_dose.shape
+    cfg = gga.make_cfg(wl["L"], wl["horizon"], R, seed=seed, substeps=wl["substeps"], dose_cap=wl["dose_cap"])
+    nfrac = torch.full((P,), K, dtype=torch.int32, device=best_dose.device)
+    _, fit, _ = gga.simulate(params, cfg, best_dose.contiguous(), best_gap.contiguous(), nfrac)
+    return fit.cpu().numpy().astype(np.float64)
+
+
+def surrogate_bench(gga, workloads, md, args):
+    """Surrogate-screened GA against the GA without it, on the batched
+    workload's simulator and alphabets, both with the GA settings of the GA
+    workload (population 2048 x 4 replicas, k = 4, crossover 0.8, mutation
+    0.05).  The surrogate is trained on 200k simulated random protocols; each
+    screened generation breeds 5000 candidates (10^6 over 200 generations) and
+    fully simulates the best-predicted 1 %.  Each run's best protocol of every
+    generation is re-simulated with 64 fresh replicas; the target is the GA's
+    final best (re-simulated) within 1 %."""
+    import torch
+    wl = workloads.CONFIG2
+    N, K, R, G = 2048, 10, wl["R"], args.generations
+    C, S = args.candidates, max(1, args.candidates // 100)
+    alpha = gga.make_alphabet(0.5, [1, 2, 3, 4, 5], list(range(6, 61, 6)), K, K, wl["dose_cap"])
+    params = gga.make_params(md)
+    cfg = gga.make_cfg(wl["L"], wl["horizon"], R, seed=wl["seed"], substeps=wl["substeps"], dose_cap=wl["dose_cap"])
+    # 1. training pairs and training
+    t0 = time.perf_counter()
+    n_train = args.train_pairs
+    td, tg, tn = gga.population_random(alpha, n_train, K, seed=100)
+    _, tf, _ = gga.simulate(params, gga.make_cfg(wl["L"], wl["horizon"], 1, seed=1000, substeps=wl["substeps"],
+                                                 dose_cap=wl["dose_cap"]), td, tg, tn)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    log(f"surrogate: {n_train} training pairs simulated in {t_data:.1f} s")
+    net = gga.mlp_net(seed=3)
+    gga.mlp_set_norm(net, tf)
+    B = 1024
+    work = gga.mlp_work(B)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    t0 = time.perf_counter()
+    step = 0
+    for epoch in range(args.epochs):
+        perm = torch.randperm(n_train, generator=gen, device="cuda")
+        lr = 1e-3 if epoch < args.epochs - 2 else 2e-4
+        acc = torch.zeros((), dtype=torch.float64, device="cuda")
+        for b in range(0, n_train - B + 1, B):
+            idx = perm[b:b + B]
+            step += 1
+            gga.mlp_train_step(net, td[idx], tg[idx], tn[idx], tf[idx], step, lr, work=work, loss=loss)
+            acc += loss[0]
+        log(f"surrogate: epoch {epoch + 1}/{args.epochs} mean loss {acc.item() / (n_train // B):.4f}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    vd, vg, vn = gga.population_random(alpha, 4096, K, seed=200)
+    _, vf, _ = gga.simulate(params, gga.make_cfg(wl["L"], wl["horizon"], R, seed=2000, substeps=wl["substeps"],
+                                                 dose_cap=wl["dose_cap"]), vd, vg, vn)
+    pred = gga.mlp_predict(net, vd, vg, vn).cpu().numpy().astype(np.float64)
+    vf = vf.cpu().numpy().astype(np.float64)
+    held_out = {"protocols": 4096, "replicas": R, "corr": float(np.corrcoef(pred, vf)[0, 1]),
+                "rmse": float(np.sqrt(np.mean((pred - vf) ** 2))), "fitness_sd": float(vf.std())}
+    log(f"surrogate: trained in {t_train:.1f} s, held-out {held_out}")
+    dose0, gap0, _ = gga.population_random(alpha, N, K, seed=0)
+    ga_cfg = gga.make_ga(n_elite=N // 10, tournament_k=4, p_cross=0.8, p_mut=0.05, seed=1)
+    torch.cuda.synchronize()
+    # 2. the GA without the surrogate (replayed hipGraph generations)
+    d, g, hist, arc, times, t_off = dose0, gap0, None, True, [], 0.0
+    for g0 in range(0, G, args.chunk):
+        n = min(args.chunk, G - g0)
+        t0 = time.perf_counter()
+        d, g, hist, gen_ms, arc = gga.ga_run(params, cfg, ga_cfg, alpha, d, g, n, True, g0=g0, hist=hist, archive=arc)
+        wall = time.perf_counter() - t0
+        times.extend(t_off + gen_ms.astype(np.float64) / 1000.0)
+        t_off += wall
+        log(f"ga: generations {g0}..{g0 + n - 1} in {wall:.1f} s")
+    ga_t, ga_arc, ga_total = np.array(times), arc, t_off
+    # 3. the surrogate-screened GA
+    sga_cfg = gga.make_ga(n_elite=0, tournament_k=4, p_cross=0.8, p_mut=0.05, seed=1)
+    run = gga.SurrogateGA(params, cfg, sga_cfg, alpha, gga.make_sga(C, S, screen=True), net, dose0, gap0,
+                          archive=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.init()
+    torch.cuda.synchronize()
+    t_off = time.perf_counter() - t0
+    times = []
+    for g0 in range(0, G, args.chunk):
+        n = min(args.chunk, G - g0)
+        t0 = time.perf_counter()
+        gen_ms = run.run(n, use_graph=True)
+        wall = time.perf_counter() - t0
+        times.extend(t_off + gen_ms.astype(np.float64) / 1000.0)
+        t_off += wall
+        log(f"sga: generations {g0}..{g0 + n - 1} in {wall:.1f} s")
+    sga_t, sga_total = np.array(times), t_off
+    # 4. judge both with fresh replicas
+    RE = 64
+    ga_re = _reevaluate(gga, params, wl, ga_arc[0], ga_arc[1], RE, seed=777)
+    sga_re = _reevaluate(gga, params, wl, run.archive[0], run.archive[1], RE, seed=778)
+    ga_best_so_far = np.array([ga_re[int(np.argmin(hist.cpu().numpy()[:i + 1, 0]))] for i in range(G)])
+    target = float(ga_best_so_far[-1]) * 1.01
+    def first_hit(curve, t):
+        hit = np.nonzero(curve <= target)[0]
+        return (float(t[hit[0]]), int(hit[0])) if len(hit) else (None, None)
+    ga_ttb, ga_gen = first_hit(ga_best_so_far, ga_t)
+    sga_ttb, sga_gen = first_hit(sga_re, sga_t)
+    arc_pred = gga.mlp_predict(net, run.archive[0].contiguous(), run.archive[1].contiguous(),
+                               torch.full((G,), K, dtype=torch.int32, device="cuda")).cpu().numpy()
+    return {
+        "metric": "time to reach the GA's best fitness (within 1 %), surrogate-screened GA",
+        "value": sga_ttb, "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
+        "dtype": "bf16 surrogate (f32 accumulate), f32 simulation", "data": "synthetic",
+        "config": {"workload": "sga-2048x4-128x128-20d", "population": N, "replicas": R, "generations": G,
+                   "candidates_per_generation": C, "simulated_per_generation": S, "screened_total": C * G,
+                   "training_pairs": n_train, "training_replicas": 1, "epochs": args.epochs, "batch": B,
+                   "reevaluation_replicas": RE},
+        "target_fitness": target,
+        "ga": {"time_to_target_s": ga_ttb, "generation": ga_gen, "total_s": ga_total,
+               "final_best_reevaluated": float(ga_best_so_far[-1]), "simulations": N * G},
+        "sga": {"time_to_target_s": sga_ttb, "generation": sga_gen, "total_s": sga_total,
+                "final_best_reevaluated": float(sga_re[-1]), "best_reevaluated": float(sga_re.min()),
+                "simulations": N + S * G,
+                "time_to_target_incl_training_s": None if sga_ttb is None else sga_ttb + t_data + t_train,
+                "surrogate_error_on_archive": float(np.mean(np.abs(arc_pred - sga_re)))},
+        "surrogate": {"data_s": t_data, "train_s": t_train, "held_out": held_out},
+        "speedup_time_to_target": None if (sga_ttb is None or ga_ttb is None) else ga_ttb / max(sga_ttb, 1e-9),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "ga"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "ga", "surrogate"])
     ap.add_argument("--generations", type=int, default=200, help="GA workload: generations")
     ap.add_argument("--chunk", type=int, default=20, help="GA workload: generations per progress line")
+    ap.add_argument("--candidates", type=int, default=5000, help="surrogate workload: candidates per generation")
+    ap.add_argument("--train-pairs", type=int, default=200000, help="surrogate workload: training pairs")
+    ap.add_argument("--epochs", type=int, default=10, help="surrogate workload: training epochs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy, to scale HBM counters")
@@ -155,6 +288,9 @@ def main():
     md = gga.load_model()
     if args.workload == "ga":
         print(json.dumps(ga_bench(gga, workloads, md, args)), flush=True)
+        return
+    if args.workload == "surrogate":
+        print(json.dumps(surrogate_bench(gga, workloads, md, args)), flush=True)
         return
     if args.workload == "batched":
         wl = dict(workloads.CONFIG2)

@@ -246,7 +246,9 @@ int gga_ga_generation(const gga_params* params, const gga_sim_cfg* cfg, const gg
  * no host wait in between.  gen_ms_h[g] (HOST, or NULL) receives the time from
  * the start of the run to the end of generation g0 + g, from HIP events on
  * `stream`.  hist_d[g0 + n_gen][2] receives (best, mean) fitness at row g for
- * generation g.
+ * generation g.  Optional archive (both NULL, or both device arrays of
+ * [g0 + n_gen][K]): best_dose_d / best_gap_d row g receive the genes of the
+ * protocol with the best fitness of generation g.
  * Synchronous: returns after the stream has finished.  Creates and destroys
  * HIP graphs and events (host-side objects); allocates no device memory.
  * Errors: as gga_ga_generation.
@@ -255,7 +257,7 @@ int gga_ga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cf
                const gga_alphabet* a, float* dose_a_d, int32_t* gap_a_d, float* dose_b_d,
                int32_t* gap_b_d, const int32_t* nfrac_d, int32_t N, int32_t K, int32_t g0,
                int32_t n_gen, int32_t use_graph, void* ws_d, size_t ws_bytes, float* hist_d,
-               float* gen_ms_h, hipStream_t stream);
+               float* best_dose_d, int32_t* best_gap_d, float* gen_ms_h, hipStream_t stream);
 
 /*
  * Surrogate of the simulation for pre-screening GA offspring (not part of the
@@ -353,15 +355,17 @@ int gga_sga_generation(const gga_params* params, const gga_sim_cfg* cfg, const g
 
 /*
  * Generations g0 .. g0+n_gen-1 of gga_sga_generation, host-driven
- * (use_graph = 0) or as a captured hipGraph replayed (use_graph = 1); timing
- * and history as gga_ga_run.  Synchronous; creates and destroys HIP graphs
- * and events; allocates no device memory.  Errors: as gga_sga_generation.
+ * (use_graph = 0) or as a captured hipGraph replayed (use_graph = 1); timing,
+ * history and the optional best-protocol archive as gga_ga_run (the archived
+ * protocol of generation g is row 0 of the kept population).  Synchronous;
+ * creates and destroys HIP graphs and events; allocates no device memory.
+ * Errors: as gga_sga_generation.
  */
 int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga,
                 const gga_alphabet* a, const gga_sga_cfg* sga, const void* net_d, float* pop_dose_d,
                 int32_t* pop_gap_d, float* pop_fit_d, int32_t N, int32_t K, int32_t g0, int32_t n_gen,
-                int32_t use_graph, void* ws_d, size_t ws_bytes, float* hist_d, float* gen_ms_h,
-                hipStream_t stream);
+                int32_t use_graph, void* ws_d, size_t ws_bytes, float* hist_d, float* best_dose_d,
+                int32_t* best_gap_d, float* gen_ms_h, hipStream_t stream);
 
 /*
  * Philox4x32-10 blocks (Salmon et al., SC'11) from the device implementation

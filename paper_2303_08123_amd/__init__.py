@@ -91,7 +91,7 @@ def _load():
         "gga_ga_generation": ([vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, ctypes.c_size_t, vp, i32,
                                i32, vp], ctypes.c_int),
         "gga_ga_run": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, ctypes.c_size_t, vp,
-                        vp, vp], ctypes.c_int),
+                        vp, vp, vp, vp], ctypes.c_int),
         "gga_mlp_net_bytes": ([], ctypes.c_size_t),
         "gga_mlp_work_bytes": ([i32], ctypes.c_size_t),
         "gga_mlp_init": ([vp, u64, vp], ctypes.c_int),
@@ -106,7 +106,7 @@ def _load():
         "gga_sga_generation": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, i32, vp],
                                ctypes.c_int),
         "gga_sga_run": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, ctypes.c_size_t, vp, vp,
-                         vp], ctypes.c_int),
+                         vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -331,10 +331,23 @@ def ga_generation(params, cfg, ga, alphabet, dose, gap, nfrac, ws, hist=None, ad
     return nd, ng
 
 
-def ga_run(params, cfg, ga, alphabet, dose, gap, n_gen, use_graph, g0=0, hist=None):
+def _archive(archive, rows, K, device):
+    """Best-protocol archive (dose [rows][K], gap [rows][K]) grown to rows,
+    keeping what an earlier archive held."""
+    d = torch.zeros((rows, K), dtype=torch.float32, device=device)
+    g = torch.zeros((rows, K), dtype=torch.int32, device=device)
+    if archive is not None:
+        n = min(rows, archive[0].shape[0])
+        d[:n], g[:n] = archive[0][:n], archive[1][:n]
+    return d, g
+
+
+def ga_run(params, cfg, ga, alphabet, dose, gap, n_gen, use_graph, g0=0, hist=None, archive=None):
     """Run generations g0 .. g0+n_gen-1 from (dose, gap) (not modified).
     Returns (final dose, final gap, hist[g0+n_gen, 2] (best, mean), gen_ms[n_gen]).
-    Pass the previous hist to keep filling it when continuing a run."""
+    Pass the previous hist to keep filling it when continuing a run.  With
+    archive=True (or a previous archive), the best protocol of every
+    generation is kept too and a fifth value (best_dose, best_gap) returned."""
     N, K = dose.shape
     nfrac = torch.full((N,), K, dtype=torch.int32, device=dose.device)
     da, ga_ = dose.clone(), gap.clone()
@@ -345,6 +358,7 @@ def ga_run(params, cfg, ga, alphabet, dose, gap, n_gen, use_graph, g0=0, hist=No
     if hist is not None:
         h[:min(rows, hist.shape[0])] = hist[:rows]
     gen_ms = np.zeros(max(n_gen, 1), dtype=np.float32)
+    arc = _archive(None if archive is True else archive, rows, K, dose.device) if archive is not None else None
     # a captured stream must not be the legacy default stream
     side = torch.cuda.Stream(device=dose.device)
     side.wait_stream(torch.cuda.current_stream())
@@ -352,9 +366,12 @@ def ga_run(params, cfg, ga, alphabet, dose, gap, n_gen, use_graph, g0=0, hist=No
         _check(LIB.gga_ga_run(ctypes.byref(_as_params(params)), ctypes.byref(cfg), ctypes.byref(ga),
                               ctypes.byref(alphabet), _ptr(da), _ptr(ga_), _ptr(db), _ptr(gb), _ptr(nfrac), N, K,
                               int(g0), int(n_gen), int(bool(use_graph)), _ptr(ws), ws.numel(), _ptr(h),
+                              _ptr(arc[0]) if arc else None, _ptr(arc[1]) if arc else None,
                               gen_ms.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(side.cuda_stream)))
     torch.cuda.current_stream().wait_stream(side)
     final = (da, ga_) if n_gen % 2 == 0 else (db, gb)
+    if arc is not None:
+        return final[0], final[1], h[:g0 + n_gen], gen_ms[:n_gen], (arc[0][:g0 + n_gen], arc[1][:g0 + n_gen])
     return final[0], final[1], h[:g0 + n_gen], gen_ms[:n_gen]
 
 
@@ -465,9 +482,11 @@ class SurrogateGA:
     """Population (N + S rows) and workspace of a surrogate-screened GA run.
 
     init() simulates the initial population; run() advances generations (in
-    chunks if wanted: continuing with g0 reproduces one longer run)."""
+    chunks if wanted: continuing with g0 reproduces one longer run).  With
+    archive=True the best protocol of every generation is kept in
+    self.archive = (best_dose, best_gap)."""
 
-    def __init__(self, params, cfg, ga, alphabet, sga, net, dose, gap):
+    def __init__(self, params, cfg, ga, alphabet, sga, net, dose, gap, archive=False):
         self.params, self.cfg, self.ga, self.alphabet, self.sga, self.net = _as_params(params), cfg, ga, alphabet, sga, net
         N, K = dose.shape
         S = sga.n_simulated
@@ -481,6 +500,8 @@ class SurrogateGA:
         self.ws = torch.empty(int(LIB.gga_sga_workspace_bytes(N, K, cfg.R, sga.n_candidates, S)),
                               dtype=torch.uint8, device=dev)
         self.hist = None
+        self.keep_archive = bool(archive)
+        self.archive = None
         self.g = 0
         self.stream = torch.cuda.Stream(device=dev)     # capturable (not the legacy default stream)
 
@@ -498,14 +519,18 @@ class SurrogateGA:
         if self.hist is not None:
             h[:self.hist.shape[0]] = self.hist
         gen_ms = np.zeros(max(n_gen, 1), dtype=np.float32)
+        arc = _archive(self.archive, max(rows, 1), self.K, self.dose.device) if self.keep_archive else None
         self.stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(self.stream):
             _check(LIB.gga_sga_run(ctypes.byref(self.params), ctypes.byref(self.cfg), ctypes.byref(self.ga),
                                    ctypes.byref(self.alphabet), ctypes.byref(self.sga), _ptr(self.net),
                                    _ptr(self.dose), _ptr(self.gap), _ptr(self.fit), self.N, self.K, self.g, n_gen,
                                    int(bool(use_graph)), _ptr(self.ws), self.ws.numel(), _ptr(h),
+                                   _ptr(arc[0]) if arc else None, _ptr(arc[1]) if arc else None,
                                    gen_ms.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(self.stream.cuda_stream)))
         torch.cuda.current_stream().wait_stream(self.stream)
         self.hist = h[:rows]
+        if arc is not None:
+            self.archive = (arc[0][:rows], arc[1][:rows])
         self.g = rows
         return gen_ms[:n_gen]

@@ -46,9 +46,11 @@ __global__ __launch_bounds__(256) void rank_kernel(const float* fitness, int N, 
     }
 }
 
-// hist[g] = (best fitness, mean fitness over finite entries) of this generation.
+// hist[g] = (best fitness, mean fitness over finite entries) of this generation;
+// with an archive, its row g receives the best protocol's genes.
 __global__ __launch_bounds__(256) void history_kernel(const float* fitness, int N, const int32_t* order,
-                                                      const int32_t* generation, float* hist, int hist_cap) {
+                                                      const int32_t* generation, float* hist, int hist_cap,
+                                                      Archive arc) {
     __shared__ double s_sum[256];
     __shared__ int s_cnt[256];
     double sum = 0.0;
@@ -67,12 +69,16 @@ __global__ __launch_bounds__(256) void history_kernel(const float* fitness, int 
         }
         __syncthreads();
     }
+    const int g = *generation;
+    if (g < 0 || g >= hist_cap) return;
+    const int best = order ? order[0] : 0;
     if (threadIdx.x == 0) {
-        const int g = *generation;
-        if (g >= 0 && g < hist_cap) {
-            hist[2 * g] = fitness[order ? order[0] : 0];
-            hist[2 * g + 1] = s_cnt[0] ? (float)(s_sum[0] / s_cnt[0]) : __builtin_nanf("");
-        }
+        hist[2 * g] = fitness[best];
+        hist[2 * g + 1] = s_cnt[0] ? (float)(s_sum[0] / s_cnt[0]) : __builtin_nanf("");
+    }
+    if (arc.best_dose && (int)threadIdx.x < arc.K) {
+        arc.best_dose[(size_t)g * arc.K + threadIdx.x] = arc.dose[(size_t)best * arc.K + threadIdx.x];
+        arc.best_gap[(size_t)g * arc.K + threadIdx.x] = arc.gap[(size_t)best * arc.K + threadIdx.x];
     }
 }
 
@@ -208,9 +214,10 @@ hipError_t launch_rank(const float* fitness, int N, int32_t* order, int32_t* pos
 }
 
 hipError_t launch_history(const float* fitness, int N, const int32_t* order, const int32_t* generation,
-                          float* hist, int hist_cap, hipStream_t s) {
+                          float* hist, int hist_cap, const Archive& arc, hipStream_t s) {
     if (N <= 0 || !hist) return hipSuccess;
-    hipLaunchKernelGGL(history_kernel, dim3(1), dim3(256), 0, s, fitness, N, order, generation, hist, hist_cap);
+    if (arc.best_dose && (arc.K > 256 || !arc.best_gap || !arc.dose || !arc.gap)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(history_kernel, dim3(1), dim3(256), 0, s, fitness, N, order, generation, hist, hist_cap, arc);
     return hipGetLastError();
 }
 

@@ -312,7 +312,8 @@ int check_ga(const gga_ga_cfg* ga, const gga_alphabet* a, int32_t N, int32_t K, 
 hipError_t enqueue_generation(const gga_params* params, const gga_sim_cfg* cfg, gga::GaArgs ga_args,
                               const float* dose, const int32_t* gap, const int32_t* nfrac, int32_t N,
                               int32_t K, float* next_dose, int32_t* next_gap, const GaWorkspace& w,
-                              float* hist, int32_t hist_cap, int32_t advance, hipStream_t stream) {
+                              float* hist, int32_t hist_cap, float* best_dose, int32_t* best_gap, int32_t advance,
+                              hipStream_t stream) {
     gga::SimArgs sa = make_args(params, cfg, dose, gap, nfrac, K);
     sa.n0 = 0;
     sa.nsteps = cfg->horizon;
@@ -323,7 +324,8 @@ hipError_t enqueue_generation(const gga_params* params, const gga_sim_cfg* cfg, 
     hipError_t e = gga::launch_simulation(sa, cfg->L, N * cfg->R, stream);
     if (e == hipSuccess) e = gga::launch_fitness(w.live, N, cfg->R, w.fitness, stream);
     if (e == hipSuccess) e = gga::launch_rank(w.fitness, N, w.order, w.position, stream);
-    if (e == hipSuccess) e = gga::launch_history(w.fitness, N, w.order, w.generation, hist, hist_cap, stream);
+    const gga::Archive arc{dose, gap, K, best_dose, best_gap};
+    if (e == hipSuccess) e = gga::launch_history(w.fitness, N, w.order, w.generation, hist, hist_cap, arc, stream);
     ga_args.dose = dose;
     ga_args.gap = gap;
     ga_args.order = w.order;
@@ -426,19 +428,21 @@ int gga_ga_generation(const gga_params* params, const gga_sim_cfg* cfg, const gg
     if (!dose_d || !gap_h_d || !nfrac_d || !next_dose_d || !next_gap_h_d || !ws_d) return GGA_E_ARG;
     if (ws_bytes < ga_ws_bytes(N, cfg->R) || hist_cap < 0 || (hist_cap > 0 && !hist_d)) return GGA_E_ARG;
     const hipError_t e = enqueue_generation(params, cfg, ga_args, dose_d, gap_h_d, nfrac_d, N, K, next_dose_d,
-                                            next_gap_h_d, ga_ws(ws_d, N, cfg->R), hist_d, hist_cap, advance,
-                                            stream);
+                                            next_gap_h_d, ga_ws(ws_d, N, cfg->R), hist_d, hist_cap, nullptr,
+                                            nullptr, advance, stream);
     return e == hipSuccess ? GGA_OK : hip_fail(e);
 }
 
 int gga_ga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga, const gga_alphabet* a,
                float* dose_a_d, int32_t* gap_a_d, float* dose_b_d, int32_t* gap_b_d, const int32_t* nfrac_d,
                int32_t N, int32_t K, int32_t g0, int32_t n_gen, int32_t use_graph, void* ws_d,
-               size_t ws_bytes, float* hist_d, float* gen_ms_h, hipStream_t stream) {
+               size_t ws_bytes, float* hist_d, float* best_dose_d, int32_t* best_gap_d, float* gen_ms_h,
+               hipStream_t stream) {
     int rc = check_params(params);
     if (rc) return rc;
     if ((rc = check_cfg(cfg))) return rc;
     if ((rc = check_batch(N, K, cfg->R))) return rc;
+    if (!best_dose_d != !best_gap_d) return GGA_E_ARG;
     gga::GaArgs ga_args;
     if ((rc = check_ga(ga, a, N, K, &ga_args))) return rc;
     if (!dose_a_d || !gap_a_d || !dose_b_d || !gap_b_d || !nfrac_d || !ws_d || n_gen < 0 || g0 < 0) return GGA_E_ARG;
@@ -450,7 +454,7 @@ int gga_ga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cf
     int32_t* pg[2] = {gap_a_d, gap_b_d};
     auto enqueue = [&](int d) {
         return enqueue_generation(params, cfg, ga_args, pd[d], pg[d], nfrac_d, N, K, pd[1 - d], pg[1 - d], w,
-                                  hist_d, hist_cap, 1, stream);
+                                  hist_d, hist_cap, best_dose_d, best_gap_d, 1, stream);
     };
     const hipError_t e = run_generations(enqueue, w.generation, g0, n_gen, use_graph, gen_ms_h, stream);
     return e == hipSuccess ? GGA_OK : hip_fail(e);
@@ -709,7 +713,8 @@ hipError_t sim_rows(const gga_params* params, const gga_sim_cfg* cfg, const floa
 
 hipError_t enqueue_sga(const gga_params* params, const gga_sim_cfg* cfg, gga::GaArgs ga_args, const gga_sga_cfg* sga,
                        const void* net, float* pop_dose, int32_t* pop_gap, float* pop_fit, const SgaDims& d,
-                       const SgaWorkspace& w, float* hist, int32_t hist_cap, hipStream_t stream) {
+                       const SgaWorkspace& w, float* hist, int32_t hist_cap, float* best_dose, int32_t* best_gap,
+                       hipStream_t stream) {
     const int N = d.N, K = d.K, C = d.C, S = d.S;
     // breed C candidates from the ranked population
     hipError_t e = gga::launch_rank(pop_fit, N, w.order_p, w.pos_p, stream);
@@ -745,7 +750,8 @@ hipError_t enqueue_sga(const gga_params* params, const gga_sim_cfg* cfg, gga::Ga
         e = gga::launch_gather(pop_dose, pop_gap, pop_fit, w.order_p, N, K, w.tmp_dose, w.tmp_gap, w.tmp_fit, stream);
     if (e == hipSuccess)
         e = gga::launch_gather(w.tmp_dose, w.tmp_gap, w.tmp_fit, nullptr, N, K, pop_dose, pop_gap, pop_fit, stream);
-    if (e == hipSuccess) e = gga::launch_history(pop_fit, N, nullptr, w.generation, hist, hist_cap, stream);
+    const gga::Archive arc{pop_dose, pop_gap, K, best_dose, best_gap};
+    if (e == hipSuccess) e = gga::launch_history(pop_fit, N, nullptr, w.generation, hist, hist_cap, arc, stream);
     if (e == hipSuccess) e = gga::launch_counter(w.generation, 1, 1, stream);
     return e;
 }
@@ -793,17 +799,18 @@ int gga_sga_generation(const gga_params* params, const gga_sim_cfg* cfg, const g
     SgaWorkspace w;
     sga_layout(d, &w, ws_d);
     const hipError_t e = enqueue_sga(params, cfg, ga_args, sga, net_d, pop_dose_d, pop_gap_d, pop_fit_d, d, w, hist_d,
-                                     hist_cap, stream);
+                                     hist_cap, nullptr, nullptr, stream);
     return e == hipSuccess ? GGA_OK : hip_fail(e);
 }
 
 int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga, const gga_alphabet* a,
                 const gga_sga_cfg* sga, const void* net_d, float* pop_dose_d, int32_t* pop_gap_d, float* pop_fit_d,
                 int32_t N, int32_t K, int32_t g0, int32_t n_gen, int32_t use_graph, void* ws_d, size_t ws_bytes,
-                float* hist_d, float* gen_ms_h, hipStream_t stream) {
+                float* hist_d, float* best_dose_d, int32_t* best_gap_d, float* gen_ms_h, hipStream_t stream) {
     int rc = check_params(params);
     if (rc) return rc;
     if ((rc = check_cfg(cfg))) return rc;
+    if (!best_dose_d != !best_gap_d) return GGA_E_ARG;
     SgaDims d;
     if ((rc = check_sga(sga, N, K, cfg->R, &d))) return rc;
     gga::GaArgs ga_args;
@@ -817,7 +824,7 @@ int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_c
     const int32_t hist_cap = g0 + n_gen;
     auto enqueue = [&](int) {
         return enqueue_sga(params, cfg, ga_args, sga, net_d, pop_dose_d, pop_gap_d, pop_fit_d, d, w, hist_d, hist_cap,
-                           stream);
+                           best_dose_d, best_gap_d, stream);
     };
     const hipError_t e = run_generations(enqueue, w.generation, g0, n_gen, use_graph, gen_ms_h, stream);
     return e == hipSuccess ? GGA_OK : hip_fail(e);

@@ -63,8 +63,17 @@ struct GaArgs {
     int32_t* next_gap;
 };
 hipError_t launch_rank(const float* fitness, int N, int32_t* order, int32_t* position, hipStream_t s);
+// Per-generation record of the best protocol: best_dose/best_gap row g = genes
+// of the best row of dose/gap (K per row); inactive when best_dose is null.
+struct Archive {
+    const float* dose;
+    const int32_t* gap;
+    int K;
+    float* best_dose;
+    int32_t* best_gap;
+};
 hipError_t launch_history(const float* fitness, int N, const int32_t* order, const int32_t* generation,
-                          float* hist, int hist_cap, hipStream_t s);
+                          float* hist, int hist_cap, const Archive& arc, hipStream_t s);
 hipError_t launch_offspring(const GaArgs& a, hipStream_t s);
 hipError_t launch_counter(int32_t* generation, int32_t value, int32_t add, hipStream_t s);
 // *dst = *src + add

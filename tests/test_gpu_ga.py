@@ -108,5 +108,11 @@ def test_graph_replays_equal_host_driven_loop(gga, model_dict):
     h2 = results[True][5]
     assert h2.shape == (9, 2) and np.all(np.isfinite(h2)) and np.all(h2[:, 0] <= h2[:, 1])
     # one run of 9 generations equals the 5 + 4 continuation
-    d9, g9, h9, _ = gga.ga_run(model_dict, cfg, ga_cfg, a, d0, g0, 9, True)
+    d9, g9, h9, _, (bd, bg) = gga.ga_run(model_dict, cfg, ga_cfg, a, d0, g0, 9, True, archive=True)
     assert np.array_equal(d9.cpu().numpy(), results[True][3]) and np.array_equal(h9.cpu().numpy(), h2)
+    # the archive's last row is the best of generation 8, which elitism copies to row 0 of the bred population
+    assert bd.shape == (9, K) and np.array_equal(bd[8].cpu().numpy(), d9[0].cpu().numpy())
+    assert np.array_equal(bg[8].cpu().numpy(), g9[0].cpu().numpy())
+    # and the first rows match the host-driven run's archive
+    _, _, _, _, (pd, pg) = gga.ga_run(model_dict, cfg, ga_cfg, a, d0, g0, 5, False, archive=True)
+    assert np.array_equal(pd.cpu().numpy(), bd[:5].cpu().numpy()) and np.array_equal(pg.cpu().numpy(), bg[:5].cpu().numpy())

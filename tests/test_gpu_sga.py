@@ -61,12 +61,13 @@ def test_graph_equals_host_driven(gga, model_dict):
     out = []
     for use_graph in (False, True):
         s = gga.SurrogateGA(model_dict, cfg, ga_cfg, _alphabet(gga), gga.make_sga(C, S, screen=True), net,
-                            torch.from_numpy(dose).cuda(), torch.from_numpy(gap).cuda())
+                            torch.from_numpy(dose).cuda(), torch.from_numpy(gap).cuda(), archive=True)
         s.init()
         s.run(3, use_graph)
         torch.cuda.synchronize()
         s.run(2, use_graph)
-        out.append([x.cpu().numpy() for x in (s.dose[:N], s.gap[:N], s.fit[:N], s.hist)])
+        out.append([x.cpu().numpy() for x in (s.dose[:N], s.gap[:N], s.fit[:N], s.hist, *s.archive)])
+        assert np.array_equal(out[-1][4][-1], out[-1][0][0]) and np.array_equal(out[-1][5][-1], out[-1][1][0])
     for a, b in zip(*out):
         assert np.array_equal(a, b, equal_nan=True)
     f = out[1][2]

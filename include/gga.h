@@ -80,7 +80,7 @@ typedef struct gga_params {
 /* One simulation batch.  Set struct_size = sizeof(gga_sim_cfg). */
 typedef struct gga_sim_cfg {
     uint32_t struct_size;
-    int32_t L;              /* lattice side; 64 and 128 are supported            */
+    int32_t L;              /* lattice side: 64 or 128 (uneven batches: 256 too)  */
     int32_t horizon;        /* steps (model hours) simulated by gga_simulate     */
     int32_t substeps;       /* diffusion sub-steps per step, 1 .. 64             */
     int32_t R;              /* replicas per protocol, >= 1                       */
@@ -375,6 +375,92 @@ int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_c
  */
 int gga_philox_fill(const uint32_t* ctr_d, uint64_t seed, uint32_t* out_d, int64_t n,
                     hipStream_t stream);
+
+/*
+ * Kernel variants and uneven batches.  The paper simulates many instances
+ * within and across GPUs (Materials and Methods, "GPU implementation"); a
+ * batch here may mix lattice sides, fraction counts and horizons.
+ *
+ * Variants of the simulation kernel, numbered 0 .. gga_variant_count()-1, each
+ * for one lattice side.  Resident variants keep an instance's whole state on
+ * one compute unit for its whole horizon; slab variants (the only form for
+ * L = 256, whose state exceeds a compute unit) advance slabs of rows of a
+ * lattice one step per launch between two state buffers in device memory,
+ * each slab recomputing `substeps + 2` halo rows at its inner edges.  Every
+ * variant gives bit-identical results.  gga_simulate and gga_state_run use the
+ * chosen resident variant of L; gga_simulate_uneven the chosen variant of any
+ * form.  Choices are process-wide; gga_autotune sets them by timing.
+ */
+int gga_variant_count(void);
+int32_t gga_variant_side(int32_t v);      /* lattice side of variant v, -1 if none    */
+int32_t gga_variant_is_slab(int32_t v);   /* 1 slab form, 0 resident, -1 no variant   */
+const char* gga_variant_name(int32_t v);  /* static string                           */
+/* Chosen variant for side L (resident_only != 0: the one gga_simulate uses).
+ * Returns the variant, or GGA_E_UNSUPPORTED. */
+int gga_get_variant(int32_t L, int32_t resident_only);
+/* Choose variant v for its side (a resident v also becomes the resident
+ * choice).  Returns GGA_OK or GGA_E_ARG. */
+int gga_set_variant(int32_t L, int32_t v);
+
+/*
+ * Device workspace of gga_simulate_uneven for these HOST arrays lattice_h[P]
+ * (64, 128 or 256) and horizon_h[P] (>= 0 steps) under the current variant
+ * choices; 0 for invalid arguments.
+ */
+size_t gga_uneven_workspace_bytes(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, int32_t K,
+                                  int32_t R);
+
+/*
+ * gga_simulate for a batch whose protocol p runs on a lattice_h[p] x
+ * lattice_h[p] lattice for horizon_h[p] steps (HOST arrays; cfg->L and
+ * cfg->horizon are not used).  Instances are grouped by lattice side and
+ * launched longest horizon first; slab-form groups take one launch per step
+ * over the instances still running.  live_d[P][R], fitness_d[P] as
+ * gga_simulate (-1 / NaN for invalid protocols).  The instance order is
+ * uploaded from host memory, and the call waits for that copy (and the work
+ * already on `stream`) before enqueueing the kernels; it returns without
+ * waiting for them.  Errors: as gga_simulate; GGA_E_UNSUPPORTED for another
+ * side or too many sub-steps for the slab plan; GGA_E_ARG for a small
+ * workspace.
+ */
+int gga_simulate_uneven(const gga_params* params, const gga_sim_cfg* cfg, const float* dose_d,
+                        const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P, int32_t K,
+                        const int32_t* lattice_h, const int32_t* horizon_h, void* ws_d, size_t ws_bytes,
+                        int32_t* live_d, float* fitness_d, hipStream_t stream);
+
+/* Workspace of gga_state_run_variant's event table. */
+size_t gga_event_table_bytes(int32_t P, int32_t K);
+
+/*
+ * Test hook: gga_state_run with kernel variant `variant` (side cfg->L).  Slab
+ * variants need nsteps >= 1, second state buffers fields2_d / cells2_d of the
+ * same shape (overwritten) and ws_d of gga_event_table_bytes(P, K) bytes; the
+ * result is in fields_d / cells_d.  live_d[P][R] (or NULL) receives the live
+ * counts after the last step.  Errors: as gga_state_run; GGA_E_ARG for a
+ * variant of another side.
+ */
+int gga_state_run_variant(const gga_params* params, const gga_sim_cfg* cfg, int32_t variant,
+                          const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P,
+                          int32_t K, int32_t n0, int32_t nsteps, float* fields_d, uint16_t* cells_d,
+                          float* fields2_d, uint16_t* cells2_d, void* ws_d, size_t ws_bytes, int32_t* live_d,
+                          hipStream_t stream);
+
+/* Workspace of gga_autotune: the largest uneven workspace over L's variants. */
+size_t gga_autotune_workspace_bytes(int32_t L, int32_t P, int32_t K, int32_t R, int32_t horizon);
+
+/*
+ * Autotuner: simulate the protocols on side cfg->L for cfg->horizon steps with
+ * every variant of that side (one warm-up run, then the faster of two timed
+ * runs, HIP events on `stream`), write each variant's milliseconds to ms_h
+ * (HOST, gga_variant_count() entries, NaN for variants not timed), and make
+ * the fastest the choice for L (and the fastest resident one the resident
+ * choice).  live_d[P][R] and fitness_d[P] hold the last run's results.
+ * Synchronous.  Returns the chosen variant, or an error as
+ * gga_simulate_uneven.
+ */
+int gga_autotune(const gga_params* params, const gga_sim_cfg* cfg, const float* dose_d, const int32_t* gap_h_d,
+                 const int32_t* nfrac_d, int32_t P, int32_t K, void* ws_d, size_t ws_bytes, int32_t* live_d,
+                 float* fitness_d, float* ms_h, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -107,6 +107,20 @@ def _load():
                                ctypes.c_int),
         "gga_sga_run": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, ctypes.c_size_t, vp, vp,
                          vp, vp, vp], ctypes.c_int),
+        "gga_variant_count": ([], ctypes.c_int),
+        "gga_variant_side": ([i32], i32),
+        "gga_variant_is_slab": ([i32], i32),
+        "gga_variant_name": ([i32], ctypes.c_char_p),
+        "gga_get_variant": ([i32, i32], ctypes.c_int),
+        "gga_set_variant": ([i32, i32], ctypes.c_int),
+        "gga_uneven_workspace_bytes": ([vp, vp, i32, i32, i32], ctypes.c_size_t),
+        "gga_simulate_uneven": ([vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, ctypes.c_size_t, vp, vp, vp],
+                                ctypes.c_int),
+        "gga_event_table_bytes": ([i32, i32], ctypes.c_size_t),
+        "gga_state_run_variant": ([vp, vp, i32, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp,
+                                   ctypes.c_size_t, vp, vp], ctypes.c_int),
+        "gga_autotune_workspace_bytes": ([i32, i32, i32, i32, i32], ctypes.c_size_t),
+        "gga_autotune": ([vp, vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -121,7 +135,10 @@ EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
            "gga_philox_fill", "gga_ga_breed", "gga_ga_workspace_bytes", "gga_ga_set_generation",
            "gga_ga_generation", "gga_ga_run", "gga_mlp_net_bytes", "gga_mlp_work_bytes", "gga_mlp_init",
            "gga_mlp_set_norm", "gga_mlp_predict", "gga_mlp_grad", "gga_mlp_train_step", "gga_mlp_gemm",
-           "gga_sga_workspace_bytes", "gga_sga_init", "gga_sga_generation", "gga_sga_run")
+           "gga_sga_workspace_bytes", "gga_sga_init", "gga_sga_generation", "gga_sga_run",
+           "gga_variant_count", "gga_variant_side", "gga_variant_is_slab", "gga_variant_name", "gga_get_variant",
+           "gga_set_variant", "gga_uneven_workspace_bytes", "gga_simulate_uneven", "gga_event_table_bytes",
+           "gga_state_run_variant", "gga_autotune_workspace_bytes", "gga_autotune")
 
 
 class GGAError(RuntimeError):
@@ -287,6 +304,88 @@ def philox_fill(ctr, seed, stream=None):
     out = torch.empty_like(ctr)
     _check(LIB.gga_philox_fill(_ptr(ctr), int(seed), _ptr(out), ctr.shape[0], _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------- kernel variants, uneven batches
+
+def variants():
+    """[(id, lattice side, slab form, name)] of the simulation kernel variants."""
+    return [(v, int(LIB.gga_variant_side(v)), bool(LIB.gga_variant_is_slab(v)), LIB.gga_variant_name(v).decode())
+            for v in range(LIB.gga_variant_count())]
+
+
+def get_variant(L, resident_only=False):
+    v = LIB.gga_get_variant(int(L), int(bool(resident_only)))
+    _check(min(v, 0))
+    return v
+
+
+def set_variant(L, v):
+    _check(LIB.gga_set_variant(int(L), int(v)))
+
+
+def _host_i32(x, P, what):
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(x, dtype=np.int32), (P,)))
+    if a.shape != (P,):
+        raise ValueError(f"{what} must hold one value per protocol")
+    return a
+
+
+def uneven_workspace(lattice, horizon, P, K, R, device="cuda"):
+    lat, hor = _host_i32(lattice, P, "lattice"), _host_i32(horizon, P, "horizon")
+    n = LIB.gga_uneven_workspace_bytes(lat.ctypes.data_as(ctypes.c_void_p), hor.ctypes.data_as(ctypes.c_void_p),
+                                       P, K, R)
+    if n == 0 and P > 0:
+        raise GGAError("no uneven plan: lattice sides must be 64, 128 or 256 and horizons >= 0")
+    return torch.empty(int(n), dtype=torch.uint8, device=device)
+
+
+def simulate_uneven(params, cfg, dose, gap, nfrac, lattice, horizon, ws=None, out=None, stream=None):
+    """Simulate protocol p on a lattice[p] x lattice[p] lattice for horizon[p]
+    steps (host arrays or scalars; cfg.L and cfg.horizon are not used).
+    Returns (live[P, R], fitness[P])."""
+    P, K = _protocols(dose, gap, nfrac)
+    lat, hor = _host_i32(lattice, P, "lattice"), _host_i32(horizon, P, "horizon")
+    if ws is None:
+        ws = uneven_workspace(lat, hor, P, K, cfg.R, dose.device)
+    if out is None:
+        out = (torch.empty((P, cfg.R), dtype=torch.int32, device=dose.device),
+               torch.empty((P,), dtype=torch.float32, device=dose.device))
+    live, fit = out
+    _check(LIB.gga_simulate_uneven(ctypes.byref(_as_params(params)), ctypes.byref(cfg), _ptr(dose), _ptr(gap),
+                                   _ptr(nfrac), P, K, lat.ctypes.data_as(ctypes.c_void_p),
+                                   hor.ctypes.data_as(ctypes.c_void_p), _ptr(ws), ws.numel(), _ptr(live), _ptr(fit),
+                                   _stream(stream)))
+    return live, fit
+
+
+def state_run_variant(params, cfg, variant, dose, gap, nfrac, n0, nsteps, fields, cells, stream=None):
+    """state_run with a given kernel variant (slab variants step through a second
+    state buffer); advances (fields, cells) in place, returns live[P, R]."""
+    P, K = _protocols(dose, gap, nfrac)
+    live = torch.empty((P, cfg.R), dtype=torch.int32, device=dose.device)
+    f2, c2 = torch.empty_like(fields), torch.empty_like(cells)
+    ws = torch.empty(max(int(LIB.gga_event_table_bytes(P, K)), 1), dtype=torch.uint8, device=dose.device)
+    _check(LIB.gga_state_run_variant(ctypes.byref(_as_params(params)), ctypes.byref(cfg), int(variant), _ptr(dose),
+                                     _ptr(gap), _ptr(nfrac), P, K, int(n0), int(nsteps), _ptr(fields), _ptr(cells),
+                                     _ptr(f2), _ptr(c2), _ptr(ws), ws.numel(), _ptr(live), _stream(stream)))
+    return live
+
+
+def autotune(params, cfg, dose, gap, nfrac, stream=None):
+    """Time every kernel variant for cfg.L on these protocols (cfg.horizon steps)
+    and make the fastest the choice for cfg.L.  Returns (variant, {variant: ms})."""
+    P, K = _protocols(dose, gap, nfrac)
+    n = LIB.gga_autotune_workspace_bytes(cfg.L, P, K, cfg.R, cfg.horizon)
+    ws = torch.empty(max(int(n), 1), dtype=torch.uint8, device=dose.device)
+    live = torch.empty((P, cfg.R), dtype=torch.int32, device=dose.device)
+    fit = torch.empty((P,), dtype=torch.float32, device=dose.device)
+    ms = np.zeros(LIB.gga_variant_count(), dtype=np.float32)
+    v = LIB.gga_autotune(ctypes.byref(_as_params(params)), ctypes.byref(cfg), _ptr(dose), _ptr(gap), _ptr(nfrac),
+                         P, K, _ptr(ws), ws.numel(), _ptr(live), _ptr(fit), ms.ctypes.data_as(ctypes.c_void_p),
+                         _stream(stream))
+    _check(min(v, 0))
+    return v, {i: float(t) for i, t in enumerate(ms) if np.isfinite(t)}
 
 
 # ---------------------------------------------------------------- GA

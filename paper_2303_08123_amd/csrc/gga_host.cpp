@@ -831,3 +831,366 @@ int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_c
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ kernel variants, uneven batches
+
+namespace {
+
+// Slab rows for lattice side L, RR rows per workgroup and a halo of H rows:
+// the first and last slab own RR - H rows at the lattice edges, middle slabs
+// at most RR - 2H.  Returns the slab count (0: RR >= L, resident; -1: no plan).
+int slab_plan(int L, int RR, int H, gga::SimArgs* a) {
+    if (RR >= L) return 0;
+    const int own_edge = RR - H;
+    if (own_edge < 1) return -1;
+    int ns = 0;
+    auto add = [&](int ys, int i0, int i1) {
+        if (ns < gga::MAX_SLABS) {
+            a->slab_ys[ns] = ys;
+            a->slab_i0[ns] = i0;
+            a->slab_i1[ns] = i1;
+        }
+        ++ns;
+    };
+    if (2 * own_edge >= L) {                      // the two edge slabs meet
+        const int half = L / 2;
+        add(0, 0, half);
+        add(L - RR, half - (L - RR), RR);
+    } else {
+        const int mid = RR - 2 * H;
+        if (mid < 1) return -1;
+        const int m = L - 2 * own_edge;
+        const int nm = (m + mid - 1) / mid;
+        add(0, 0, own_edge);
+        int at = own_edge;
+        for (int j = 0; j < nm; ++j) {
+            const int len = m / nm + (j < m % nm ? 1 : 0);
+            add(at - H, H, H + len);
+            at += len;
+        }
+        add(L - RR, H, RR);
+    }
+    a->n_slabs = ns;
+    return ns <= gga::MAX_SLABS ? ns : -1;
+}
+
+int side_ok(int L) { return L == 64 || L == 128 || L == 256; }
+
+size_t state_bytes(int L) { return (size_t)L * L * (3 * sizeof(float) + sizeof(uint16_t)); }
+
+// One group of instances that share a lattice side (and so a kernel variant).
+struct Group {
+    int L, variant, first, count, max_h;   // instances list[first .. first+count), horizon-descending
+    size_t state_off;                      // slab form: two state buffers of count instances
+};
+
+struct UnevenPlan {
+    std::vector<int32_t> host;             // instance lists then horizons, uploaded together
+    std::vector<Group> groups;
+    size_t off_lists, off_horizon, off_valid, off_count, off_step, off_thr, total;
+};
+
+// Group the P*R instances by lattice side, each group sorted by horizon
+// (longest first, then by index), and lay out the workspace.
+int plan_uneven(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, int32_t K, int32_t R,
+                const int* force, UnevenPlan* plan) {
+    const int sides[3] = {64, 128, 256};
+    for (int32_t p = 0; p < P; ++p) {
+        if (!side_ok(lattice_h[p])) return GGA_E_UNSUPPORTED;
+        if (horizon_h[p] < 0) return GGA_E_ARG;
+    }
+    plan->host.clear();
+    plan->groups.clear();
+    for (int si = 0; si < 3; ++si) {
+        const int L = sides[si];
+        std::vector<int32_t> list;
+        for (int32_t p = 0; p < P; ++p)
+            if (lattice_h[p] == L)
+                for (int32_t r = 0; r < R; ++r) list.push_back(p * R + r);
+        if (list.empty()) continue;
+        std::stable_sort(list.begin(), list.end(),
+                         [&](int32_t x, int32_t y) { return horizon_h[x / R] > horizon_h[y / R]; });
+        const int v = force && force[si] >= 0 ? force[si] : gga::variant_choice(L, false);
+        if (v < 0) return GGA_E_UNSUPPORTED;
+        Group g{L, v, (int)plan->host.size(), (int)list.size(), horizon_h[list[0] / R], 0};
+        plan->groups.push_back(g);
+        plan->host.insert(plan->host.end(), list.begin(), list.end());
+    }
+    const size_t n_inst = plan->host.size();
+    plan->host.insert(plan->host.end(), horizon_h, horizon_h + P);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t at = off; off += align256(bytes); return at; };
+    plan->off_lists = take(sizeof(int32_t) * n_inst);
+    plan->off_horizon = take(sizeof(int32_t) * (size_t)P);
+    plan->off_valid = take(sizeof(int32_t) * (size_t)P);
+    plan->off_count = take(sizeof(int32_t) * (size_t)P);
+    plan->off_step = take(sizeof(int32_t) * (size_t)P * K);
+    plan->off_thr = take(sizeof(uint32_t) * 4 * (size_t)P * K);
+    for (auto& g : plan->groups)
+        if (gga::variant_is_slab(g.variant)) g.state_off = take(2 * state_bytes(g.L) * (size_t)g.count);
+    plan->total = off;
+    return GGA_OK;
+}
+
+// Enqueue the uneven batch (the plan's host part already uploaded).
+hipError_t enqueue_uneven(const gga::SimArgs& base, const UnevenPlan& plan, char* ws, int32_t P, int32_t R,
+                          int32_t* live_d, float* fitness_d, hipStream_t stream) {
+    gga::SimArgs a = base;
+    a.live = live_d;
+    a.horizon = reinterpret_cast<const int32_t*>(ws + plan.off_horizon);
+    a.ev_valid = reinterpret_cast<const int32_t*>(ws + plan.off_valid);
+    a.ev_count = reinterpret_cast<const int32_t*>(ws + plan.off_count);
+    a.ev_step = reinterpret_cast<const int32_t*>(ws + plan.off_step);
+    a.ev_thr = reinterpret_cast<const uint32_t*>(ws + plan.off_thr);
+    hipError_t e = gga::launch_event_table(a, P, reinterpret_cast<int32_t*>(ws + plan.off_valid),
+                                           reinterpret_cast<int32_t*>(ws + plan.off_count),
+                                           reinterpret_cast<int32_t*>(ws + plan.off_step),
+                                           reinterpret_cast<uint32_t*>(ws + plan.off_thr), stream);
+    const int32_t* lists = reinterpret_cast<const int32_t*>(ws + plan.off_lists);
+    for (const Group& g : plan.groups) {
+        if (e != hipSuccess) break;
+        a.inst_list = lists + g.first;
+        if (!gga::variant_is_slab(g.variant)) {
+            a.n0 = 0;
+            a.nsteps = 0;                          // steps come from horizon[]
+            a.mode = 0;
+            e = gga::launch_variant(g.variant, a, g.count, stream);
+            continue;
+        }
+        const gga::SimVariant& v = gga::SIM_VARIANTS[g.variant];
+        if (slab_plan(g.L, v.rpt * v.nw, a.substeps + 2, &a) <= 0) return hipErrorInvalidValue;
+        const size_t sb = state_bytes(g.L) * (size_t)g.count;
+        float* fa = reinterpret_cast<float*>(ws + g.state_off);
+        uint16_t* ca = reinterpret_cast<uint16_t*>(ws + g.state_off + (size_t)g.count * g.L * g.L * 3 * sizeof(float));
+        float* fb = reinterpret_cast<float*>(ws + g.state_off + sb);
+        uint16_t* cb = reinterpret_cast<uint16_t*>(ws + g.state_off + sb + (size_t)g.count * g.L * g.L * 3 * sizeof(float));
+        e = gga::launch_slab_init(a, g.L, g.count, fa, ca, stream);
+        // step n: the instances with horizon > n are a prefix of the group's list
+        int active = g.count;
+        for (int n = 0; n < g.max_h && e == hipSuccess; ++n) {
+            while (active > 0 && plan.host[plan.host.size() - P + plan.host[g.first + active - 1] / R] <= n) --active;
+            if (active == 0) break;
+            a.n0 = n;
+            a.nsteps = 1;
+            a.fields = (n & 1) ? fb : fa;
+            a.cells = (n & 1) ? cb : ca;
+            a.fields_out = (n & 1) ? fa : fb;
+            a.cells_out = (n & 1) ? ca : cb;
+            e = gga::launch_variant(g.variant, a, active * a.n_slabs, stream);
+        }
+    }
+    if (e == hipSuccess) e = gga::launch_fitness(live_d, P, R, fitness_d, stream);
+    return e;
+}
+
+}  // namespace
+
+namespace {
+
+int upload_plan(const UnevenPlan& plan, char* ws, int32_t P, hipStream_t stream) {
+    const size_t n_inst = plan.host.size() - (size_t)P;
+    hipError_t e = hipSuccess;
+    if (n_inst) e = hipMemcpyAsync(ws + plan.off_lists, plan.host.data(), sizeof(int32_t) * n_inst,
+                                   hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && P)
+        e = hipMemcpyAsync(ws + plan.off_horizon, plan.host.data() + n_inst, sizeof(int32_t) * (size_t)P,
+                           hipMemcpyHostToDevice, stream);
+    // the host vector is released on return
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int check_uneven_cfg(const gga_sim_cfg* c) {
+    if (!c) return GGA_E_ARG;
+    if (c->struct_size != sizeof(gga_sim_cfg)) return GGA_E_ABI;
+    if (c->flags != 0 || c->R < 1 || !std::isfinite(c->dose_cap)) return GGA_E_ARG;
+    if (c->substeps < 1 || c->substeps > 64) return GGA_E_UNSUPPORTED;
+    return GGA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gga_variant_count(void) { return gga::N_SIM_VARIANTS; }
+
+int32_t gga_variant_side(int32_t v) { return (v >= 0 && v < gga::N_SIM_VARIANTS) ? gga::SIM_VARIANTS[v].L : -1; }
+
+int32_t gga_variant_is_slab(int32_t v) {
+    return (v >= 0 && v < gga::N_SIM_VARIANTS) ? (gga::variant_is_slab(v) ? 1 : 0) : -1;
+}
+
+const char* gga_variant_name(int32_t v) {
+    return (v >= 0 && v < gga::N_SIM_VARIANTS) ? gga::SIM_VARIANTS[v].name : "no such variant";
+}
+
+int gga_get_variant(int32_t L, int32_t resident_only) {
+    const int v = gga::variant_choice(L, resident_only != 0);
+    return v < 0 ? GGA_E_UNSUPPORTED : v;
+}
+
+int gga_set_variant(int32_t L, int32_t v) { return gga::set_variant_choice(L, v) == 0 ? GGA_OK : GGA_E_ARG; }
+
+size_t gga_uneven_workspace_bytes(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, int32_t K,
+                                  int32_t R) {
+    if (check_batch(P, K, R) || R < 1 || (P > 0 && (!lattice_h || !horizon_h))) return 0;
+    UnevenPlan plan;
+    if (plan_uneven(lattice_h, horizon_h, P, K, R, nullptr, &plan)) return 0;
+    return plan.total;
+}
+
+int gga_simulate_uneven(const gga_params* params, const gga_sim_cfg* cfg, const float* dose_d,
+                        const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P, int32_t K,
+                        const int32_t* lattice_h, const int32_t* horizon_h, void* ws_d, size_t ws_bytes,
+                        int32_t* live_d, float* fitness_d, hipStream_t stream) {
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((rc = check_uneven_cfg(cfg))) return rc;
+    if ((rc = check_batch(P, K, cfg->R))) return rc;
+    if (P == 0) return GGA_OK;
+    if (!lattice_h || !horizon_h || !nfrac_d || !live_d || !fitness_d || !ws_d || (K > 0 && (!dose_d || !gap_h_d)))
+        return GGA_E_ARG;
+    UnevenPlan plan;
+    if ((rc = plan_uneven(lattice_h, horizon_h, P, K, cfg->R, nullptr, &plan))) return rc;
+    if (ws_bytes < plan.total) return GGA_E_ARG;
+    char* ws = static_cast<char*>(ws_d);
+    if ((rc = upload_plan(plan, ws, P, stream))) return rc;
+    const gga::SimArgs base = make_args(params, cfg, dose_d, gap_h_d, nfrac_d, K);
+    const hipError_t e = enqueue_uneven(base, plan, ws, P, cfg->R, live_d, fitness_d, stream);
+    return e == hipSuccess ? GGA_OK : (e == hipErrorInvalidValue ? GGA_E_UNSUPPORTED : hip_fail(e));
+}
+
+size_t gga_event_table_bytes(int32_t P, int32_t K) {
+    if (P < 0 || K < 0 || K > GGA_KMAX) return 0;
+    return align256(sizeof(int32_t) * 2 * (size_t)P) + align256(sizeof(int32_t) * 5 * (size_t)P * K);
+}
+
+int gga_state_run_variant(const gga_params* params, const gga_sim_cfg* cfg, int32_t variant,
+                          const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P,
+                          int32_t K, int32_t n0, int32_t nsteps, float* fields_d, uint16_t* cells_d,
+                          float* fields2_d, uint16_t* cells2_d, void* ws_d, size_t ws_bytes, int32_t* live_d,
+                          hipStream_t stream) {
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((rc = check_uneven_cfg(cfg))) return rc;
+    if ((rc = check_batch(P, K, cfg->R))) return rc;
+    if (variant < 0 || variant >= gga::N_SIM_VARIANTS || gga::SIM_VARIANTS[variant].L != cfg->L) return GGA_E_ARG;
+    if (n0 < 0 || nsteps < 0 || (long long)n0 + nsteps > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
+    if (P == 0) return GGA_OK;
+    if (!nfrac_d || !fields_d || !cells_d || (K > 0 && (!dose_d || !gap_h_d))) return GGA_E_ARG;
+    gga::SimArgs a = make_args(params, cfg, dose_d, gap_h_d, nfrac_d, K);
+    a.live = live_d;
+    hipError_t e = hipSuccess;
+    if (!gga::variant_is_slab(variant)) {
+        a.n0 = n0;
+        a.nsteps = nsteps;
+        a.mode = gga::MODE_LOAD | gga::MODE_STORE;
+        a.fields = fields_d;
+        a.cells = cells_d;
+        e = gga::launch_variant(variant, a, P * cfg->R, stream);
+        return e == hipSuccess ? GGA_OK : hip_fail(e);
+    }
+    if (nsteps < 1 || !fields2_d || !cells2_d || !ws_d || ws_bytes < gga_event_table_bytes(P, K)) return GGA_E_ARG;
+    const gga::SimVariant& v = gga::SIM_VARIANTS[variant];
+    if (slab_plan(cfg->L, v.rpt * v.nw, cfg->substeps + 2, &a) <= 0) return GGA_E_UNSUPPORTED;
+    char* ws = static_cast<char*>(ws_d);
+    int32_t* valid = reinterpret_cast<int32_t*>(ws);
+    int32_t* count = valid + P;
+    int32_t* step = reinterpret_cast<int32_t*>(ws + align256(sizeof(int32_t) * 2 * (size_t)P));
+    uint32_t* thr = reinterpret_cast<uint32_t*>(step + (size_t)P * K);
+    a.ev_valid = valid;
+    a.ev_count = count;
+    a.ev_step = step;
+    a.ev_thr = thr;
+    a.count_at = n0 + nsteps;
+    e = gga::launch_event_table(a, P, valid, count, step, thr, stream);
+    if (e == hipSuccess) e = gga::launch_slab_live(a, P * cfg->R, stream);
+    for (int32_t n = n0; n < n0 + nsteps && e == hipSuccess; ++n) {
+        const bool odd = ((n - n0) & 1) != 0;
+        a.n0 = n;
+        a.nsteps = 1;
+        a.fields = odd ? fields2_d : fields_d;
+        a.cells = odd ? cells2_d : cells_d;
+        a.fields_out = odd ? fields_d : fields2_d;
+        a.cells_out = odd ? cells_d : cells2_d;
+        e = gga::launch_variant(variant, a, P * cfg->R * a.n_slabs, stream);
+    }
+    if (e == hipSuccess && (nsteps & 1)) {         // the result is in the second buffers
+        const size_t plane = (size_t)cfg->L * cfg->L, inst = (size_t)P * cfg->R;
+        e = hipMemcpyAsync(fields_d, fields2_d, sizeof(float) * 3 * plane * inst, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(cells_d, cells2_d, sizeof(uint16_t) * plane * inst, hipMemcpyDeviceToDevice, stream);
+    }
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+size_t gga_autotune_workspace_bytes(int32_t L, int32_t P, int32_t K, int32_t R, int32_t horizon) {
+    if (!side_ok(L) || P < 1 || R < 1 || horizon < 0 || check_batch(P, K, R)) return 0;
+    std::vector<int32_t> lat((size_t)P, L), hor((size_t)P, horizon);
+    size_t most = 0;
+    const int si = L == 64 ? 0 : L == 128 ? 1 : 2;
+    for (int v = 0; v < gga::N_SIM_VARIANTS; ++v) {
+        if (gga::SIM_VARIANTS[v].L != L) continue;
+        int force[3] = {-1, -1, -1};
+        force[si] = v;
+        UnevenPlan plan;
+        if (plan_uneven(lat.data(), hor.data(), P, K, R, force, &plan) == GGA_OK) most = std::max(most, plan.total);
+    }
+    return most;
+}
+
+int gga_autotune(const gga_params* params, const gga_sim_cfg* cfg, const float* dose_d, const int32_t* gap_h_d,
+                 const int32_t* nfrac_d, int32_t P, int32_t K, void* ws_d, size_t ws_bytes, int32_t* live_d,
+                 float* fitness_d, float* ms_h, hipStream_t stream) {
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((rc = check_uneven_cfg(cfg))) return rc;
+    if ((rc = check_batch(P, K, cfg->R))) return rc;
+    if (!side_ok(cfg->L)) return GGA_E_UNSUPPORTED;
+    if (P < 1 || cfg->horizon < 0 || !nfrac_d || !live_d || !fitness_d || !ws_d || (K > 0 && (!dose_d || !gap_h_d)))
+        return GGA_E_ARG;
+    const int L = cfg->L, si = L == 64 ? 0 : L == 128 ? 1 : 2;
+    std::vector<int32_t> lat((size_t)P, L), hor((size_t)P, cfg->horizon);
+    const gga::SimArgs base = make_args(params, cfg, dose_d, gap_h_d, nfrac_d, K);
+    char* ws = static_cast<char*>(ws_d);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    int best = -1, best_res = -1;
+    float best_ms = 0.0f, best_res_ms = 0.0f;
+    for (int v = 0; v < gga::N_SIM_VARIANTS && e == hipSuccess; ++v) {
+        if (ms_h) ms_h[v] = std::numeric_limits<float>::quiet_NaN();
+        if (gga::SIM_VARIANTS[v].L != L) continue;
+        int force[3] = {-1, -1, -1};
+        force[si] = v;
+        UnevenPlan plan;
+        if (plan_uneven(lat.data(), hor.data(), P, K, cfg->R, force, &plan) != GGA_OK) continue;
+        if (ws_bytes < plan.total) { rc = GGA_E_ARG; break; }
+        if ((rc = upload_plan(plan, ws, P, stream))) break;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {    // the first run warms up
+            e = hipEventRecord(t0, stream);
+            if (e == hipSuccess) e = enqueue_uneven(base, plan, ws, P, cfg->R, live_d, fitness_d, stream);
+            if (e == hipSuccess) e = hipEventRecord(t1, stream);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, t0, t1);
+            if (rep == 1 || (rep == 2 && t < ms)) ms = t;
+        }
+        if (e == hipErrorInvalidValue) { e = hipSuccess; continue; }   // no slab plan for these sub-steps
+        if (e != hipSuccess) break;
+        if (ms_h) ms_h[v] = ms;
+        if (best < 0 || ms < best_ms) { best = v; best_ms = ms; }
+        if (!gga::variant_is_slab(v) && (best_res < 0 || ms < best_res_ms)) { best_res = v; best_res_ms = ms; }
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return hip_fail(e);
+    if (rc) return rc;
+    if (best < 0) return GGA_E_UNSUPPORTED;
+    if (best_res >= 0) gga::set_variant_choice(L, best_res);
+    gga::set_variant_choice(L, best);
+    return best;
+}
+
+}  // extern "C"

@@ -26,10 +26,60 @@ struct SimArgs {
     // g read from this device counter (replayed GA generations).
     const int32_t* generation;
     uint64_t seed;
+    // Uneven batches.  Resident form: instance of block b = inst_list[b] (or b),
+    // steps = horizon[p] (or nsteps).  Slab form: instance = inst_list[b / n_slabs],
+    // slab b % n_slabs, one step n0 from fields/cells (state row b / n_slabs) to
+    // fields_out/cells_out, the event table below instead of decoding the
+    // protocol, and the live count added into live[inst] at step horizon[p] - 1.
+    const int32_t* inst_list;
+    const int32_t* horizon;   // [P]
+    float* fields_out;
+    uint16_t* cells_out;
+    int32_t n_slabs;
+    int32_t slab_ys[16], slab_i0[16], slab_i1[16];   // first lattice row; own rows [i0, i1) of the slab
+    const int32_t* ev_valid;  // [P]
+    const int32_t* ev_count;  // [P]
+    const int32_t* ev_step;   // [P][K] steps of the positive-dose fractions, in order
+    const uint32_t* ev_thr;   // [P][K][4] survival thresholds per sensitivity class
+    int32_t count_at;         // slab form without horizon[]: the step whose end is counted
 };
+constexpr int MAX_SLABS = 16;
+
+// Kernel variants: columns per lane, rows per thread, waves; RR = rpt * nw
+// rows per workgroup (slab form when RR < L = 64 * cpl).
+struct SimVariant {
+    int L, cpl, rpt, nw;
+    const char* name;
+};
+constexpr SimVariant SIM_VARIANTS[] = {
+    {64, 1, 4, 16, "L64 resident 4x1 x16 waves"},
+    {64, 1, 2, 16, "L64 slabs of 32 rows, 2x1 x16 waves"},
+    {128, 2, 8, 16, "L128 resident 8x2 x16 waves"},
+    {128, 2, 16, 8, "L128 resident 16x2 x8 waves"},
+    {128, 2, 4, 16, "L128 slabs of 64 rows, 4x2 x16 waves"},
+    {256, 4, 4, 16, "L256 slabs of 64 rows, 4x4 x16 waves"},
+    {256, 4, 8, 8, "L256 slabs of 64 rows, 8x4 x8 waves"},
+};
+constexpr int N_SIM_VARIANTS = sizeof(SIM_VARIANTS) / sizeof(SIM_VARIANTS[0]);
+constexpr bool variant_is_slab(int v) { return SIM_VARIANTS[v].rpt * SIM_VARIANTS[v].nw < SIM_VARIANTS[v].L; }
 
 bool sim_supported(int L);
+// resident launch with the variant chosen for L (gga_simulate's path)
 hipError_t launch_simulation(const SimArgs& a, int L, int n_inst, hipStream_t stream);
+// launch variant v over n_blocks workgroups (slab form: n_blocks = instances * n_slabs)
+hipError_t launch_variant(int v, const SimArgs& a, int n_blocks, hipStream_t stream);
+hipError_t launch_slab_variant(int v, const SimArgs& a, int n_blocks, hipStream_t stream);
+// process-wide variant choice per lattice side: resident (gga_simulate) and any (uneven batches)
+int variant_choice(int L, bool resident_only);
+int set_variant_choice(int L, int v);
+// event table of P protocols for the slab form (validity as the resident kernel decides it)
+hipError_t launch_event_table(const SimArgs& a, int P, int32_t* valid, int32_t* count, int32_t* step,
+                              uint32_t* thr, hipStream_t stream);
+// live[inst] = 0 (-1 for invalid protocols) for instances inst_list[0 .. n-1] (or 0 .. n-1)
+hipError_t launch_slab_live(const SimArgs& a, int n, hipStream_t stream);
+// initial state of the slab-form instances inst_list[0 .. n-1] into state rows 0 .. n-1, live
+// counts set to 0 (-1 for invalid protocols; the initial count when horizon is 0)
+hipError_t launch_slab_init(const SimArgs& a, int L, int n, float* fields, uint16_t* cells, hipStream_t stream);
 hipError_t launch_fitness(const int32_t* live, int P, int R, float* fitness, hipStream_t stream);
 hipError_t launch_philox_fill(const uint32_t* ctr, uint64_t seed, uint32_t* out, long long n,
                               hipStream_t stream);

@@ -1,0 +1,641 @@
+// The simulation kernel template.  Resident form (RR = L): one workgroup
+// advances one (protocol, replica) instance through all of its steps without
+// leaving the compute unit.  Slab form (RR < L): one workgroup advances RR
+// rows of a larger lattice by one step, from one state buffer in device memory
+// to the other (see Geo).
+//
+// Layout.  L = 64 * CPL.  Wave w owns rows [w*RPT, (w+1)*RPT) of the
+// workgroup's RR rows; lane l owns columns [l*CPL, (l+1)*CPL).  The three
+// float32 fields of a thread's RPT x CPL sites live in VGPRs for the whole run
+// (resident) or step (slab); the uint16 cell words live in LDS.  One diffusion sub-step needs, per wave, only the row above and the
+// row below its slab from the neighbouring waves (an LDS exchange of 2 rows),
+// while left/right neighbours come from the adjacent lane through DPP lane
+// shifts fused into the VALU adds.  A wave's 64 lanes span a whole lattice row,
+// so the lane shifts' zero fill at lanes 0 and 63 is exactly the missing
+// neighbour outside the lattice; the Dirichlet ghost value enters through a
+// per-site constant added to the reaction term.
+//
+// Slabs.  A slab edge that is not a lattice edge is treated as if it were
+// one; the error this makes reaches `substeps` rows into the slab through the
+// diffusion and two rows further through the division proposals and their
+// conflicts, so the rows within substeps + 2 of such an edge are a halo:
+// computed, not stored, and owned by the neighbouring slab.  Every site's
+// arithmetic is the resident form's, so both give identical results.
+//
+// The method (Materials and Methods: nutrient and waste diffusion, cell
+// cycle, quiescence and death driven by the local environment, irradiation
+// damage; fitness from the final number of occupied sites, equation
+// final_fit_fun) with the synthetic model's rules:
+//   step n:  (1) fraction at n?  live cell of class c survives iff w1 < T_c
+//            (2) activity a = act[state], frozen for the hour
+//            (3) `substeps` FTCS sub-steps
+//                c' = c + lam (N + S + E + W - 4c) - kappa a  (O, G; then max(., 0))
+//                H' = H + lam (N + S + E + W - 4H) + kappa a
+//            (4) synchronous cell update from the snapshot (lysis, environment,
+//                division proposals into free von Neumann neighbours, conflict
+//                resolution by the smallest key)
+//            (5) live count (PROLIF + QUIESC) by wave reduction.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gga_device.h"
+#include "gga_internal.h"
+
+namespace gga {
+namespace {
+
+constexpr uint32_t NONE_KEY = 0xFFFFFFFFu;
+constexpr uint32_t INIT_STEP = 0xFFFFFFFFu;
+constexpr int EMPTY = 0, PROLIF = 1, QUIESC = 2, DEAD = 3;
+
+// 32-bit linear-quadratic survival threshold, evaluated in float64 exactly as
+// written: x = m d, S = exp(-alpha x - beta x x), T = min(floor(S 2^32), 2^32-1).
+#pragma clang fp contract(off)
+__device__ uint32_t lq_threshold(double d, double m, double alpha, double beta) {
+    const double x = m * d;
+    const double e = -(alpha * x) - (beta * x) * x;
+    const double s = exp(e) * 4294967296.0;
+    const double f = floor(s);
+    return f >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)f;
+}
+#pragma clang fp contract(on)
+
+// CPL consecutive uint16 cell words of one row, read or written with one
+// LDS access (the address is 2*CPL-byte aligned: x0 = lane * CPL).
+template <int CPL>
+__device__ __forceinline__ void load_words(const uint16_t* p, uint32_t (&w)[CPL]) {
+    if constexpr (CPL == 1) {
+        w[0] = p[0];
+    } else if constexpr (CPL == 2) {
+        const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+        w[0] = v & 0xFFFFu; w[1] = v >> 16;
+    } else {
+        static_assert(CPL == 4, "CPL must be 1, 2 or 4");
+        const uint2 v = *reinterpret_cast<const uint2*>(p);
+        w[0] = v.x & 0xFFFFu; w[1] = v.x >> 16; w[2] = v.y & 0xFFFFu; w[3] = v.y >> 16;
+    }
+}
+template <int CPL>
+__device__ __forceinline__ void store_words(uint16_t* p, const uint32_t (&w)[CPL]) {
+    if constexpr (CPL == 1) {
+        p[0] = (uint16_t)w[0];
+    } else if constexpr (CPL == 2) {
+        *reinterpret_cast<uint32_t*>(p) = w[0] | (w[1] << 16);
+    } else {
+        *reinterpret_cast<uint2*>(p) = make_uint2(w[0] | (w[1] << 16), w[2] | (w[3] << 16));
+    }
+}
+
+// Constants of the cell update.  They sit in LDS and are read at their point
+// of use after a barrier, so they do not occupy scalar registers across the
+// diffusion loop.
+struct CellConst {
+    float thOq, thGq, thOd, thGd, thHd;
+    int T_min, T_lys, ca0, ca1;
+    uint32_t T_div;
+};
+
+template <int CPL>
+__device__ __forceinline__ void store_keys(uint32_t* p, const uint32_t (&k)[CPL]) {
+    if constexpr (CPL == 1) {
+        p[0] = k[0];
+    } else if constexpr (CPL == 2) {
+        *reinterpret_cast<uint2*>(p) = make_uint2(k[0], k[1]);
+    } else {
+        *reinterpret_cast<uint4*>(p) = make_uint4(k[0], k[1], k[2], k[3]);
+    }
+}
+
+// L = 64 * CPL columns; NW waves of RPT rows hold RR = NW * RPT rows.  RR = L:
+// the whole lattice (resident).  RR < L: a slab of a larger lattice advanced by
+// one step per launch (the rows within `substeps + 2` of a slab edge that is
+// not a lattice edge are a halo, recomputed by the neighbouring slab).
+template <int CPL, int RPT, int NW>
+struct Geo {
+    static constexpr int L = 64 * CPL;
+    static constexpr int NWAVE = NW;
+    static constexpr int RR = NW * RPT;
+    static constexpr bool SLAB = RR < L;
+    static constexpr int NT = 64 * NWAVE;
+    static constexpr int HALO = NWAVE * 2 * 3 * L;   // one buffer: [wave][top/bottom][field][L]
+    // halo double buffer when it fits beside the cells and claim bits in LDS
+    static constexpr int NBUF = (RR * L * 2 + 2 * HALO * 4 + RR * L / 8 + 4096 <= 160 * 1024) ? 2 : 1;
+    static constexpr int POOL = (NBUF * HALO > RR * L) ? NBUF * HALO : RR * L;
+    static_assert(RR <= L && NWAVE <= 16, "workgroup above 1024 threads");
+    static_assert(RPT * CPL <= 32, "per-thread site masks are 32 bits wide");
+    static constexpr uint32_t ALL = (RPT * CPL == 32) ? 0xFFFFFFFFu : ((1u << (RPT * CPL)) - 1u);
+    // mask bits of the first / last column of every row (bit idx = i * CPL + c)
+    static constexpr uint32_t col_bits(int c) {
+        uint32_t m = 0;
+        for (int i = 0; i < RPT; ++i) m |= 1u << (i * CPL + c);
+        return m;
+    }
+    static constexpr uint32_t COL_FIRST = col_bits(0);
+    static constexpr uint32_t COL_LAST = col_bits(CPL - 1);
+};
+
+template <int CPL, int RPT, int NW>
+__global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
+    using G = Geo<CPL, RPT, NW>;
+    constexpr int L = G::L;
+    constexpr int RR = G::RR;
+    constexpr int NWAVE = G::NWAVE;
+    constexpr bool SLAB = G::SLAB;
+    constexpr uint32_t ALL_SITES = G::ALL;
+
+    __shared__ __attribute__((aligned(16))) uint16_t s_cell[RR * L];
+    __shared__ __attribute__((aligned(16))) uint32_t s_pool[G::POOL];   // halo buffer(s), then claim slots
+    __shared__ uint32_t s_claim[RR * L / 32];  // one "has a daughter" bit per site
+    __shared__ int s_ev_step[GGA_KMAX];
+    __shared__ float s_ev_dose[GGA_KMAX];
+    __shared__ uint32_t s_ev_thr[GGA_KMAX][4];
+    __shared__ int s_nev, s_valid, s_evj;
+    __shared__ int s_count[2];
+    __shared__ CellConst s_k;                  // cell-update constants, read where used
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    // instance (and slab) of this workgroup
+    int inst, slab = 0;
+    if constexpr (SLAB) {
+        inst = a.inst_list ? a.inst_list[blockIdx.x / a.n_slabs] : (int)(blockIdx.x / a.n_slabs);
+        slab = blockIdx.x - (blockIdx.x / a.n_slabs) * a.n_slabs;
+    } else {
+        inst = a.inst_list ? a.inst_list[blockIdx.x] : (int)blockIdx.x;
+    }
+    const int slot = SLAB ? (int)(blockIdx.x / a.n_slabs) : inst;   // state buffer row
+    const int p = inst / a.R;
+    const int r = inst - p * a.R;
+    // the slab's first lattice row, and its own (non-halo) rows [iy0, iy1) of the slab
+    const int ys = SLAB ? a.slab_ys[slab] : 0;
+    const int iy0 = SLAB ? a.slab_i0[slab] : 0, iy1 = SLAB ? a.slab_i1[slab] : RR;
+    const int gofs = ys * L;                         // slab site index + gofs = lattice site index
+    const int nsteps = (!SLAB && a.horizon) ? a.horizon[p] : a.nsteps;
+    const int y0 = wave * RPT;
+    const int x0 = lane * CPL;
+    const gga_params& P = a.prm;
+    // Philox key; `a` itself stays unmodified (a written kernel argument would
+    // be copied to scratch memory)
+    uint32_t seed_lo = a.seed_lo, seed_hi = a.seed_hi;
+    if (a.generation) {             // per-generation key of a replayed GA generation
+        const uint64_t key = a.seed + (uint64_t)(uint32_t)*a.generation * 0x9E3779B97F4A7C15ull;
+        seed_lo = (uint32_t)key;
+        seed_hi = (uint32_t)(key >> 32);
+    }
+
+    // ---- protocol: validity and irradiation events ----
+    if constexpr (SLAB) {
+        // event table (one fraction per step at most): lane j of wave 0 checks fraction j
+        if (wave == 0) {
+            const int k = a.ev_count[p];
+            bool hit = false;
+            for (int j = lane; j < k; j += 64) hit |= (a.ev_step[(size_t)p * a.K + j] == a.n0);
+            int jj = -1;
+            for (int j = lane; j < k; j += 64)
+                if (a.ev_step[(size_t)p * a.K + j] == a.n0) jj = j;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+            if (lane == (m ? __builtin_ctzll(m) : 0)) s_evj = jj;
+            if (lane == 0) {
+                s_valid = a.ev_valid[p];
+                s_nev = m ? 1 : 0;
+                s_ev_step[0] = a.n0;
+            }
+        }
+    }
+    if (tid == 0) {
+        const int k = a.nfrac ? a.nfrac[p] : 0;
+        int valid = (k >= 0 && k <= a.K);
+        int nev = 0;
+        double total = 0.0;
+        long long t = 0;
+        for (int j = 0; !SLAB && valid && j < k; ++j) {
+            const float d = a.dose[(size_t)p * a.K + j];
+            const int g = a.gap[(size_t)p * a.K + j];
+            if (!(d >= 0.0f) || !isfinite(d)) { valid = 0; break; }
+            if (g < (j == 0 ? 0 : 1)) { valid = 0; break; }
+            total += (double)d;
+            t += g;
+            if (d > 0.0f && t >= a.n0 && t < (long long)a.n0 + nsteps) {
+                s_ev_step[nev] = (int)t;
+                s_ev_dose[nev] = d;
+                ++nev;
+            }
+        }
+        if (valid && total > a.dose_cap + 1e-6) valid = 0;
+        if (!SLAB) {
+            s_valid = valid;
+            s_nev = nev;
+        }
+        const gga_params& Q = a.prm;
+        s_k.thOq = Q.theta_O_quiesce; s_k.thGq = Q.theta_G_quiesce;
+        s_k.thOd = Q.theta_O_death; s_k.thGd = Q.theta_G_death; s_k.thHd = Q.theta_H_death;
+        s_k.T_min = Q.T_min; s_k.T_lys = Q.T_lys;
+        s_k.ca0 = Q.class_age[0]; s_k.ca1 = Q.class_age[1];
+        s_k.T_div = (Q.P_div >= 1.0) ? 0xFFFFFFFFu : (uint32_t)floor(Q.P_div * 4294967296.0);
+        s_count[0] = 0;
+        s_count[1] = 0;
+    }
+    __syncthreads();
+    if (!s_valid) {
+        if (!SLAB && tid == 0 && a.live) a.live[inst] = -1;   // slabs: set before the first step
+        return;                                   // uniform across the workgroup
+    }
+    const int nev = s_nev;
+    if constexpr (SLAB) {
+        if (tid < 4 * nev) s_ev_thr[0][tid] = a.ev_thr[((size_t)p * a.K + s_evj) * 4 + tid];
+    } else {
+        for (int e = tid; e < 4 * nev; e += G::NT)
+            s_ev_thr[e >> 2][e & 3] = lq_threshold((double)s_ev_dose[e >> 2], P.m[e & 3], P.alpha, P.beta);
+    }
+
+    // ---- state: fields in registers, cells in LDS ----
+    float F[3][RPT][CPL];
+    const size_t plane = (size_t)L * L;
+    if (SLAB || (a.mode & MODE_LOAD)) {
+        const float* src = a.fields + (size_t)slot * 3 * plane + gofs;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    F[f][i][c] = src[f * plane + (size_t)(y0 + i) * L + x0 + c];
+        const uint16_t* cs = a.cells + (size_t)slot * plane + gofs;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+                s_cell[(y0 + i) * L + x0 + c] = cs[(size_t)(y0 + i) * L + x0 + c];
+    } else {
+        const int ctr = L / 2;
+        const int rad2 = P.seed_radius * P.seed_radius;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) F[f][i][c] = P.init[f];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int y = y0 + i, x = x0 + c;
+                uint16_t w = 0;
+                if ((x - ctr) * (x - ctr) + (y - ctr) * (y - ctr) <= rad2) {
+                    const Block4 b = philox10(y * L + x, INIT_STEP, r, p, seed_lo, seed_hi);
+                    const uint32_t age = (uint32_t)(((uint64_t)b.w0 * (uint32_t)P.A0) >> 32);
+                    w = (uint16_t)(PROLIF | (age << 2));
+                }
+                s_cell[y * L + x] = w;
+            }
+    }
+
+    // Per-field constants.
+    float lam[3], cen[3], kap[3], gst[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        lam[f] = P.lambda[f];
+        cen[f] = 1.0f - 4.0f * P.lambda[f];
+        kap[f] = (f < 2) ? -P.kappa[f] : P.kappa[f];
+        gst[f] = P.ghost[f];
+    }
+    const float actv[4] = {P.activity[0], P.activity[1], P.activity[2], P.activity[3]};
+    // Ghost flux through the left / right lattice edge, folded into the
+    // reaction constant of the edge columns (the lane shifts deliver 0 there).
+    const bool left_edge = (lane == 0), right_edge = (lane == 63);
+    // R_f = rho_f Ro + e_f:  rho_f = kappa_f' / kappa_O' (signed uptake; the
+    // host requires kappa_O > 0), and e_f = lam_f g_f - rho_f lam_O g_O on an
+    // edge column, 0 elsewhere.
+    float rho[3], eoff[3][CPL];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) rho[f] = kap[f] / kap[0];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const bool edge = (c == 0 && left_edge) || (c == CPL - 1 && right_edge);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+            eoff[f][c] = edge ? lam[f] * gst[f] - rho[f] * (lam[0] * gst[0]) : 0.0f;
+    }
+
+    int ev = 0;
+    int count = 0;
+    __syncthreads();
+
+    for (int n = a.n0; n < a.n0 + nsteps; ++n) {
+        // Every LDS access below addresses a row as base + constant offset.  The
+        // base is opaque to the compiler at the top of each step, so per-row
+        // addresses are not hoisted out of the loop into registers.
+        int own = y0 * L + x0;
+        asm volatile("" : "+v"(own));
+        uint16_t* const cellp = s_cell + own;            // row i: cellp + i * L
+        // (1) irradiation: every live cell draws w1 against its class threshold
+        if (ev < nev && s_ev_step[ev] == n) {
+            const uint32_t t0 = s_ev_thr[ev][0], t1 = s_ev_thr[ev][1];
+            const uint32_t t2 = s_ev_thr[ev][2], t3 = s_ev_thr[ev][3];
+            const int ca0 = s_k.ca0, ca1 = s_k.ca1;
+            uint32_t live_mask = 0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int st = cellp[i * L + c] & 3;
+                    if (st == PROLIF || st == QUIESC) live_mask |= 1u << (i * CPL + c);
+                }
+            while (live_mask) {
+                const int idx = __builtin_ctz(live_mask);
+                live_mask &= live_mask - 1;
+                const int site = own + (idx / CPL) * L + idx % CPL;
+                const uint32_t w = s_cell[site];
+                const int st = w & 3, age = w >> 2;
+                const uint32_t thr = (st == QUIESC) ? t3 : (age < ca0 ? t0 : (age < ca1 ? t1 : t2));
+                const Block4 b = philox10(site + gofs, n, r, p, seed_lo, seed_hi);
+                if (b.w1 >= thr) s_cell[site] = DEAD;
+            }
+            ++ev;
+        }
+
+        // (2) reaction constants for the hour.  Only oxygen's term is kept per
+        // site, Ro = -kappa_O a (+ lam_O g_O on an edge column); the glucose and
+        // acid terms are affine in it, R_f = rho_f Ro + e_f with per-lane
+        // constants, which saves two VGPRs per site for one FMA each.
+        float Ro[RPT][CPL];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const bool edge = (c == 0 && left_edge) || (c == CPL - 1 && right_edge);
+                const float act = actv[cellp[i * L + c] & 3];
+                Ro[i][c] = fmaf(kap[0], act, edge ? lam[0] * gst[0] : 0.0f);
+            }
+
+        // (3) diffusion sub-steps
+        for (int s = 0; s < a.substeps; ++s) {
+            // Keep the glucose / acid terms from being hoisted out of the loop
+            // (they would cost two live VGPRs per site): Ro is opaque here.
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) asm volatile("" : "+v"(Ro[i][c]));
+            // this wave's halo block: [top/bottom][field][L] at wave * 6 L
+            float* const hw = reinterpret_cast<float*>(s_pool) + (G::NBUF == 2 ? (s & 1) * G::HALO : 0) + wave * 6 * L + x0;
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    hw[f * L + c] = F[f][0][c];
+                    hw[(3 + f) * L + c] = F[f][RPT - 1][c];
+                }
+            __syncthreads();
+            float up[3][CPL], dn[3][CPL];
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    up[f][c] = (wave > 0) ? hw[(f - 3) * L + c] : gst[f];            // bottom row of wave-1
+                    dn[f][c] = (wave < NWAVE - 1) ? hw[(6 + f) * L + c] : gst[f];    // top row of wave+1
+                }
+            if constexpr (G::NBUF == 1) __syncthreads();   // one buffer: all reads before the next writes
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                float nw[3][CPL];
+#pragma unroll
+                for (int f = 0; f < 3; ++f)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const float below = (i < RPT - 1) ? F[f][i + 1][c] : dn[f][c];
+                        const float west = (c > 0) ? F[f][i][c - 1] : lane_from_left(F[f][i][CPL - 1]);
+                        const float east = (c < CPL - 1) ? F[f][i][c + 1] : lane_from_right(F[f][i][0]);
+                        const float sum = (up[f][c] + below) + (west + east);
+                        const float rx = (f == 0) ? Ro[i][c] : fmaf(rho[f], Ro[i][c], eoff[f][c]);
+                        float v = fmaf(lam[f], sum, fmaf(F[f][i][c], cen[f], rx));
+                        if (f < 2) v = fmaxf(v, 0.0f);
+                        nw[f][c] = v;
+                    }
+#pragma unroll
+                for (int f = 0; f < 3; ++f)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        up[f][c] = F[f][i][c];
+                        F[f][i][c] = nw[f][c];
+                    }
+            }
+        }
+
+        // Environment flags of every site, taken from the fields right after the
+        // sub-steps (x < th  <=>  sign bit of x - th: the difference of two finite
+        // floats is zero only when they are equal and otherwise keeps the sign of
+        // the exact difference).  The cell update below reads only these masks.
+        uint32_t nec_m = 0, starv_m = 0;
+        {
+            const float thOq = s_k.thOq, thGq = s_k.thGq, thOd = s_k.thOd, thGd = s_k.thGd, thHd = s_k.thHd;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int idx = i * CPL + c;
+                    const float O = F[0][i][c], Gl = F[1][i][c], H = F[2][i][c];
+                    nec_m |= ((__float_as_uint(Gl - thGd) | __float_as_uint(O - thOd) |
+                               __float_as_uint(thHd - H)) >> 31) << idx;
+                    starv_m |= ((__float_as_uint(O - thOq) | __float_as_uint(Gl - thGq)) >> 31) << idx;
+                    asm volatile("" : "+v"(nec_m), "+v"(starv_m));   // fold each site in now
+                }
+        }
+
+        // (4) cell update, bit-parallel over the thread's RPT x CPL sites
+        // (bit idx = i * CPL + c of 32-bit masks).  Proposers claim an EMPTY
+        // target with ds_min_u32 on best[t] (one slot per site, sharing the
+        // halo pool) and set the target's bit in s_claim; the smallest key's
+        // low two bits name the winner's direction, so no key is kept.
+        __syncthreads();   // the last sub-step's halo reads are done
+        uint32_t* best = s_pool;
+        uint32_t* const bestp = best + own;              // row i: bestp + i * L
+        // From the snapshot: the EMPTY state of the rows just above and below
+        // this slab (owned by the neighbouring waves) and whether any of this
+        // wave's sites holds a cell.
+        uint32_t top = 0, bot = 0, occupied = 0;
+        if (wave > 0) {
+            uint32_t w[CPL];
+            load_words<CPL>(cellp - L, w);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) top |= (uint32_t)((w[c] & 3u) == EMPTY) << c;
+        }
+        if (wave < NWAVE - 1) {
+            uint32_t w[CPL];
+            load_words<CPL>(cellp + RPT * L, w);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) bot |= (uint32_t)((w[c] & 3u) == EMPTY) << c;
+        }
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            uint32_t w[CPL];
+            load_words<CPL>(cellp + i * L, w);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) occupied |= w[c];
+        }
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            uint32_t none[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) none[c] = NONE_KEY;
+            store_keys<CPL>(bestp + i * L, none);
+        }
+        for (int k = tid; k < RR * L / 32; k += G::NT) s_claim[k] = 0u;
+        __syncthreads();   // boundary rows read, claims reset: own rows may now be rewritten
+        // Per site: lysis and environment transitions, written back row by row.
+        uint32_t empty_m = ALL_SITES, cyc_m = 0, old_m = 0, alive_m = 0;
+        if (__builtin_amdgcn_ballot_w64(occupied != 0u) != 0) {   // wave-uniform; else all EMPTY
+            const int T_lys = s_k.T_lys, T_min = s_k.T_min;
+            empty_m = 0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                uint32_t w[CPL];
+                load_words<CPL>(cellp + i * L, w);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int idx = i * CPL + c;
+                    const uint32_t st = w[c] & 3u, age = w[c] >> 2;
+                    const uint32_t older = age < 255u ? age + 1u : 255u;
+                    const uint32_t nec = (nec_m >> idx) & 1u, starv = (starv_m >> idx) & 1u;
+                    const uint32_t live = (0x6u >> st) & 1u;
+                    // branch-free selects: x ^ ((y ^ x) & -flag) picks y when flag is 1
+                    const uint32_t kept = (uint32_t)QUIESC | (w[c] & ~3u), grown = (uint32_t)PROLIF | (older << 2);
+                    uint32_t nl = grown ^ ((kept ^ grown) & (0u - starv));          // live outcome
+                    nl ^= (nl ^ (uint32_t)DEAD) & (0u - nec);
+                    const uint32_t decay = (uint32_t)((st == DEAD) & ((int)older < T_lys));
+                    const uint32_t nd = ((uint32_t)DEAD | (older << 2)) & (0u - decay);  // DEAD ages or lyses
+                    w[c] = nd ^ ((nl ^ nd) & (0u - live));
+                    empty_m |= (uint32_t)(st == EMPTY) << idx;
+                    cyc_m |= (live & ~(nec | starv) & 1u) << idx;
+                    old_m |= (uint32_t)((int)age >= T_min) << idx;
+                    alive_m |= (live & ~nec & 1u) << idx;
+                    asm volatile("" : "+v"(empty_m), "+v"(cyc_m), "+v"(old_m), "+v"(alive_m));
+                }
+                store_words<CPL>(cellp + i * L, w);
+            }
+        }
+        constexpr uint32_t C0 = G::COL_FIRST, CL = G::COL_LAST;
+        const uint32_t fN = ((empty_m << CPL) | top) & ALL_SITES;
+        const uint32_t fS = (empty_m >> CPL) | (bot << ((RPT - 1) * CPL));
+        const uint32_t from_left = lane_from_left_u32(empty_m), from_right = lane_from_right_u32(empty_m);
+        const uint32_t fW = (CPL == 1) ? from_left : (((empty_m << 1) & ~C0 & ALL_SITES) | ((from_left >> (CPL - 1)) & C0));
+        const uint32_t fE = (CPL == 1) ? from_right : (((empty_m >> 1) & ~CL) | ((from_right << (CPL - 1)) & CL));
+        const uint32_t cand = cyc_m & old_m & (fN | fE | fS | fW);
+        uint32_t prop_m = 0;
+        uint64_t dirs = 0;
+        {
+            uint32_t m = cand;
+            while (m) {
+                const int idx = __builtin_ctz(m);
+                m &= m - 1;
+                const int site = own + (idx / CPL) * L + idx % CPL;
+                const Block4 b = philox10(site + gofs, n, r, p, seed_lo, seed_hi);
+                if (b.w3 < s_k.T_div) {
+                    const uint32_t fm = ((fN >> idx) & 1u) | (((fE >> idx) & 1u) << 1) |
+                                        (((fS >> idx) & 1u) << 2) | (((fW >> idx) & 1u) << 3);
+                    const uint32_t kth = (uint32_t)(((uint64_t)b.w0 * __builtin_popcount(fm)) >> 32);
+                    uint32_t rest = fm;
+                    for (uint32_t j = 0; j < kth; ++j) rest &= rest - 1;
+                    const uint32_t dir = __builtin_ctz(rest);                 // 0 N, 1 E, 2 S, 3 W
+                    const int t = site + (dir == 0 ? -L : dir == 1 ? 1 : dir == 2 ? L : -1);
+                    atomicMin(&best[t], ((b.w2 >> 3) << 2) | ((dir + 2) & 3u));
+                    atomicOr(&s_claim[t >> 5], 1u << (t & 31));
+                    prop_m |= 1u << idx;
+                    dirs |= (uint64_t)dir << (2 * idx);
+                }
+            }
+        }
+        __syncthreads();   // all claims are in
+        uint32_t won_m = 0;
+        {
+            uint32_t m = prop_m;
+            while (m) {
+                const int idx = __builtin_ctz(m);
+                m &= m - 1;
+                const uint32_t dir = (uint32_t)(dirs >> (2 * idx)) & 3u;
+                const int site = own + (idx / CPL) * L + idx % CPL;
+                const int t = site + (dir == 0 ? -L : dir == 1 ? 1 : dir == 2 ? L : -1);
+                if ((best[t] & 3u) == ((dir + 2) & 3u)) won_m |= 1u << idx;
+            }
+        }
+        uint32_t born_m = 0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            born_m |= ((s_claim[(own >> 5) + i * (L / 32)] >> (x0 & 31)) & ((1u << CPL) - 1u)) << (i * CPL);
+        }
+        born_m &= empty_m;
+        {
+            uint32_t m = born_m | won_m;             // daughters and winning parents restart at age 0
+            while (m) {
+                const int idx = __builtin_ctz(m);
+                m &= m - 1;
+                cellp[(idx / CPL) * L + idx % CPL] = (uint16_t)PROLIF;
+            }
+        }
+        uint32_t counted = alive_m | born_m;
+        if constexpr (SLAB) {                      // a slab counts its own rows only
+            uint32_t own_rows = 0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                own_rows |= (uint32_t)(y0 + i >= iy0 && y0 + i < iy1) * (((1u << CPL) - 1u) << (i * CPL));
+            counted &= own_rows;
+        }
+        int live = __builtin_popcount(counted);
+        // (5) live count: wave reduction, one LDS atomic per wave
+        live = wave_sum(live);
+        if (lane == 0) atomicAdd(&s_count[n & 1], live);
+        __syncthreads();
+        if (tid == 0) {
+            count = s_count[n & 1];
+            s_count[(n + 1) & 1] = 0;
+            if (!SLAB && a.traj) a.traj[(size_t)inst * a.nsteps + (n - a.n0)] = count;
+        }
+    }
+
+    if (!SLAB && nsteps == 0) {
+        int live = 0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int st = s_cell[(y0 + i) * L + x0 + c] & 3;
+                live += (st == PROLIF || st == QUIESC);
+            }
+        live = wave_sum(live);
+        if (lane == 0) atomicAdd(&s_count[0], live);
+        __syncthreads();
+        if (tid == 0) count = s_count[0];
+    }
+    if constexpr (SLAB) {
+        // the instance's last step: add this slab's share of the live count
+        if (tid == 0 && a.live && a.n0 + 1 == (a.horizon ? a.horizon[p] : a.count_at)) atomicAdd(&a.live[inst], count);
+    } else {
+        if (tid == 0 && a.live) a.live[inst] = count;
+    }
+
+    if (SLAB || (a.mode & MODE_STORE)) {
+        // slabs write their own rows into the other state buffer
+        float* dst = (SLAB ? a.fields_out : a.fields) + (size_t)slot * 3 * plane + gofs;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                if (!SLAB || (y0 + i >= iy0 && y0 + i < iy1))
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c)
+                        dst[f * plane + (size_t)(y0 + i) * L + x0 + c] = F[f][i][c];
+        __syncthreads();
+        uint16_t* cd = (SLAB ? a.cells_out : a.cells) + (size_t)slot * plane + gofs;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i)
+            if (!SLAB || (y0 + i >= iy0 && y0 + i < iy1))
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    cd[(size_t)(y0 + i) * L + x0 + c] = s_cell[(y0 + i) * L + x0 + c];
+    }
+}
+
+}  // namespace
+}  // namespace gga

@@ -1,0 +1,118 @@
+// Slab variants of the simulation kernel (see sim_kernel.h) for lattices whose
+// state does not fit one compute unit, and the two kernels that prepare them:
+// the per-protocol event table and the initial state in device memory.
+#include "sim_kernel.h"
+
+namespace gga {
+namespace {
+
+// Per protocol: validity (the resident kernel's rules), and the step and class
+// survival thresholds of every positive-dose fraction, in order.
+__global__ void event_table_kernel(SimArgs a, int P, int32_t* valid_out, int32_t* count_out, int32_t* step_out,
+                                   uint32_t* thr_out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int k = a.nfrac[p];
+    int valid = (k >= 0 && k <= a.K);
+    int nev = 0;
+    double total = 0.0;
+    long long t = 0;
+    for (int j = 0; valid && j < k; ++j) {
+        const float d = a.dose[(size_t)p * a.K + j];
+        const int g = a.gap[(size_t)p * a.K + j];
+        if (!(d >= 0.0f) || !isfinite(d)) { valid = 0; break; }
+        if (g < (j == 0 ? 0 : 1)) { valid = 0; break; }
+        total += (double)d;
+        t += g;
+        if (d > 0.0f) {
+            step_out[(size_t)p * a.K + nev] = t > 0x7FFFFFFFll ? 0x7FFFFFFF : (int)t;
+            for (int c = 0; c < 4; ++c)
+                thr_out[((size_t)p * a.K + nev) * 4 + c] = lq_threshold((double)d, a.prm.m[c], a.prm.alpha, a.prm.beta);
+            ++nev;
+        }
+    }
+    if (valid && total > a.dose_cap + 1e-6) valid = 0;
+    valid_out[p] = valid;
+    count_out[p] = valid ? nev : 0;
+}
+
+__global__ void slab_live_kernel(SimArgs a, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int inst = a.inst_list ? a.inst_list[k] : k;
+    a.live[inst] = a.ev_valid[inst / a.R] ? 0 : -1;
+}
+
+// Initial state (seed disc of radius seed_radius at L/2 with Philox ages,
+// uniform fields) of state rows 0 .. n-1; one thread per site.
+__global__ void slab_init_kernel(SimArgs a, int L, int n, float* fields, uint16_t* cells) {
+    const size_t plane = (size_t)L * L;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= plane * n) return;
+    const int k = (int)(i / plane);
+    const int site = (int)(i - (size_t)k * plane);
+    const int inst = a.inst_list ? a.inst_list[k] : k;
+    const int p = inst / a.R, r = inst - p * a.R;
+    uint32_t k0 = a.seed_lo, k1 = a.seed_hi;
+    if (a.generation) {
+        const uint64_t key = a.seed + (uint64_t)(uint32_t)*a.generation * 0x9E3779B97F4A7C15ull;
+        k0 = (uint32_t)key;
+        k1 = (uint32_t)(key >> 32);
+    }
+    for (int f = 0; f < 3; ++f) fields[(size_t)k * 3 * plane + f * plane + site] = a.prm.init[f];
+    const int y = site / L, x = site - y * L, ctr = L / 2;
+    uint16_t w = 0;
+    if ((x - ctr) * (x - ctr) + (y - ctr) * (y - ctr) <= a.prm.seed_radius * a.prm.seed_radius) {
+        const Block4 b = philox10((uint32_t)site, INIT_STEP, (uint32_t)r, (uint32_t)p, k0, k1);
+        const uint32_t age = (uint32_t)(((uint64_t)b.w0 * (uint32_t)a.prm.A0) >> 32);
+        w = (uint16_t)(PROLIF | (age << 2));
+        if ((a.horizon ? a.horizon[p] : a.count_at) == 0 && a.ev_valid[p] && a.live) atomicAdd(&a.live[inst], 1);
+    }
+    cells[(size_t)k * plane + site] = w;
+}
+
+template <int CPL, int RPT, int NW>
+hipError_t launch_slab(const SimArgs& a, int n_blocks, hipStream_t stream) {
+    using G = Geo<CPL, RPT, NW>;
+    static_assert(G::SLAB, "resident variants are built in sim.hip");
+    hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_slab_variant(int v, const SimArgs& a, int n_blocks, hipStream_t stream) {
+    if (n_blocks <= 0) return hipSuccess;
+    switch (v) {
+        case 1: return launch_slab<1, 2, 16>(a, n_blocks, stream);
+        case 4: return launch_slab<2, 4, 16>(a, n_blocks, stream);
+        case 5: return launch_slab<4, 4, 16>(a, n_blocks, stream);
+        case 6: return launch_slab<4, 8, 8>(a, n_blocks, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_event_table(const SimArgs& a, int P, int32_t* valid, int32_t* count, int32_t* step,
+                              uint32_t* thr, hipStream_t stream) {
+    if (P <= 0) return hipSuccess;
+    hipLaunchKernelGGL(event_table_kernel, dim3((P + 127) / 128), dim3(128), 0, stream, a, P, valid, count, step, thr);
+    return hipGetLastError();
+}
+
+hipError_t launch_slab_live(const SimArgs& a, int n, hipStream_t stream) {
+    if (n <= 0 || !a.live) return hipSuccess;
+    hipLaunchKernelGGL(slab_live_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_slab_init(const SimArgs& a, int L, int n, float* fields, uint16_t* cells, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const hipError_t e = launch_slab_live(a, n, stream);
+    if (e != hipSuccess) return e;
+    const size_t sites = (size_t)L * L * n;
+    hipLaunchKernelGGL(slab_init_kernel, dim3((unsigned)((sites + 255) / 256)), dim3(256), 0, stream, a, L, n, fields,
+                       cells);
+    return hipGetLastError();
+}
+
+}  // namespace gga

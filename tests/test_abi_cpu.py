@@ -28,7 +28,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(gga):
     names = declared_functions()
-    assert len(names) == 26
+    assert len(names) == 38
     for n in names:
         assert hasattr(gga.LIB, n), n
     assert set(names) == set(gga.EXPORTS)
@@ -116,3 +116,64 @@ def test_mlp_layout_matches_library(gga):
     for k in (128, 512, 512):
         total += 2 * gga._align256(2 * k * 512)
     assert gga.LIB.gga_mlp_net_bytes() == total
+
+
+def test_variant_table_and_choices(gga):
+    vs = gga.variants()
+    assert [v[1] for v in vs] == [64, 64, 128, 128, 128, 256, 256]
+    assert [v[2] for v in vs] == [False, True, False, False, True, True, True]
+    assert gga.get_variant(64) == 0 and gga.get_variant(128) == 2 and gga.get_variant(256) == 5
+    assert gga.get_variant(128, resident_only=True) == 2
+    with pytest.raises(gga.GGAError):
+        gga.get_variant(256, resident_only=True)            # no resident form for 256
+    with pytest.raises(gga.GGAError):
+        gga.set_variant(64, 2)                               # a variant of another side
+    gga.set_variant(128, 4)
+    assert gga.get_variant(128) == 4 and gga.get_variant(128, resident_only=True) == 2
+    gga.set_variant(128, 3)
+    assert gga.get_variant(128) == 3 and gga.get_variant(128, resident_only=True) == 3
+    gga.set_variant(128, 2)
+    assert gga.LIB.gga_variant_side(99) == -1 and gga.LIB.gga_variant_is_slab(-1) == -1
+
+
+def _uneven_bytes(gga, lattice, horizon, K, R):
+    lat = np.ascontiguousarray(lattice, np.int32)
+    hor = np.ascontiguousarray(horizon, np.int32)
+    return gga.LIB.gga_uneven_workspace_bytes(lat.ctypes.data_as(ctypes.c_void_p), hor.ctypes.data_as(ctypes.c_void_p),
+                                              len(lat), K, R)
+
+
+def test_uneven_workspace_holds_two_states_per_slab_instance(gga):
+    state = 256 * 256 * 14                                   # 3 float fields + one uint16 word per site
+    small = _uneven_bytes(gga, [64, 128, 64], [10, 20, 30], 8, 4)
+    big = _uneven_bytes(gga, [64, 128, 256], [10, 20, 30], 8, 4)
+    assert 0 < small < 1 << 20
+    assert big - small >= 2 * 4 * state - (1 << 20) and big >= 2 * 4 * state
+    # a slab choice for 128 needs state buffers too
+    gga.set_variant(128, 4)
+    try:
+        assert _uneven_bytes(gga, [64, 128, 64], [10, 20, 30], 8, 4) >= 2 * 4 * 128 * 128 * 14
+    finally:
+        gga.set_variant(128, 2)
+    assert _uneven_bytes(gga, [64, 96], [10, 10], 8, 1) == 0     # unsupported side
+    assert _uneven_bytes(gga, [64, 64], [10, -1], 8, 1) == 0     # negative horizon
+
+
+def test_uneven_argument_errors_before_any_launch(gga):
+    p = gga.make_params(gga.load_model())
+    cfg = gga.make_cfg(64, 0, 1)
+    fake = ctypes.c_void_p(0x1000)
+    lat = np.array([64, 96], np.int32)
+    hor = np.array([5, 5], np.int32)
+    rc = gga.LIB.gga_simulate_uneven(ctypes.byref(p), ctypes.byref(cfg), fake, fake, fake, 2, 1,
+                                     lat.ctypes.data_as(ctypes.c_void_p), hor.ctypes.data_as(ctypes.c_void_p),
+                                     fake, 1 << 30, fake, fake, None)
+    assert rc == -3
+    lat[1] = 64
+    rc = gga.LIB.gga_simulate_uneven(ctypes.byref(p), ctypes.byref(cfg), fake, fake, fake, 2, 1,
+                                     lat.ctypes.data_as(ctypes.c_void_p), hor.ctypes.data_as(ctypes.c_void_p),
+                                     fake, 16, fake, fake, None)
+    assert rc == -1                                           # workspace too small
+    rc = gga.LIB.gga_state_run_variant(ctypes.byref(p), ctypes.byref(cfg), 5, fake, fake, fake, 2, 1, 0, 1,
+                                       fake, fake, fake, fake, fake, 1 << 20, fake, None)
+    assert rc == -1                                           # a 256 variant on a 64 lattice

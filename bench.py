@@ -251,12 +251,66 @@ def surrogate_bench(gga, workloads, md, args):
     }
 
 
+def uneven_bench(gga, workloads, md, args):
+    """The uneven batch: 8192 protocols x 8 replicas, lattice side 64, 128 or
+    256 and horizon 10-40 days per protocol, 3-40 fractions.  The autotuner
+    first picks each side's kernel variant on a sample (256 protocols x 4
+    replicas, 48 steps); then whole gga_simulate_uneven calls are timed."""
+    import torch
+    wl = dict(workloads.CONFIG3)
+    P, K, R = wl["P"], wl["K"], wl["R"]
+    alpha = gga.make_alphabet(wl["dose_quantum"], wl["dose_q"], wl["gaps"], wl["kmin"], K, wl["dose_cap"])
+    params = gga.make_params(md)
+    dose, gap, nfrac = gga.population_random(alpha, P, K, seed=3)
+    lattice, horizon = workloads.config3_shapes(P, seed=wl["seed"], sides=wl["sides"], days=wl["days"])
+    tuning = {}
+    for L in wl["sides"]:
+        t0 = time.perf_counter()
+        cfg_t = gga.make_cfg(L, 48, 4, seed=1, substeps=wl["substeps"], dose_cap=wl["dose_cap"])
+        v, ms = gga.autotune(params, cfg_t, dose[:256].contiguous(), gap[:256].contiguous(), nfrac[:256].contiguous())
+        tuning[L] = {"variant": gga.variants()[v][3], "ms": {gga.variants()[i][3]: t for i, t in ms.items()}}
+        log(f"autotune L={L}: {tuning[L]['variant']} in {time.perf_counter() - t0:.1f} s ({ms})")
+    cfg = gga.make_cfg(64, 0, R, seed=wl["seed"], substeps=wl["substeps"], dose_cap=wl["dose_cap"])
+    ws = gga.uneven_workspace(lattice, horizon, P, K, R)
+    out = (torch.empty((P, R), dtype=torch.int32, device="cuda"), torch.empty((P,), dtype=torch.float32, device="cuda"))
+    for i in range(args.warmup):
+        gga.simulate_uneven(params, cfg, dose, gap, nfrac, lattice, horizon, ws=ws, out=out)
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        gga.simulate_uneven(params, cfg, dose, gap, nfrac, lattice, horizon, ws=ws, out=out)
+        torch.cuda.synchronize()
+        log(f"step {i + 1}/{args.steps} done at {time.perf_counter() - t0:.1f} s")
+    wall = time.perf_counter() - t0
+    live = out[0].cpu().numpy()
+    assert np.all(live >= 0)
+    site_steps = float(np.sum(lattice.astype(np.float64) ** 2 * horizon) * R)
+    s = wall / args.steps
+    return {
+        "metric": "protocols/sec (uneven batch: 8192 protocols x 8 replicas, sides 64-256, 10-40 days)",
+        "value": P / s, "unit": "protocols/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * s, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl["name"], "protocols": P, "replicas": R, "sides": list(wl["sides"]),
+                   "days": list(wl["days"]), "fractions": [wl["kmin"], K], "dose_cap_gy": wl["dose_cap"],
+                   "instances_per_side": {int(L): int(np.sum(lattice == L)) * R for L in wl["sides"]}},
+        "site_steps_per_s": site_steps / s,
+        "valu_op_rate": {"achieved": OPS_PER_SITE_SUBSTEP * site_steps * wl["substeps"] / s / 1e12,
+                         "peak": VALU_PEAK_OPS / 1e12, "unit": "Top/s",
+                         "frac": OPS_PER_SITE_SUBSTEP * site_steps * wl["substeps"] / s / VALU_PEAK_OPS},
+        "tuning": tuning,
+        "mean_fitness": float(np.nanmean(out[1].cpu().numpy())),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "ga", "surrogate"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "ga", "surrogate", "uneven"])
     ap.add_argument("--generations", type=int, default=200, help="GA workload: generations")
     ap.add_argument("--chunk", type=int, default=20, help="GA workload: generations per progress line")
     ap.add_argument("--candidates", type=int, default=5000, help="surrogate workload: candidates per generation")
@@ -288,6 +342,9 @@ def main():
     md = gga.load_model()
     if args.workload == "ga":
         print(json.dumps(ga_bench(gga, workloads, md, args)), flush=True)
+        return
+    if args.workload == "uneven":
+        print(json.dumps(uneven_bench(gga, workloads, md, args)), flush=True)
         return
     if args.workload == "surrogate":
         print(json.dumps(surrogate_bench(gga, workloads, md, args)), flush=True)

@@ -40,6 +40,9 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "gga_device.h"
 #include "gga_internal.h"
 
@@ -112,6 +115,16 @@ __device__ __forceinline__ void store_keys(uint32_t* p, const uint32_t (&k)[CPL]
 // the whole lattice (resident).  RR < L: a slab of a larger lattice advanced by
 // one step per launch (the rows within `substeps + 2` of a slab edge that is
 // not a lattice edge are a halo, recomputed by the neighbouring slab).
+// Register slot of row i after k sub-steps of a rotating chunk (S = RPT + 1 slots).
+template <int S>
+constexpr int rot_slot(int i, int k) { return ((i - k) % S + S) % S; }
+
+// fn(integral_constant<int, K>) for K = 0, 1, ..., in order, at compile time
+template <int... Ks, class Fn>
+__device__ __forceinline__ void for_each_index(std::integer_sequence<int, Ks...>, Fn&& fn) {
+    (fn(std::integral_constant<int, Ks>{}), ...);
+}
+
 template <int CPL, int RPT, int NW>
 struct Geo {
     static constexpr int L = 64 * CPL;
@@ -252,7 +265,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     }
 
     // ---- state: fields in registers, cells in LDS ----
-    float F[3][RPT][CPL];
+    float F[3][RPT + 1][CPL];                  // slot RPT: spare row for the rotating sub-steps
     const size_t plane = (size_t)L * L;
     if (SLAB || (a.mode & MODE_LOAD)) {
         const float* src = a.fields + (size_t)slot * 3 * plane + gofs;
@@ -371,8 +384,14 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                 Ro[i][c] = fmaf(kap[0], act, edge ? lam[0] * gst[0] : 0.0f);
             }
 
-        // (3) diffusion sub-steps
-        for (int s = 0; s < a.substeps; ++s) {
+        // (3) diffusion sub-steps.  Within a chunk of RPT + 1 sub-steps the rows
+        // rotate through the RPT + 1 register slots: new row i is written over
+        // old row i - 1, which row i was the last to read, so no row is copied,
+        // and after the chunk every row is back in its own slot.  Leftover
+        // sub-steps run one at a time with a copy of the row above.
+        // Per field and column: the halo rows of this wave's neighbours, then
+        // c' = lam (up + below + west + east) + (c cen + r).
+        auto halo = [&](auto slot0, auto slotL, int par, float (&up)[3][CPL], float (&dn)[3][CPL]) {
             // Keep the glucose / acid terms from being hoisted out of the loop
             // (they would cost two live VGPRs per site): Ro is opaque here.
 #pragma unroll
@@ -380,16 +399,15 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) asm volatile("" : "+v"(Ro[i][c]));
             // this wave's halo block: [top/bottom][field][L] at wave * 6 L
-            float* const hw = reinterpret_cast<float*>(s_pool) + (G::NBUF == 2 ? (s & 1) * G::HALO : 0) + wave * 6 * L + x0;
+            float* const hw = reinterpret_cast<float*>(s_pool) + (G::NBUF == 2 ? par * G::HALO : 0) + wave * 6 * L + x0;
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
-                    hw[f * L + c] = F[f][0][c];
-                    hw[(3 + f) * L + c] = F[f][RPT - 1][c];
+                    hw[f * L + c] = F[f][decltype(slot0)::value][c];
+                    hw[(3 + f) * L + c] = F[f][decltype(slotL)::value][c];
                 }
             __syncthreads();
-            float up[3][CPL], dn[3][CPL];
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
@@ -398,6 +416,45 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                     dn[f][c] = (wave < NWAVE - 1) ? hw[(6 + f) * L + c] : gst[f];    // top row of wave+1
                 }
             if constexpr (G::NBUF == 1) __syncthreads();   // one buffer: all reads before the next writes
+        };
+        auto update = [&](int f, int i, int c, float up, float below, float west, float east, float cur) {
+            const float sum = (up + below) + (west + east);
+            const float rx = (f == 0) ? Ro[i][c] : fmaf(rho[f], Ro[i][c], eoff[f][c]);
+            float v = fmaf(lam[f], sum, fmaf(cur, cen[f], rx));
+            if (f < 2) v = fmaxf(v, 0.0f);
+            return v;
+        };
+        auto rotating_substep = [&](auto KC, int par) {
+            constexpr int k = decltype(KC)::value;
+            // sub-steps stay in order: no work moves across this point
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int j = 0; j <= RPT; ++j)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) asm volatile("" : "+v"(F[f][j][c]));
+            float up[3][CPL], dn[3][CPL];
+            halo(std::integral_constant<int, rot_slot<RPT + 1>(0, k)>{},
+                 std::integral_constant<int, rot_slot<RPT + 1>(RPT - 1, k)>{}, par, up, dn);
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int si = rot_slot<RPT + 1>(i, k), sa = rot_slot<RPT + 1>(i - 1, k);
+#pragma unroll
+                for (int f = 0; f < 3; ++f)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const float above = (i == 0) ? up[f][c] : F[f][sa][c];
+                        const float below = (i < RPT - 1) ? F[f][rot_slot<RPT + 1>(i + 1, k)][c] : dn[f][c];
+                        const float west = (c > 0) ? F[f][si][c - 1] : lane_from_left(F[f][si][CPL - 1]);
+                        const float east = (c < CPL - 1) ? F[f][si][c + 1] : lane_from_right(F[f][si][0]);
+                        // old row i - 1 (slot sa) is dead once row i has read it
+                        F[f][sa][c] = update(f, i, c, above, below, west, east, F[f][si][c]);
+                    }
+            }
+        };
+        auto plain_substep = [&](int par) {
+            float up[3][CPL], dn[3][CPL];
+            halo(std::integral_constant<int, 0>{}, std::integral_constant<int, RPT - 1>{}, par, up, dn);
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
                 float nw[3][CPL];
@@ -408,11 +465,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                         const float below = (i < RPT - 1) ? F[f][i + 1][c] : dn[f][c];
                         const float west = (c > 0) ? F[f][i][c - 1] : lane_from_left(F[f][i][CPL - 1]);
                         const float east = (c < CPL - 1) ? F[f][i][c + 1] : lane_from_right(F[f][i][0]);
-                        const float sum = (up[f][c] + below) + (west + east);
-                        const float rx = (f == 0) ? Ro[i][c] : fmaf(rho[f], Ro[i][c], eoff[f][c]);
-                        float v = fmaf(lam[f], sum, fmaf(F[f][i][c], cen[f], rx));
-                        if (f < 2) v = fmaxf(v, 0.0f);
-                        nw[f][c] = v;
+                        nw[f][c] = update(f, i, c, up[f][c], below, west, east, F[f][i][c]);
                     }
 #pragma unroll
                 for (int f = 0; f < 3; ++f)
@@ -422,7 +475,13 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                         F[f][i][c] = nw[f][c];
                     }
             }
-        }
+        };
+        int s = 0;
+        for (; s + RPT + 1 <= a.substeps; s += RPT + 1)
+            for_each_index(std::make_integer_sequence<int, RPT + 1>{}, [&](auto KC) {
+                rotating_substep(KC, (s + decltype(KC)::value) & 1);
+            });
+        for (; s < a.substeps; ++s) plain_substep(s & 1);
 
         // Environment flags of every site, taken from the fields right after the
         // sub-steps (x < th  <=>  sign bit of x - th: the difference of two finite

@@ -132,10 +132,15 @@ struct Geo {
     static constexpr int RR = NW * RPT;
     static constexpr bool SLAB = RR < L;
     static constexpr int NT = 64 * NWAVE;
-    static constexpr int HALO = NWAVE * 2 * 3 * L;   // one buffer: [wave][top/bottom][field][L]
-    // halo double buffer when it fits beside the cells and claim bits in LDS
-    static constexpr int NBUF = (RR * L * 2 + 2 * HALO * 4 + RR * L / 8 + 4096 <= 160 * 1024) ? 2 : 1;
-    static constexpr int POOL = (NBUF * HALO > RR * L) ? NBUF * HALO : RR * L;
+    static constexpr int BLK = 2 * 3 * L;             // one wave's halo block: [top/bottom][field][L]
+    // Halo area [ghost][buffer 0: NW blocks][ghost]([buffer 1][ghost]): the ghost
+    // blocks hold the boundary values, so the first and last wave read their
+    // outer neighbour row like every other wave.  Double buffer when it fits
+    // beside the cells and claim bits in LDS.
+    static constexpr int area(int nbuf) { return (nbuf * (NWAVE + 1) + 1) * BLK; }
+    static constexpr int NBUF = (RR * L * 2 + area(2) * 4 + RR * L / 8 + 4096 <= 160 * 1024) ? 2 : 1;
+    static constexpr int AREA = area(NBUF);
+    static constexpr int POOL = (AREA > RR * L) ? AREA : RR * L;
     static_assert(RR <= L && NWAVE <= 16, "workgroup above 1024 threads");
     static_assert(RPT * CPL <= 32, "per-thread site masks are 32 bits wide");
     static constexpr uint32_t ALL = (RPT * CPL == 32) ? 0xFFFFFFFFu : ((1u << (RPT * CPL)) - 1u);
@@ -399,7 +404,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) asm volatile("" : "+v"(Ro[i][c]));
             // this wave's halo block: [top/bottom][field][L] at wave * 6 L
-            float* const hw = reinterpret_cast<float*>(s_pool) + (G::NBUF == 2 ? par * G::HALO : 0) + wave * 6 * L + x0;
+            float* const hw = reinterpret_cast<float*>(s_pool) + ((G::NBUF == 2 ? par * (NWAVE + 1) : 0) + 1 + wave) * G::BLK + x0;
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
@@ -412,8 +417,8 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             for (int f = 0; f < 3; ++f)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
-                    up[f][c] = (wave > 0) ? hw[(f - 3) * L + c] : gst[f];            // bottom row of wave-1
-                    dn[f][c] = (wave < NWAVE - 1) ? hw[(6 + f) * L + c] : gst[f];    // top row of wave+1
+                    up[f][c] = hw[(f - 3) * L + c];     // bottom row of wave-1 (or a ghost block)
+                    dn[f][c] = hw[(6 + f) * L + c];     // top row of wave+1 (or a ghost block)
                 }
             if constexpr (G::NBUF == 1) __syncthreads();   // one buffer: all reads before the next writes
         };
@@ -476,6 +481,12 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                     }
             }
         };
+        // ghost blocks (the cell update's claim slots share this memory); the
+        // first sub-step's barrier orders these writes before any read
+        for (int k = tid; k < (G::NBUF + 1) * G::BLK; k += G::NT) {
+            const int blk = k / G::BLK, off = k - blk * G::BLK;
+            reinterpret_cast<float*>(s_pool)[blk * (NWAVE + 1) * G::BLK + off] = gst[(off / L) % 3];
+        }
         int s = 0;
         for (; s + RPT + 1 <= a.substeps; s += RPT + 1)
             for_each_index(std::make_integer_sequence<int, RPT + 1>{}, [&](auto KC) {

@@ -183,13 +183,35 @@ int gga_state_run(const gga_params* params, const gga_sim_cfg* cfg,
                   hipStream_t stream);
 
 /* GA settings.  Set struct_size = sizeof(gga_ga_cfg). */
+/* Operator variants (the paper's appendix on the GA operators describes
+ * simple, roulette and rank-based tournament selection, one-point (cut between
+ * 25 % and 75 %), two-point and uniform crossover, and swap and dose-raising
+ * mutations among others; zero selects the defaults). */
+#define GGA_SEL_TOURNAMENT 0    /* best of k uniform picks                                 */
+#define GGA_SEL_RANK 1          /* j-th best of k picks with probability q (1 - q)^j       */
+#define GGA_SEL_ROULETTE 2      /* proportional to max(roulette_base - fitness, 0)         */
+#define GGA_SEL_TRUNCATION 3    /* uniform over the best floor(trunc_frac N)               */
+#define GGA_X_ONE_POINT 0       /* cut uniform on 1 .. K-1                                  */
+#define GGA_X_MIDDLE 1          /* cut uniform on max(1, K/4) .. min(K-1, 3K/4)             */
+#define GGA_X_TWO_POINT 2       /* genes [c1, c2) exchanged, c1 in K/4..K/2, c2 in K/2..3K/4 */
+#define GGA_X_UNIFORM 3         /* each gene exchanged with probability 1/2                 */
+#define GGA_MUT_GENE 1          /* per gene: dose and delay redrawn with probability p_mut  */
+#define GGA_MUT_SWAP 2          /* per child: two doses exchanged with probability p_mut    */
+#define GGA_MUT_RAISE 4         /* per child: one dose raised (if under the cap), p_mut     */
 typedef struct gga_ga_cfg {
     uint32_t struct_size;
     int32_t n_elite;        /* best protocols copied unchanged, 0 .. N            */
-    int32_t tournament_k;   /* tournament size, 1 .. 64                            */
-    double p_cross;         /* one-point crossover probability, [0, 1]             */
-    double p_mut;           /* per-gene mutation probability (dose, delay), [0, 1] */
+    int32_t tournament_k;   /* picks per tournament (GGA_SEL_TOURNAMENT, _RANK), 1 .. 64 */
+    double p_cross;         /* crossover probability, [0, 1]                       */
+    double p_mut;           /* mutation probability (see GGA_MUT_*), [0, 1]        */
     uint64_t seed;          /* key of the GA's Philox blocks                        */
+    int32_t selection;      /* GGA_SEL_*                                           */
+    int32_t crossover;      /* GGA_X_*                                             */
+    int32_t mutation;       /* GGA_MUT_* bits applied in the order gene, swap, raise; 0 = GGA_MUT_GENE */
+    int32_t reserved;       /* 0                                                   */
+    double q;               /* GGA_SEL_RANK: (0, 1]                                */
+    double trunc_frac;      /* GGA_SEL_TRUNCATION: (0, 1]                          */
+    double roulette_base;   /* GGA_SEL_ROULETTE: finite                            */
 } gga_ga_cfg;
 
 /*

@@ -66,7 +66,15 @@ class GaCfg(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32), ("n_elite", ctypes.c_int32), ("tournament_k", ctypes.c_int32),
         ("p_cross", ctypes.c_double), ("p_mut", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("selection", ctypes.c_int32), ("crossover", ctypes.c_int32), ("mutation", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("q", ctypes.c_double), ("trunc_frac", ctypes.c_double),
+        ("roulette_base", ctypes.c_double),
     ]
+
+
+SELECTIONS = {"tournament": 0, "rank": 1, "roulette": 2, "truncation": 3}
+CROSSOVERS = {"one_point": 0, "middle": 1, "two_point": 2, "uniform": 3}
+MUTATIONS = {"gene": 1, "swap": 2, "raise": 4}
 
 
 def _load():
@@ -390,11 +398,17 @@ def autotune(params, cfg, dose, gap, nfrac, stream=None):
 
 # ---------------------------------------------------------------- GA
 
-def make_ga(n_elite=2, tournament_k=4, p_cross=0.8, p_mut=0.05, seed=0):
+def make_ga(n_elite=2, tournament_k=4, p_cross=0.8, p_mut=0.05, seed=0, selection="tournament",
+            crossover="one_point", mutation=("gene",), q=0.9, trunc_frac=0.4, roulette_base=0.0):
+    """GA settings; selection, crossover and mutation name the operator
+    variants (see GGA_SEL_*, GGA_X_*, GGA_MUT_* in gga.h)."""
     g = GaCfg()
     g.struct_size = ctypes.sizeof(GaCfg)
     g.n_elite, g.tournament_k = int(n_elite), int(tournament_k)
     g.p_cross, g.p_mut, g.seed = float(p_cross), float(p_mut), int(seed)
+    g.selection, g.crossover = SELECTIONS[selection], CROSSOVERS[crossover]
+    g.mutation = sum(MUTATIONS[m] for m in set(mutation))
+    g.q, g.trunc_frac, g.roulette_base = float(q), float(trunc_frac), float(roulette_base)
     return g
 
 

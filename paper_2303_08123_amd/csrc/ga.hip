@@ -2,9 +2,11 @@
 //
 // The paper's loop (Materials and Methods, "The Main GA Loop"; appendix "GA
 // Operators: additional details"): the best protocols are copied unchanged,
-// parents are selected (here a k-way tournament), recombined by crossover (one
-// point), mutated, and repaired by a guard that lowers the largest dose while
-// the total exceeds the cap.  Lower fitness (mean live count) is better.
+// parents are selected (k-way tournament by default; rank-based, roulette or
+// truncation), recombined by crossover (one point by default; middle cut,
+// two-point or uniform), mutated (per gene by default; dose swap, dose raise),
+// and repaired by a guard that lowers the largest dose while the total exceeds
+// the cap.  Lower fitness (mean live count) is better.
 //
 // Kernels: rank (position of each protocol in (fitness, index) order, NaN
 // last), history (best and mean fitness of the generation), offspring (one
@@ -90,9 +92,71 @@ __device__ __forceinline__ uint32_t word_of(const Block4& b, int i) {
     return i == 0 ? b.w0 : i == 1 ? b.w1 : i == 2 ? b.w2 : b.w3;
 }
 
+// Word i of the selection words of one parent (blocks base .. base + nb - 1).
+__device__ __forceinline__ uint32_t sel_word(int c, uint32_t g, int base, int i, const GaArgs& a) {
+    return word_of(ga_words(c, g, (uint32_t)(base + i / 4), a.seed_lo, a.seed_hi), i & 3);
+}
+
+__device__ __forceinline__ int pick_of(uint32_t w, int n) { return (int)(((uint64_t)w * (uint32_t)n) >> 32); }
+
+// One parent (an index into the population) by the configured selection.
+#pragma clang fp contract(off)
+__device__ int select_parent(int c, uint32_t g, int base, const GaArgs& a) {
+    const int N = a.N, k = a.k;
+    if (a.selection == GGA_SEL_TOURNAMENT) {
+        int best = -1, best_pos = 0x7FFFFFFF;
+        for (int i = 0; i < k; ++i) {
+            const int pick = pick_of(sel_word(c, g, base, i, a), N);
+            const int pos = a.position[pick];
+            if (pos < best_pos) { best_pos = pos; best = pick; }
+        }
+        return best;
+    }
+    if (a.selection == GGA_SEL_RANK) {
+        // k picks sorted by rank position (insertion sort), then the j-th best
+        // is taken with probability q (1 - q)^j, the last with the rest
+        int pos[64];
+        for (int i = 0; i < k; ++i) {
+            const int p = a.position[pick_of(sel_word(c, g, base, i, a), N)];
+            int j = i;
+            while (j > 0 && pos[j - 1] > p) { pos[j] = pos[j - 1]; --j; }
+            pos[j] = p;
+        }
+        int take = k - 1;
+        for (int j = 0; j < k - 1; ++j)
+            if (sel_word(c, g, base, k + j, a) < a.t_q) { take = j; break; }
+        return a.order[pos[take]];
+    }
+    const uint32_t w0 = sel_word(c, g, base, 0, a);
+    if (a.selection == GGA_SEL_TRUNCATION) return a.order[pick_of(w0, a.trunc_m)];
+    // roulette over max(base - fitness, 0), sums in index order in float64
+    double total = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const float f = a.fitness[i];
+        total += isnan(f) ? 0.0 : fmax(a.roulette_base - (double)f, 0.0);
+    }
+    if (!(total > 0.0)) return pick_of(w0, N);
+    const double u = ((double)w0 * total) * 2.3283064365386963e-10;   // w0 total / 2^32
+    double run = 0.0;
+    int last = 0;
+    for (int i = 0; i < N; ++i) {
+        const float f = a.fitness[i];
+        const double v = isnan(f) ? 0.0 : fmax(a.roulette_base - (double)f, 0.0);
+        run += v;
+        if (v > 0.0) last = i;
+        if (run > u) return i;
+    }
+    return last;
+}
+#pragma clang fp contract(on)
+
+__device__ __forceinline__ int selection_words(const GaArgs& a) {
+    return a.selection == GGA_SEL_TOURNAMENT ? a.k : a.selection == GGA_SEL_RANK ? 2 * a.k - 1 : 1;
+}
+
 __global__ __launch_bounds__(128) void offspring_kernel(GaArgs a) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int N = a.N, K = a.K;
+    const int K = a.K;
     const uint32_t g = (uint32_t)*a.generation;
     if (t < a.n_elite) {                                   // elites: copied unchanged
         const int src = a.order[t];
@@ -105,36 +169,71 @@ __global__ __launch_bounds__(128) void offspring_kernel(GaArgs a) {
     const int c = t - a.n_elite;                           // child pair
     const int n_pairs = (a.n_out - a.n_elite + 1) / 2;
     if (c < 0 || c >= n_pairs) return;
-    const int nb = (a.k + 3) / 4;
-    int parent[2];
-    for (int side = 0; side < 2; ++side) {
-        int best = -1, best_pos = 0x7FFFFFFF;
-        for (int i = 0; i < a.k; ++i) {
-            const Block4 b = ga_words(c, g, (uint32_t)(side * nb + i / 4), a.seed_lo, a.seed_hi);
-            const int pick = (int)(((uint64_t)word_of(b, i & 3) * (uint32_t)N) >> 32);
-            const int pos = a.position[pick];
-            if (pos < best_pos) { best_pos = pos; best = pick; }
-        }
-        parent[side] = best;
-    }
+    const int nb = (selection_words(a) + 3) / 4;
+    const int parent[2] = {select_parent(c, g, 0, a), select_parent(c, g, nb, a)};
+    // crossover: the genes child 0 takes from parent 1 (bit j), child 1 the complement
+    uint64_t from_b = 0;
     const Block4 bc = ga_words(c, g, (uint32_t)(2 * nb), a.seed_lo, a.seed_hi);
-    int cut = K;                                           // no crossover: children copy the parents
-    if (bc.w0 < a.t_cross && K > 1) cut = 1 + (int)(((uint64_t)bc.w1 * (uint32_t)(K - 1)) >> 32);
+    if (bc.w0 < a.t_cross && K > 1) {
+        const uint64_t all = (K == 64) ? ~0ull : ((1ull << K) - 1ull);
+        if (a.crossover == GGA_X_ONE_POINT || a.crossover == GGA_X_MIDDLE) {
+            int lo = 1, hi = K - 1;
+            if (a.crossover == GGA_X_MIDDLE) {
+                lo = max(1, K / 4);
+                hi = max(lo, min(K - 1, 3 * K / 4));
+            }
+            const int cut = lo + pick_of(bc.w1, hi - lo + 1);
+            from_b = all & ~((1ull << cut) - 1ull);
+        } else if (a.crossover == GGA_X_TWO_POINT) {
+            const int c1 = K / 4 + pick_of(bc.w1, K / 2 - K / 4 + 1);
+            const int c2 = K / 2 + pick_of(bc.w2, 3 * K / 4 - K / 2 + 1);
+            if (c1 < c2) from_b = ((1ull << c2) - 1ull) & ~((1ull << c1) - 1ull);
+        } else {
+            from_b = ((uint64_t)bc.w1 | ((uint64_t)bc.w2 << 32)) & all;
+        }
+    }
     for (int ch = 0; ch < 2; ++ch) {
         const int slot = a.n_elite + 2 * c + ch;
         if (slot >= a.n_out) break;
         int q[GGA_KMAX], gp[GGA_KMAX];
         int total = 0;
         for (int j = 0; j < K; ++j) {
-            const int src = (j < cut) == (ch == 0) ? parent[0] : parent[1];
+            const bool other = ((from_b >> j) & 1ull) != 0;
+            const int src = (other == (ch == 0)) ? parent[1] : parent[0];
             int qd = (int)rintf(a.dose[(size_t)src * K + j] / a.quantum);
             int gg = a.gap[(size_t)src * K + j];
-            const Block4 bm = ga_words(c, g, (uint32_t)(2 * nb + 1 + ch * K + j), a.seed_lo, a.seed_hi);
-            if (bm.w0 < a.t_mut) qd = a.dose_q[(int)(((uint64_t)bm.w1 * (uint32_t)a.n_dose) >> 32)];
-            if (bm.w2 < a.t_mut) gg = a.gaps[(int)(((uint64_t)bm.w3 * (uint32_t)a.n_gap) >> 32)];
+            if (a.mutation & GGA_MUT_GENE) {
+                const Block4 bm = ga_words(c, g, (uint32_t)(2 * nb + 1 + ch * K + j), a.seed_lo, a.seed_hi);
+                if (bm.w0 < a.t_mut) qd = a.dose_q[pick_of(bm.w1, a.n_dose)];
+                if (bm.w2 < a.t_mut) gg = a.gaps[pick_of(bm.w3, a.n_gap)];
+            }
             q[j] = qd;
             gp[j] = gg;
             total += qd;
+        }
+        if ((a.mutation & GGA_MUT_SWAP) && K > 1) {       // two doses exchange places
+            const Block4 bs = ga_words(c, g, (uint32_t)(2 * nb + 1 + 2 * K + 2 * ch), a.seed_lo, a.seed_hi);
+            if (bs.w0 < a.t_mut) {
+                const int i = pick_of(bs.w1, K);
+                int j = pick_of(bs.w2, K - 1);
+                j += (j >= i);
+                const int tmp = q[i];
+                q[i] = q[j];
+                q[j] = tmp;
+            }
+        }
+        if (a.mutation & GGA_MUT_RAISE) {                 // one dose rises to a larger alphabet value
+            const Block4 br = ga_words(c, g, (uint32_t)(2 * nb + 2 + 2 * K + 2 * ch), a.seed_lo, a.seed_hi);
+            if (br.w0 < a.t_mut && total < a.cap_q) {
+                const int i = pick_of(br.w1, K);
+                int first = 0;                             // alphabet doses are increasing
+                while (first < a.n_dose && a.dose_q[first] <= q[i]) ++first;
+                if (first < a.n_dose) {
+                    const int nq = a.dose_q[first + pick_of(br.w2, a.n_dose - first)];
+                    total += nq - q[i];
+                    q[i] = nq;
+                }
+            }
         }
         // guard: the largest dose (first among equals) steps down the alphabet
         while (total > a.cap_q) {

@@ -279,6 +279,12 @@ int check_ga(const gga_ga_cfg* ga, const gga_alphabet* a, int32_t N, int32_t K, 
     if (N < 2 || K < 1 || K > GGA_KMAX) return GGA_E_ARG;
     if (ga->n_elite < 0 || ga->n_elite > N || ga->tournament_k < 1 || ga->tournament_k > 64) return GGA_E_ARG;
     if (!(ga->p_cross >= 0.0 && ga->p_cross <= 1.0) || !(ga->p_mut >= 0.0 && ga->p_mut <= 1.0)) return GGA_E_ARG;
+    if (ga->selection < 0 || ga->selection > 3 || ga->crossover < 0 || ga->crossover > 3 || ga->mutation < 0 ||
+        ga->mutation > 7 || ga->reserved != 0)
+        return GGA_E_ARG;
+    if (ga->selection == GGA_SEL_RANK && !(ga->q > 0.0 && ga->q <= 1.0)) return GGA_E_ARG;
+    if (ga->selection == GGA_SEL_TRUNCATION && !(ga->trunc_frac > 0.0 && ga->trunc_frac <= 1.0)) return GGA_E_ARG;
+    if (ga->selection == GGA_SEL_ROULETTE && !std::isfinite(ga->roulette_base)) return GGA_E_ARG;
     if (a->n_dose < 1 || a->n_dose > GGA_ALPHABET_MAX || a->n_gap < 1 || a->n_gap > GGA_ALPHABET_MAX)
         return GGA_E_ALPHABET;
     if (!(std::isfinite(a->dose_quantum) && a->dose_quantum > 0.0f) || !(std::isfinite(a->cap) && a->cap >= 0.0f))
@@ -300,6 +306,14 @@ int check_ga(const gga_ga_cfg* ga, const gga_alphabet* a, int32_t N, int32_t K, 
     out->cap_q = static_cast<int32_t>(capq);
     out->t_cross = prob_threshold(ga->p_cross);
     out->t_mut = prob_threshold(ga->p_mut);
+    out->selection = ga->selection;
+    out->crossover = ga->crossover;
+    out->mutation = ga->mutation ? ga->mutation : GGA_MUT_GENE;
+    out->t_q = ga->selection == GGA_SEL_RANK ? prob_threshold(ga->q) : 0u;
+    out->trunc_m = ga->selection == GGA_SEL_TRUNCATION
+                       ? std::max(1, std::min(N, static_cast<int>(std::floor(ga->trunc_frac * N))))
+                       : 0;
+    out->roulette_base = ga->roulette_base;
     out->seed_lo = static_cast<uint32_t>(ga->seed);
     out->seed_hi = static_cast<uint32_t>(ga->seed >> 32);
     out->quantum = a->dose_quantum;
@@ -326,6 +340,7 @@ hipError_t enqueue_generation(const gga_params* params, const gga_sim_cfg* cfg, 
     if (e == hipSuccess) e = gga::launch_rank(w.fitness, N, w.order, w.position, stream);
     const gga::Archive arc{dose, gap, K, best_dose, best_gap};
     if (e == hipSuccess) e = gga::launch_history(w.fitness, N, w.order, w.generation, hist, hist_cap, arc, stream);
+    ga_args.fitness = w.fitness;
     ga_args.dose = dose;
     ga_args.gap = gap;
     ga_args.order = w.order;
@@ -403,6 +418,7 @@ int gga_ga_breed(const gga_ga_cfg* ga, const gga_alphabet* a, const float* fitne
         !next_gap_h_d)
         return GGA_E_ARG;
     hipError_t e = gga::launch_rank(fitness_d, N, order_d, position_d, stream);
+    ga_args.fitness = fitness_d;
     ga_args.dose = dose_d;
     ga_args.gap = gap_h_d;
     ga_args.order = order_d;
@@ -720,6 +736,7 @@ hipError_t enqueue_sga(const gga_params* params, const gga_sim_cfg* cfg, gga::Ga
     hipError_t e = gga::launch_rank(pop_fit, N, w.order_p, w.pos_p, stream);
     ga_args.n_elite = 0;
     ga_args.n_out = C;
+    ga_args.fitness = pop_fit;
     ga_args.dose = pop_dose;
     ga_args.gap = pop_gap;
     ga_args.order = w.order_p;

@@ -101,6 +101,10 @@ struct GaArgs {
     int32_t N, K, n_elite, k, n_dose, n_gap, cap_q;
     int32_t n_out;                  // children written: slots n_elite .. n_out-1 (n_out = N for a generation)
     uint32_t t_cross, t_mut, seed_lo, seed_hi;
+    int32_t selection, crossover, mutation, trunc_m;   // operators (GGA_SEL_*, GGA_X_*, GGA_MUT_* bits)
+    uint32_t t_q;
+    double roulette_base;
+    const float* fitness;           // [N], read by roulette selection
     float quantum;
     int32_t dose_q[GGA_ALPHABET_MAX];
     int32_t gaps[GGA_ALPHABET_MAX];

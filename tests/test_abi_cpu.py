@@ -46,6 +46,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(gga_params), sizeof(gga_sim_cfg), sizeof(gga_alphabet),
          offsetof(gga_params, P_div), offsetof(gga_params, m), offsetof(gga_sim_cfg, seed),
          offsetof(gga_alphabet, gaps), sizeof(gga_ga_cfg), offsetof(gga_ga_cfg, seed));
+  printf("%zu %zu %zu\n", offsetof(gga_ga_cfg, selection), offsetof(gga_ga_cfg, q), offsetof(gga_ga_cfg, roulette_base));
   return 0;
 }
 """
@@ -61,7 +62,8 @@ def test_struct_layout_matches_python_mirror(gga, tmp_path):
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert vals == [ctypes.sizeof(gga.Params), ctypes.sizeof(gga.SimCfg), ctypes.sizeof(gga.Alphabet),
                     gga.Params.P_div.offset, gga.Params.m.offset, gga.SimCfg.seed.offset,
-                    gga.Alphabet.gaps.offset, ctypes.sizeof(gga.GaCfg), gga.GaCfg.seed.offset]
+                    gga.Alphabet.gaps.offset, ctypes.sizeof(gga.GaCfg), gga.GaCfg.seed.offset,
+                    gga.GaCfg.selection.offset, gga.GaCfg.q.offset, gga.GaCfg.roulette_base.offset]
 
 
 def test_version_and_errors(gga):

@@ -53,6 +53,32 @@ def test_breed_matches_oracle(gga, N, gen, elite, k, doses):
     assert np.array_equal(ng.cpu().numpy(), rg)
 
 
+@pytest.mark.parametrize("selection,crossover,mutation,k", [
+    ("rank", "middle", ("gene",), 16),
+    ("roulette", "two_point", ("swap",), 1),
+    ("truncation", "uniform", ("raise",), 1),
+    ("tournament", "uniform", ("gene", "swap", "raise"), 4),
+    ("rank", "two_point", ("gene", "raise"), 3),
+])
+def test_breed_variants_match_oracle(gga, selection, crossover, mutation, k):
+    """The paper-style operator variants, bit-exact against the oracle (an
+    odd child count, NaN fitness, parents over the cap)."""
+    N, K, gen, elite = 97, 10, 5, 2
+    dose, gap = _pop(N, K, 31, (1.0, 1.5, 2.0, 2.5))
+    rng = np.random.default_rng(8)
+    fitness = rng.uniform(100, 400, size=N).astype(np.float32)
+    fitness[::17] = np.nan
+    kw = dict(selection=selection, crossover=crossover, mutation=mutation, q=0.7, trunc_frac=0.3,
+              roulette_base=420.0)
+    cfg = gga.make_ga(n_elite=elite, tournament_k=k, p_cross=0.9, p_mut=0.3, seed=1234567, **kw)
+    g_t = torch.tensor([gen], dtype=torch.int32, device="cuda")
+    _, _, nd, ng = gga.ga_breed(cfg, _alphabet(gga), torch.from_numpy(fitness).cuda(),
+                                torch.from_numpy(dose).cuda(), torch.from_numpy(gap).cuda(), g_t)
+    rd, rg = oga.next_generation(dose, gap, fitness, gen, 1234567, ALPHA, elite, k, 0.9, 0.3, **kw)
+    assert np.array_equal(nd.cpu().numpy(), rd)
+    assert np.array_equal(ng.cpu().numpy(), rg)
+
+
 def test_generation_matches_oracle_simulation_and_breeding(gga, model_dict):
     """One whole generation at generation counter 3: the fitness the device
     computes equals the oracle's (short horizon, no near-threshold site), and

@@ -150,3 +150,132 @@ def test_random_screen_generation_invariants(params):
     expect = sorted(range(N + S), key=lambda i: (pool[i][2], i))[:N]
     for row, i in enumerate(expect):
         assert np.array_equal(d[row], pool[i][0]) and np.array_equal(g[row], pool[i][1]) and f[row] == pool[i][2]
+
+
+def _draw_parents(N, K, seed, n_out, **kw):
+    """Children of a population whose rows are all distinct, with crossover and
+    mutation off, so each child names its parent."""
+    rng = np.random.default_rng(seed)
+    dose = np.full((N, K), 0.5, np.float32)
+    gap = np.zeros((N, K), np.int32)
+    for i in range(N):                          # row i spells i in base 10 over the delays
+        gap[i] = [ALPHA["gaps"][(i // 10 ** j) % 10] for j in range(K)]
+    fitness = rng.permutation(N).astype(np.float64)
+    nd, ng = ga.next_generation(dose, gap, fitness, 2, 21, dict(ALPHA, cap=1e6), n_elite=0, p_cross=0.0,
+                                p_mut=0.0, n_out=n_out, **kw)
+    index = {tuple(r): i for i, r in enumerate(gap.tolist())}
+    parents = np.array([index[tuple(r)] for r in ng.tolist()])
+    _, pos = ga.rank_order(fitness)
+    return parents, pos, fitness
+
+
+def _chi2_ok(counts, expect):
+    keep = expect > 5
+    obs, exp = counts[keep], expect[keep]
+    if (~keep).any():
+        obs, exp = np.append(obs, counts[~keep].sum()), np.append(exp, expect[~keep].sum())
+    exp = exp * obs.sum() / exp.sum()
+    return chisquare(obs, exp).pvalue > 1e-3
+
+
+def test_rank_selection_follows_truncated_geometric_over_order_statistics():
+    """The j-th best of k uniform picks is taken with probability q (1-q)^j
+    (the last with the rest): P(rank r) = sum_j P(take j) P(X_(j) = r), with
+    P(X_(j) <= r) = sum_{m > j} C(k, m) p^m (1-p)^(k-m), p = (r + 1) / N."""
+    N, K, k, q = 40, 3, 4, 0.6
+    parents, pos, _ = _draw_parents(N, K, 0, 8000, k=k, selection="rank", q=q)
+    counts = np.bincount(pos[parents], minlength=N).astype(float)
+    take = [q * (1 - q) ** j for j in range(k - 1)] + [(1 - q) ** (k - 1)]
+
+    def cdf(j, r):
+        p = (r + 1) / N
+        return sum(math.comb(k, m) * p ** m * (1 - p) ** (k - m) for m in range(j + 1, k + 1))
+    law = np.array([sum(take[j] * (cdf(j, r) - (cdf(j, r - 1) if r else 0.0)) for j in range(k)) for r in range(N)])
+    assert abs(law.sum() - 1) < 1e-12
+    assert _chi2_ok(counts, law * counts.sum())
+
+
+def test_roulette_selection_is_proportional_to_score():
+    N, K = 30, 3
+    parents, _, fitness = _draw_parents(N, K, 1, 8000, k=1, selection="roulette", roulette_base=25.0)
+    score = np.maximum(25.0 - fitness, 0.0)
+    counts = np.bincount(parents, minlength=N).astype(float)
+    assert counts[score == 0].sum() == 0                  # scores at or below zero are never drawn
+    assert _chi2_ok(counts[score > 0], score[score > 0] / score.sum() * counts.sum())
+
+
+def test_truncation_selection_is_uniform_over_the_best():
+    N, K = 50, 3
+    parents, pos, _ = _draw_parents(N, K, 2, 6000, k=1, selection="truncation", trunc_frac=0.4)
+    counts = np.bincount(pos[parents], minlength=N).astype(float)
+    assert counts[20:].sum() == 0
+    assert _chi2_ok(counts[:20], np.full(20, counts.sum() / 20))
+
+
+@pytest.mark.parametrize("kind", ["middle", "two_point", "uniform"])
+def test_crossover_variants_exchange_genes_between_the_two_parents(kind):
+    N, K = 64, 12
+    dose, gap = _pop(N, K, 5)
+    gap = (np.arange(N * K).reshape(N, K) % 997 + 1).astype(np.int32)      # every gene distinct
+    fitness = np.arange(N, dtype=np.float64)
+    nd, ng = ga.next_generation(dose, gap, fitness, 0, 8, dict(ALPHA, cap=1e6), n_elite=0, k=1, p_cross=1.0,
+                                p_mut=0.0, crossover=kind)
+    where = {v: divmod(i, K) for i, v in enumerate(gap.ravel().tolist())}
+    cuts, exchanged = [], []
+    for c in range(N // 2):
+        src = [[where[v] for v in ng[2 * c + h]] for h in (0, 1)]
+        assert all(j == jj for h in (0, 1) for jj, (_, j) in enumerate(src[h]))   # genes keep their position
+        a = src[0][0][0] if kind != "uniform" else None
+        rows0 = [p for p, _ in src[0]]
+        rows1 = [p for p, _ in src[1]]
+        pa, pb = sorted(set(rows0 + rows1))[0], sorted(set(rows0 + rows1))[-1]
+        assert set(rows0 + rows1) <= {pa, pb}
+        assert all({x, y} == {pa, pb} or pa == pb for x, y in zip(rows0, rows1))   # complementary children
+        if kind == "middle" and pa != pb:
+            cut = next(j for j in range(1, K) if rows0[j] != rows0[0])
+            assert all(r == rows0[0] for r in rows0[:cut]) and all(r != rows0[0] for r in rows0[cut:])
+            cuts.append(cut)
+        if kind == "two_point" and pa != pb:
+            inside = [j for j in range(K) if rows0[j] != a]
+            if inside:
+                c1, c2 = inside[0], inside[-1] + 1
+                assert inside == list(range(c1, c2)) and K // 4 <= c1 <= K // 2 and K // 2 <= c2 <= 3 * K // 4
+        if kind == "uniform" and pa != pb:
+            exchanged.append(np.mean([r != rows0[0] for r in rows0]))
+    if kind == "middle":
+        assert min(cuts) >= K // 4 and max(cuts) <= 3 * K // 4 and len(set(cuts)) == 3 * K // 4 - K // 4 + 1
+    if kind == "uniform":
+        assert abs(np.mean(exchanged) - 0.5) < 0.1
+
+
+def test_swap_mutation_exchanges_two_doses():
+    N, K = 60, 8
+    rng = np.random.default_rng(6)
+    dose = rng.choice([0.5, 1.0, 1.5, 2.0, 2.5], size=(N, K)).astype(np.float32)
+    gap = np.tile((np.arange(N)[:, None] % 10 + 1) * 6, (1, K)).astype(np.int32)  # delays name the parent
+    nd, ng = ga.next_generation(dose, gap, np.zeros(N), 1, 4, dict(ALPHA, cap=1e6), n_elite=0, k=1, p_cross=0.0,
+                                p_mut=1.0, mutation=("swap",))
+    swapped = 0
+    for c in range(N // 2):
+        for t, ch in ((0, 2 * c), (1, 2 * c + 1)):
+            src = (ga._words(c, 1, t, 4)[0] * N) >> 32
+            assert np.array_equal(ng[ch], gap[src])
+            diff = np.nonzero(nd[ch] != dose[src])[0]
+            assert len(diff) in (0, 2) and sorted(nd[ch]) == sorted(dose[src])
+            swapped += len(diff) == 2
+    assert swapped > N // 2
+
+
+def test_raise_mutation_lifts_one_dose_then_the_guard_holds_the_cap():
+    N, K = 60, 8
+    dose = np.full((N, K), 1.0, np.float32)
+    gap = np.full((N, K), 12, np.int32)
+    nd, _ = ga.next_generation(dose, gap, np.zeros(N), 3, 9, dict(ALPHA, cap=1e6), n_elite=0, k=1, p_cross=0.0,
+                               p_mut=1.0, mutation=("raise",))
+    for row in nd:
+        up = np.nonzero(row != 1.0)[0]
+        assert len(up) == 1 and row[up[0]] in (1.5, 2.0, 2.5)
+    tight = dict(ALPHA, cap=8.5)
+    nd, _ = ga.next_generation(dose, gap, np.zeros(N), 3, 9, tight, n_elite=0, k=1, p_cross=0.0, p_mut=1.0,
+                               mutation=("raise",))
+    assert np.all(nd.astype(np.float64).sum(1) <= 8.5 + 1e-9) and np.any(nd > 1.0)

@@ -390,6 +390,21 @@ int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_c
                 int32_t* best_gap_d, float* gen_ms_h, hipStream_t stream);
 
 /*
+ * gga_simulate from a library of pre-grown tumours instead of the seed disc
+ * (Materials and Methods, "The tumour case library": protocols are evaluated
+ * on tumours grown beforehand without treatment).  Replica r of every
+ * protocol starts from library state r mod n_lib: lib_fields_d[n_lib][3][L][L]
+ * (f32) and lib_cells_d[n_lib][L][L] (u16 words), for example states grown by
+ * gga_state_init and gga_state_run; the library is read, never written.
+ * Treatment steps count from 0; Philox counters as gga_simulate.
+ * Errors: as gga_simulate; GGA_E_ARG for n_lib < 1.
+ */
+int gga_simulate_library(const gga_params* params, const gga_sim_cfg* cfg, const float* dose_d,
+                         const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P, int32_t K,
+                         const float* lib_fields_d, const uint16_t* lib_cells_d, int32_t n_lib, int32_t* live_d,
+                         float* fitness_d, hipStream_t stream);
+
+/*
  * Philox4x32-10 blocks (Salmon et al., SC'11) from the device implementation
  * the simulator uses: out_d[i][0..3] = Philox(counter ctr_d[i][0..3], key
  * (seed lo, seed hi)) for i < n.  A test hook.

@@ -80,7 +80,7 @@ MUTATIONS = {"gene": 1, "swap": 2, "raise": 4}
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_2303_08123_amd.build` (hipcc, gfx950)")
+                          "`python paper_2303_08123_amd/build.py` (hipcc, gfx950)")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
     sig = {
@@ -115,6 +115,7 @@ def _load():
                                ctypes.c_int),
         "gga_sga_run": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, ctypes.c_size_t, vp, vp,
                          vp, vp, vp], ctypes.c_int),
+        "gga_simulate_library": ([vp, vp, vp, vp, vp, i32, i32, vp, vp, i32, vp, vp, vp], ctypes.c_int),
         "gga_variant_count": ([], ctypes.c_int),
         "gga_variant_side": ([i32], i32),
         "gga_variant_is_slab": ([i32], i32),
@@ -146,7 +147,7 @@ EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
            "gga_sga_workspace_bytes", "gga_sga_init", "gga_sga_generation", "gga_sga_run",
            "gga_variant_count", "gga_variant_side", "gga_variant_is_slab", "gga_variant_name", "gga_get_variant",
            "gga_set_variant", "gga_uneven_workspace_bytes", "gga_simulate_uneven", "gga_event_table_bytes",
-           "gga_state_run_variant", "gga_autotune_workspace_bytes", "gga_autotune")
+           "gga_state_run_variant", "gga_autotune_workspace_bytes", "gga_autotune", "gga_simulate_library")
 
 
 class GGAError(RuntimeError):
@@ -303,6 +304,35 @@ def state_run(params, cfg, dose, gap, nfrac, n0, nsteps, fields, cells, traj=Fal
                              _ptr(nfrac), P, K, int(n0), int(nsteps), _ptr(fields), _ptr(cells),
                              _ptr(live), _ptr(tr), _stream(stream)))
     return live, tr
+
+
+def grow_library(params, L, n, days, seed=0, substeps=10, stream=None):
+    """n untreated tumours grown from the seed disc for `days` days (replica
+    streams 0 .. n-1 of protocol 0 under `seed`): (fields, cells) for
+    simulate_library."""
+    cfg = make_cfg(L, 24 * days, n, seed=seed, substeps=substeps)
+    fields, cells = state_init(params, cfg, 1, stream=stream)
+    z = torch.zeros((1, 1), dtype=torch.float32, device=fields.device)
+    state_run(params, cfg, z, z.int(), torch.zeros(1, dtype=torch.int32, device=fields.device), 0, 24 * days,
+              fields, cells, stream=stream)
+    return fields, cells
+
+
+def simulate_library(params, cfg, dose, gap, nfrac, lib_fields, lib_cells, stream=None):
+    """Simulate each protocol's replica r from library tumour r mod n_lib;
+    returns (live[P, R], fitness[P])."""
+    P, K = _protocols(dose, gap, nfrac)
+    n_lib = lib_fields.shape[0]
+    if lib_fields.shape != (n_lib, 3, cfg.L, cfg.L) or lib_cells.shape != (n_lib, cfg.L, cfg.L):
+        raise ValueError("library states must be [n, 3, L, L] fields and [n, L, L] cells")
+    if not (lib_fields.is_contiguous() and lib_cells.is_contiguous()):
+        raise ValueError("library states must be contiguous")
+    live = torch.empty((P, cfg.R), dtype=torch.int32, device=dose.device)
+    fit = torch.empty((P,), dtype=torch.float32, device=dose.device)
+    _check(LIB.gga_simulate_library(ctypes.byref(_as_params(params)), ctypes.byref(cfg), _ptr(dose), _ptr(gap),
+                                    _ptr(nfrac), P, K, _ptr(lib_fields), _ptr(lib_cells),
+                                    n_lib, _ptr(live), _ptr(fit), _stream(stream)))
+    return live, fit
 
 
 def philox_fill(ctr, seed, stream=None):

@@ -1,6 +1,7 @@
 """Build the HIP library libgga.so in-tree with hipcc for gfx950.
 
-Usage: python -m paper_2303_08123_amd.build  (or build() from Python).
+Usage: python paper_2303_08123_amd/build.py  (run as a script: importing the package
+needs the library it builds).
 """
 import os
 import shutil

@@ -223,6 +223,31 @@ int gga_state_run(const gga_params* params, const gga_sim_cfg* cfg, const float*
     return e == hipSuccess ? GGA_OK : hip_fail(e);
 }
 
+int gga_simulate_library(const gga_params* params, const gga_sim_cfg* cfg, const float* dose_d,
+                         const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P, int32_t K,
+                         const float* lib_fields_d, const uint16_t* lib_cells_d, int32_t n_lib, int32_t* live_d,
+                         float* fitness_d, hipStream_t stream) {
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((rc = check_cfg(cfg))) return rc;
+    if ((rc = check_batch(P, K, cfg->R))) return rc;
+    if (n_lib < 1) return GGA_E_ARG;
+    if (P == 0) return GGA_OK;
+    if (!nfrac_d || !live_d || !fitness_d || !lib_fields_d || !lib_cells_d || (K > 0 && (!dose_d || !gap_h_d)))
+        return GGA_E_ARG;
+    gga::SimArgs a = make_args(params, cfg, dose_d, gap_h_d, nfrac_d, K);
+    a.n0 = 0;
+    a.nsteps = cfg->horizon;
+    a.mode = gga::MODE_LOAD;                       // read-only: the library is not written
+    a.fields = const_cast<float*>(lib_fields_d);
+    a.cells = const_cast<uint16_t*>(lib_cells_d);
+    a.lib_n = n_lib;
+    a.live = live_d;
+    hipError_t e = gga::launch_simulation(a, cfg->L, P * cfg->R, stream);
+    if (e == hipSuccess) e = gga::launch_fitness(live_d, P, cfg->R, fitness_d, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
 int gga_philox_fill(const uint32_t* ctr_d, uint64_t seed, uint32_t* out_d, int64_t n,
                     hipStream_t stream) {
     if (n < 0 || (n > 0 && (!ctr_d || !out_d))) return GGA_E_ARG;

@@ -42,6 +42,7 @@ struct SimArgs {
     const int32_t* ev_step;   // [P][K] steps of the positive-dose fractions, in order
     const uint32_t* ev_thr;   // [P][K][4] survival thresholds per sensitivity class
     int32_t count_at;         // slab form without horizon[]: the step whose end is counted
+    int32_t lib_n;            // resident form with MODE_LOAD: replica r loads state r mod lib_n (0: its own)
 };
 constexpr int MAX_SLABS = 16;
 

@@ -184,9 +184,11 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     } else {
         inst = a.inst_list ? a.inst_list[blockIdx.x] : (int)blockIdx.x;
     }
-    const int slot = SLAB ? (int)(blockIdx.x / a.n_slabs) : inst;   // state buffer row
     const int p = inst / a.R;
     const int r = inst - p * a.R;
+    // state buffer row: the slab's list position; a library tumour (replica r
+    // starts from library state r mod lib_n); or the instance
+    const int slot = SLAB ? (int)(blockIdx.x / a.n_slabs) : (a.lib_n ? r % a.lib_n : inst);
     // the slab's first lattice row, and its own (non-halo) rows [iy0, iy1) of the slab
     const int ys = SLAB ? a.slab_ys[slab] : 0;
     const int iy0 = SLAB ? a.slab_i0[slab] : 0, iy1 = SLAB ? a.slab_i1[slab] : RR;

@@ -246,3 +246,21 @@ def test_outputs_are_deterministic(gga, model_dict):
     a = gga.simulate(model_dict, cfg, *dd, traj=True)
     b = gga.simulate(model_dict, cfg, *dd, traj=True)
     assert all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+def test_library_tumours_equal_state_runs_from_the_same_states(gga, model_dict):
+    """Replica r of every protocol starts from library tumour r mod n: the live
+    counts equal state_run from copies of those states."""
+    L, P, R, n_lib, H = 64, 5, 3, 2, 40
+    lib_f, lib_c = gga.grow_library(model_dict, L, n_lib, days=4, seed=12)
+    assert (lib_c.cpu().numpy().view(np.uint16) & 3 != 0).sum() > 2 * 113      # the tumours grew
+    dose, gap, nfrac = workloads.random_protocols(P, 4, seed=3, kmin=1)
+    dd = _dev(dose, gap, nfrac)
+    cfg = gga.make_cfg(L, H, R, seed=21, dose_cap=100.0)
+    live, fit = gga.simulate_library(model_dict, cfg, *dd, lib_f, lib_c)
+    idx = torch.tensor([r % n_lib for p in range(P) for r in range(R)], device="cuda")
+    f, c = lib_f[idx].contiguous(), lib_c[idx].contiguous()
+    ref, _ = gga.state_run(model_dict, cfg, *dd, 0, H, f, c)
+    assert torch.equal(live, ref)
+    assert np.allclose(fit.cpu().numpy(), ref.cpu().numpy().mean(1))
+    assert torch.equal(lib_f, gga.grow_library(model_dict, L, n_lib, days=4, seed=12)[0])   # read only, repeatable

@@ -179,3 +179,20 @@ def test_uneven_argument_errors_before_any_launch(gga):
     rc = gga.LIB.gga_state_run_variant(ctypes.byref(p), ctypes.byref(cfg), 5, fake, fake, fake, 2, 1, 0, 1,
                                        fake, fake, fake, fake, fake, 1 << 20, fake, None)
     assert rc == -1                                           # a 256 variant on a 64 lattice
+
+
+def test_ga_operator_settings_are_checked_before_any_launch(gga):
+    fake = ctypes.c_void_p(0x1000)
+    a = gga.make_alphabet(0.5, [1, 2, 3, 4, 5], list(range(6, 61, 6)), 10, 10, 20.0)
+    for kw in (dict(selection="rank", q=0.0), dict(selection="truncation", trunc_frac=1.5),
+               dict(selection="roulette", roulette_base=float("inf"))):
+        g = gga.make_ga(**kw)
+        rc = gga.LIB.gga_ga_breed(ctypes.byref(g), ctypes.byref(a), fake, fake, fake, 16, 10, fake, fake, fake,
+                                  fake, fake, None)
+        assert rc == -1, kw
+    g = gga.make_ga()
+    g.selection = 7
+    assert gga.LIB.gga_ga_breed(ctypes.byref(g), ctypes.byref(a), fake, fake, fake, 16, 10, fake, fake, fake,
+                                fake, fake, None) == -1
+    g = gga.make_ga(mutation=("gene", "swap", "raise"), crossover="uniform")
+    assert g.mutation == 7 and g.crossover == 3

@@ -496,26 +496,6 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             });
         for (; s < a.substeps; ++s) plain_substep(s & 1);
 
-        // Environment flags of every site, taken from the fields right after the
-        // sub-steps (x < th  <=>  sign bit of x - th: the difference of two finite
-        // floats is zero only when they are equal and otherwise keeps the sign of
-        // the exact difference).  The cell update below reads only these masks.
-        uint32_t nec_m = 0, starv_m = 0;
-        {
-            const float thOq = s_k.thOq, thGq = s_k.thGq, thOd = s_k.thOd, thGd = s_k.thGd, thHd = s_k.thHd;
-#pragma unroll
-            for (int i = 0; i < RPT; ++i)
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const int idx = i * CPL + c;
-                    const float O = F[0][i][c], Gl = F[1][i][c], H = F[2][i][c];
-                    nec_m |= ((__float_as_uint(Gl - thGd) | __float_as_uint(O - thOd) |
-                               __float_as_uint(thHd - H)) >> 31) << idx;
-                    starv_m |= ((__float_as_uint(O - thOq) | __float_as_uint(Gl - thGq)) >> 31) << idx;
-                    asm volatile("" : "+v"(nec_m), "+v"(starv_m));   // fold each site in now
-                }
-        }
-
         // (4) cell update, bit-parallel over the thread's RPT x CPL sites
         // (bit idx = i * CPL + c of 32-bit masks).  Proposers claim an EMPTY
         // target with ds_min_u32 on best[t] (one slot per site, sharing the
@@ -559,6 +539,25 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         // Per site: lysis and environment transitions, written back row by row.
         uint32_t empty_m = ALL_SITES, cyc_m = 0, old_m = 0, alive_m = 0;
         if (__builtin_amdgcn_ballot_w64(occupied != 0u) != 0) {   // wave-uniform; else all EMPTY
+            // Environment flags of the thread's sites, from the fields after the
+            // sub-steps (x < th  <=>  sign bit of x - th: the difference of two
+            // finite floats is zero only when they are equal and otherwise keeps
+            // the sign of the exact difference).
+            uint32_t nec_m = 0, starv_m = 0;
+            {
+                const float thOq = s_k.thOq, thGq = s_k.thGq, thOd = s_k.thOd, thGd = s_k.thGd, thHd = s_k.thHd;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const int idx = i * CPL + c;
+                        const float O = F[0][i][c], Gl = F[1][i][c], H = F[2][i][c];
+                        nec_m |= ((__float_as_uint(Gl - thGd) | __float_as_uint(O - thOd) |
+                                   __float_as_uint(thHd - H)) >> 31) << idx;
+                        starv_m |= ((__float_as_uint(O - thOq) | __float_as_uint(Gl - thGq)) >> 31) << idx;
+                        asm volatile("" : "+v"(nec_m), "+v"(starv_m));   // fold each site in now
+                    }
+            }
             const int T_lys = s_k.T_lys, T_min = s_k.T_min;
             empty_m = 0;
 #pragma unroll

@@ -3,8 +3,9 @@
 Tolerances come from the arithmetic: the GEMM multiplies bf16 values exactly
 and accumulates in fp32, so its error is a few fp32 roundings of the sum of
 |products|; the network also rounds every hidden activation (and, backwards,
-every dZ) to bf16, a relative error of 2^-9 per value, so forward outputs are
-compared at 2 % of their spread and gradients per tensor at 5 % relative
+every dZ) to bf16, a relative error of at most 2^-9 per value.  Forward
+outputs are compared against the first-order bound of those roundings carried
+through the layers (|gelu'| <= 1.13); gradients per tensor at 5 % relative
 Frobenius error with cosine similarity above 0.998.
 """
 import numpy as np
@@ -66,9 +67,15 @@ def test_forward_matches_oracle(gga):
     pred = gga.mlp_predict(net, *dd).cpu().numpy().astype(np.float64)
     params = _oracle_params(gga, net)
     X = bf16(omlp.encode(dose, gap, nfrac))
-    y, _ = omlp.forward(params, X)
-    spread = max(np.std(y), 1e-3)
-    assert np.max(np.abs(pred - y)) <= 0.02 * spread + 1e-6 * np.max(np.abs(y)), (np.max(np.abs(pred - y)), spread)
+    y, (_, _, H1, _, H2, _, H3) = omlp.forward(params, X)
+    u = 2.0 ** -9                                    # bf16 rounding, relative
+    e1 = u * np.abs(H1)
+    e2 = u * np.abs(H2) + 1.13 * (e1 @ np.abs(params[2]))
+    e3 = u * np.abs(H3) + 1.13 * (e2 @ np.abs(params[4]))
+    bound = e3 @ np.abs(params[6]) + 1e-6 * (np.abs(H3) @ np.abs(params[6]))
+    err = np.abs(pred - y)
+    assert np.all(err <= bound), (err.max(), bound.min())
+    assert err.max() < 0.3 * bound.max()             # the bound is not vacuous here
 
 
 def test_gradients_match_oracle(gga):
@@ -96,7 +103,9 @@ def test_adam_first_step_and_training(gga):
     net = gga.mlp_net(seed=7)
     B = 512
     dose, gap, nfrac = protocols(B, 10, 4)
-    target = torch.from_numpy((dose.astype(np.float64) * np.linspace(1, 2, 10)).sum(1).astype(np.float32)).cuda()
+    # a target the encoding can see: only fractions j < nfrac are present
+    present = np.arange(10) < nfrac[:, None]
+    target = torch.from_numpy((dose.astype(np.float64) * np.linspace(1, 2, 10) * present).sum(1).astype(np.float32)).cuda()
     gga.mlp_set_norm(net, target)
     dd = [torch.from_numpy(x).cuda() for x in (dose, gap, nfrac)]
     work = gga.mlp_work(B)

@@ -57,18 +57,22 @@ PROTOS = (np.array([[2.0, 3.0, 1.0], [1.5, 0.0, 2.5]], np.float32),
 def test_variants_agree_bit_for_bit(gga, model_dict, L, variant, reference):
     md = high_uptake(model_dict)
     prm = Params.from_dict(md)
-    P, R, seed, steps = 2, 2, 13, 100
+    P, R, seed = 2, 2, 13
     f0, c0 = _oracle_init(prm, L, P, R, seed)
-    cfg = gga.make_cfg(L, steps, R, seed=seed, dose_cap=100.0)
-    out = []
+    cfg = gga.make_cfg(L, 150, R, seed=seed, dose_cap=100.0)
+    states = {}
     for v in (reference, variant):
         f_d, c_d = _dev(f0, c0.view(np.int16))
-        live = gga.state_run_variant(md, cfg, v, *_dev(*PROTOS), 0, steps, f_d, c_d)
-        out.append((f_d.cpu().numpy(), c_d.cpu().numpy(), live.cpu().numpy()))
-    for a, b in zip(*out):
-        assert np.array_equal(a, b)
-    st = out[0][1].view(np.uint16) & 3
-    assert (st == 2).any() and (st == 3).any()     # quiescent and dead cells took part
+        out = []
+        for n0, n in ((0, 50), (50, 200)):              # dead cells at step 50, quiescent ones by 250
+            live = gga.state_run_variant(md, cfg, v, *_dev(*PROTOS), n0, n, f_d, c_d)
+            out.append((f_d.cpu().numpy().copy(), c_d.cpu().numpy().copy(), live.cpu().numpy()))
+        states[v] = out
+    for seg_a, seg_b in zip(states[reference], states[variant]):
+        for a, b in zip(seg_a, seg_b):
+            assert np.array_equal(a, b)
+    st50, st250 = (states[reference][k][1].view(np.uint16) & 3 for k in (0, 1))
+    assert (st50 == 3).any() and (st250 == 2).any()   # dead and quiescent cells took part
 
 
 def test_slab_continuation_equals_one_run(gga, model_dict):

@@ -133,9 +133,10 @@ def _reevaluate(gga, params, wl, best_dose, best_gap, R, seed):
 
 def surrogate_bench(gga, workloads, md, args):
     """Surrogate-screened GA against the GA without it, on the batched
-    workload's simulator and alphabets, both with the GA settings of the GA
-    workload (population 2048 x 4 replicas, k = 4, crossover 0.8, mutation
-    0.05).  The surrogate is trained on 200k simulated random protocols; each
+    workload's simulator and alphabets, both with the GA operators of the GA
+    workload (k = 4, crossover 0.8, mutation 0.05, 4 replicas).  The GA keeps a
+    population of 2048; the screened GA starts from the best M (256) of the
+    same 2048 simulated random protocols and keeps the best M simulated.  The surrogate is trained on 200k simulated random protocols; each
     screened generation breeds 5000 candidates (10^6 over 200 generations) and
     fully simulates the best-predicted 1 %.  Each run's best protocol of every
     generation is re-simulated with 64 fresh replicas; the target is the GA's
@@ -198,12 +199,16 @@ def surrogate_bench(gga, workloads, md, args):
         t_off += wall
         log(f"ga: generations {g0}..{g0 + n - 1} in {wall:.1f} s")
     ga_t, ga_arc, ga_total = np.array(times), arc, t_off
-    # 3. the surrogate-screened GA
+    # 3. the surrogate-screened GA: the same 2048 random protocols are simulated
+    # once (the GA's first generation), the best M start the screened loop
     sga_cfg = gga.make_ga(n_elite=0, tournament_k=4, p_cross=0.8, p_mut=0.05, seed=1)
-    run = gga.SurrogateGA(params, cfg, sga_cfg, alpha, gga.make_sga(C, S, screen=True), net, dose0, gap0,
-                          archive=True)
+    M = args.sga_population
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    _, f0, _ = gga.simulate(params, cfg, dose0, gap0, torch.full((N,), K, dtype=torch.int32, device="cuda"))
+    best = torch.argsort(f0, stable=True)[:M]
+    run = gga.SurrogateGA(params, cfg, sga_cfg, alpha, gga.make_sga(C, S, screen=True), net,
+                          dose0[best].contiguous(), gap0[best].contiguous(), archive=True)
     run.init()
     torch.cuda.synchronize()
     t_off = time.perf_counter() - t0
@@ -234,7 +239,8 @@ def surrogate_bench(gga, workloads, md, args):
         "metric": "time to reach the GA's best fitness (within 1 %), surrogate-screened GA",
         "value": sga_ttb, "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
         "dtype": "bf16 surrogate (f32 accumulate), f32 simulation", "data": "synthetic",
-        "config": {"workload": "sga-2048x4-128x128-20d", "population": N, "replicas": R, "generations": G,
+        "config": {"workload": "sga-2048x4-128x128-20d", "population": N, "screened_population": M,
+                   "replicas": R, "generations": G,
                    "candidates_per_generation": C, "simulated_per_generation": S, "screened_total": C * G,
                    "training_pairs": n_train, "training_replicas": 1, "epochs": args.epochs, "batch": B,
                    "reevaluation_replicas": RE},
@@ -243,7 +249,7 @@ def surrogate_bench(gga, workloads, md, args):
                "final_best_reevaluated": float(ga_best_so_far[-1]), "simulations": N * G},
         "sga": {"time_to_target_s": sga_ttb, "generation": sga_gen, "total_s": sga_total,
                 "final_best_reevaluated": float(sga_re[-1]), "best_reevaluated": float(sga_re.min()),
-                "simulations": N + S * G,
+                "simulations": N + M + S * G,
                 "time_to_target_incl_training_s": None if sga_ttb is None else sga_ttb + t_data + t_train,
                 "surrogate_error_on_archive": float(np.mean(np.abs(arc_pred - sga_re)))},
         "surrogate": {"data_s": t_data, "train_s": t_train, "held_out": held_out},
@@ -316,6 +322,8 @@ def main():
     ap.add_argument("--candidates", type=int, default=5000, help="surrogate workload: candidates per generation")
     ap.add_argument("--train-pairs", type=int, default=200000, help="surrogate workload: training pairs")
     ap.add_argument("--epochs", type=int, default=10, help="surrogate workload: training epochs")
+    ap.add_argument("--sga-population", type=int, default=256,
+                    help="surrogate workload: simulated protocols kept by the screened GA")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy, to scale HBM counters")

@@ -134,7 +134,9 @@ def _reevaluate(gga, params, wl, best_dose, best_gap, R, seed):
 def surrogate_bench(gga, workloads, md, args):
     """Surrogate-screened GA against the GA without it, on the batched
     workload's simulator and alphabets, both with the GA operators of the GA
-    workload (k = 4, crossover 0.8, mutation 0.05, 4 replicas).  The GA keeps a
+    workload (k = 4, crossover 0.8, mutation 0.05, 4 replicas).  Training
+    pairs: 200k protocols simulated once, half random and half the
+    populations of an independent GA run (other GA, population and run seeds).  The GA keeps a
     population of 2048; the screened GA starts from the best M (256) of the
     same 2048 simulated random protocols and keeps the best M simulated.  The surrogate is trained on 200k simulated random protocols; each
     screened generation breeds 5000 candidates (10^6 over 200 generations) and
@@ -148,15 +150,31 @@ def surrogate_bench(gga, workloads, md, args):
     alpha = gga.make_alphabet(0.5, [1, 2, 3, 4, 5], list(range(6, 61, 6)), K, K, wl["dose_cap"])
     params = gga.make_params(md)
     cfg = gga.make_cfg(wl["L"], wl["horizon"], R, seed=wl["seed"], substeps=wl["substeps"], dose_cap=wl["dose_cap"])
-    # 1. training pairs and training
+    # 1. training pairs: half random protocols, half the populations visited by
+    # an independent GA run (other seeds), each simulated once; then training
     t0 = time.perf_counter()
     n_train = args.train_pairs
-    td, tg, tn = gga.population_random(alpha, n_train, K, seed=100)
+    n_rand = n_train // 2
+    rd, rg, _ = gga.population_random(alpha, n_rand, K, seed=100)
+    parts_d, parts_g = [rd], [rg]
+    g_cfg = gga.make_ga(n_elite=N // 10, tournament_k=4, p_cross=0.8, p_mut=0.05, seed=2)
+    d, g = gga.population_random(alpha, N, K, seed=5)[:2]
+    have = 0
+    while have < n_train - n_rand:
+        parts_d.append(d)
+        parts_g.append(g)
+        have += N
+        d, g, _, _ = gga.ga_run(params, gga.make_cfg(wl["L"], wl["horizon"], R, seed=77, substeps=wl["substeps"],
+                                                     dose_cap=wl["dose_cap"]), g_cfg, alpha, d, g, 1, False,
+                                g0=have // N)
+    td = torch.cat(parts_d)[:n_train].contiguous()
+    tg = torch.cat(parts_g)[:n_train].contiguous()
+    tn = torch.full((n_train,), K, dtype=torch.int32, device="cuda")
     _, tf, _ = gga.simulate(params, gga.make_cfg(wl["L"], wl["horizon"], 1, seed=1000, substeps=wl["substeps"],
                                                  dose_cap=wl["dose_cap"]), td, tg, tn)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    log(f"surrogate: {n_train} training pairs simulated in {t_data:.1f} s")
+    log(f"surrogate: {n_train} training pairs ({n_rand} random, {n_train - n_rand} from a GA run) in {t_data:.1f} s")
     net = gga.mlp_net(seed=3)
     gga.mlp_set_norm(net, tf)
     B = 1024
@@ -207,7 +225,9 @@ def surrogate_bench(gga, workloads, md, args):
     t0 = time.perf_counter()
     _, f0, _ = gga.simulate(params, cfg, dose0, gap0, torch.full((N,), K, dtype=torch.int32, device="cuda"))
     best = torch.argsort(f0, stable=True)[:M]
-    run = gga.SurrogateGA(params, cfg, sga_cfg, alpha, gga.make_sga(C, S, screen=True), net,
+    run = gga.SurrogateGA(params, cfg, sga_cfg, alpha,
+                          gga.make_sga(C, S, screen=True, refine_steps=args.refine_steps, refine_lr=args.refine_lr),
+                          net,
                           dose0[best].contiguous(), gap0[best].contiguous(), archive=True)
     run.init()
     torch.cuda.synchronize()
@@ -242,8 +262,9 @@ def surrogate_bench(gga, workloads, md, args):
         "config": {"workload": "sga-2048x4-128x128-20d", "population": N, "screened_population": M,
                    "replicas": R, "generations": G,
                    "candidates_per_generation": C, "simulated_per_generation": S, "screened_total": C * G,
-                   "training_pairs": n_train, "training_replicas": 1, "epochs": args.epochs, "batch": B,
-                   "reevaluation_replicas": RE},
+                   "training_pairs": n_train, "training_from_ga_run": n_train - n_rand, "training_replicas": 1,
+                   "epochs": args.epochs, "batch": B,
+                   "reevaluation_replicas": RE, "refine_steps": args.refine_steps, "refine_lr": args.refine_lr},
         "target_fitness": target,
         "ga": {"time_to_target_s": ga_ttb, "generation": ga_gen, "total_s": ga_total,
                "final_best_reevaluated": float(ga_best_so_far[-1]), "simulations": N * G},
@@ -322,6 +343,8 @@ def main():
     ap.add_argument("--candidates", type=int, default=5000, help="surrogate workload: candidates per generation")
     ap.add_argument("--train-pairs", type=int, default=200000, help="surrogate workload: training pairs")
     ap.add_argument("--epochs", type=int, default=10, help="surrogate workload: training epochs")
+    ap.add_argument("--refine-steps", type=int, default=4, help="surrogate workload: Adam steps per generation")
+    ap.add_argument("--refine-lr", type=float, default=1e-4, help="surrogate workload: their learning rate")
     ap.add_argument("--sga-population", type=int, default=256,
                     help="surrogate workload: simulated protocols kept by the screened GA")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -291,7 +291,8 @@ int gga_ga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cf
  *
  * Net buffer (device, caller-owned, gga_mlp_net_bytes() bytes), 256-byte
  * aligned blocks in this order: norm f32[2] (mu, sigma of the training
- * targets), params f32[591873], Adam m, Adam v, gradients (same size), then
+ * targets) and int32 Adam step count in one block, params f32[591873], Adam
+ * m, Adam v, gradients (same size), then
  * bf16 copies W1 [128][512], W1^T, W2 [512][512], W2^T, W3, W3^T.  Parameter
  * order: W1 [128][512], b1[512], W2 [512][512], b2, W3 [512][512], b3,
  * w4[512], b4[1].  Work buffer: gga_mlp_work_bytes(B) bytes for batch B.
@@ -341,6 +342,8 @@ typedef struct gga_sga_cfg {
     int32_t n_candidates;   /* C: offspring bred and screened per generation, >= 2      */
     int32_t n_simulated;    /* S: screened offspring fully simulated, 1 .. C            */
     int32_t screen;         /* 1: the S best predicted by the surrogate; 0: S random     */
+    int32_t refine_steps;   /* Adam steps per generation on the N + S simulated pairs, 0 .. 64 (screen = 1) */
+    float refine_lr;        /* their learning rate (> 0 when refine_steps > 0)           */
 } gga_sga_cfg;
 
 /* Device workspace of the surrogate-screened GA. */
@@ -364,13 +367,16 @@ int gga_sga_init(const gga_params* params, const gga_sim_cfg* cfg, const gga_sga
  * (gga_mlp_*), fully simulate the S best-predicted candidates as members of
  * population g + 1 (Philox key cfg->seed + (g + 1) * 0x9E3779B97F4A7C15, the
  * initial population being population 0), and keep the best N of the N + S
- * evaluated protocols, sorted, in rows 0 .. N-1.  hist_d[g] = (best, mean)
- * fitness of the kept population.  With screen = 0 the S candidates are
+ * evaluated protocols, sorted, in rows 0 .. N-1.  With refine_steps > 0 the
+ * surrogate first takes that many Adam steps (on the net's own step count) on
+ * the N + S simulated pairs: the simulation judges the surrogate's error and
+ * corrects it where the search is.  hist_d[g] = (best, mean) fitness of the
+ * kept population.  With screen = 0 the S candidates are
  * picked at random instead (the same loop without the surrogate).
  * Errors: as gga_ga_generation.
  */
 int gga_sga_generation(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga,
-                       const gga_alphabet* a, const gga_sga_cfg* sga, const void* net_d,
+                       const gga_alphabet* a, const gga_sga_cfg* sga, void* net_d,
                        float* pop_dose_d, int32_t* pop_gap_d, float* pop_fit_d, int32_t N, int32_t K,
                        void* ws_d, size_t ws_bytes, float* hist_d, int32_t hist_cap,
                        hipStream_t stream);
@@ -384,7 +390,7 @@ int gga_sga_generation(const gga_params* params, const gga_sim_cfg* cfg, const g
  * Errors: as gga_sga_generation.
  */
 int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga,
-                const gga_alphabet* a, const gga_sga_cfg* sga, const void* net_d, float* pop_dose_d,
+                const gga_alphabet* a, const gga_sga_cfg* sga, void* net_d, float* pop_dose_d,
                 int32_t* pop_gap_d, float* pop_fit_d, int32_t N, int32_t K, int32_t g0, int32_t n_gen,
                 int32_t use_graph, void* ws_d, size_t ws_bytes, float* hist_d, float* best_dose_d,
                 int32_t* best_gap_d, float* gen_ms_h, hipStream_t stream);

@@ -59,7 +59,8 @@ class Alphabet(ctypes.Structure):
 
 class SgaCfg(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("n_candidates", ctypes.c_int32),
-                ("n_simulated", ctypes.c_int32), ("screen", ctypes.c_int32)]
+                ("n_simulated", ctypes.c_int32), ("screen", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("refine_lr", ctypes.c_float)]
 
 
 class GaCfg(ctypes.Structure):
@@ -533,7 +534,7 @@ def _align256(x):
 def mlp_layout():
     """Byte offsets of the net buffer's blocks (norm, params, m, v, grads)."""
     off, out = 0, {}
-    for name, size in (("norm", 8), ("p", 4 * MLP_PARAMS), ("m", 4 * MLP_PARAMS), ("v", 4 * MLP_PARAMS),
+    for name, size in (("norm", 12), ("p", 4 * MLP_PARAMS), ("m", 4 * MLP_PARAMS), ("v", 4 * MLP_PARAMS),
                        ("g", 4 * MLP_PARAMS)):
         out[name] = off
         off += _align256(size)
@@ -614,10 +615,11 @@ def mlp_gemm(A, B, a_trans=False, b_trans=False, stream=None):
 
 # ---------------------------------------------------------------- surrogate-screened GA
 
-def make_sga(n_candidates, n_simulated, screen=True):
+def make_sga(n_candidates, n_simulated, screen=True, refine_steps=0, refine_lr=1e-4):
     c = SgaCfg()
     c.struct_size = ctypes.sizeof(SgaCfg)
     c.n_candidates, c.n_simulated, c.screen = int(n_candidates), int(n_simulated), int(bool(screen))
+    c.refine_steps, c.refine_lr = int(refine_steps), float(refine_lr)
     return c
 
 

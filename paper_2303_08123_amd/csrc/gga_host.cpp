@@ -515,7 +515,7 @@ Layout net_layout() {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t at = off; off += align256(bytes); return at; };
-    L.norm = take(2 * sizeof(float));
+    L.norm = take(2 * sizeof(float) + sizeof(int32_t));
     L.p = take(sizeof(float) * MLP_PARAMS);
     L.m = take(sizeof(float) * MLP_PARAMS);
     L.v = take(sizeof(float) * MLP_PARAMS);
@@ -537,6 +537,7 @@ MlpNet mlp_net(void* base) {
     char* c = static_cast<char*>(base);
     MlpNet n{};
     n.norm = reinterpret_cast<float*>(c + L.norm);
+    n.step = reinterpret_cast<int32_t*>(c + L.norm + 2 * sizeof(float));
     n.p = reinterpret_cast<float*>(c + L.p);
     n.m = reinterpret_cast<float*>(c + L.m);
     n.v = reinterpret_cast<float*>(c + L.v);
@@ -608,8 +609,8 @@ int gga_mlp_init(void* net_d, uint64_t seed, hipStream_t stream) {
     if (!net_d) return GGA_E_ARG;
     const gga::MlpNet net = gga::mlp_net(net_d);
     hipError_t e = gga::mlp_init(net, seed, stream);
-    // normalisation defaults to (0, 1) until gga_mlp_set_norm
-    static const float unit[2] = {0.0f, 1.0f};
+    // normalisation defaults to (0, 1) until gga_mlp_set_norm; Adam step 0
+    static const float unit[3] = {0.0f, 1.0f, 0.0f};
     if (e == hipSuccess) e = hipMemcpyAsync(net.norm, unit, sizeof(unit), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     return e == hipSuccess ? GGA_OK : hip_fail(e);
@@ -691,6 +692,7 @@ struct SgaWorkspace {
     float* tmp_dose;
     int32_t* tmp_gap;
     float* tmp_fit;
+    float* loss;
     void* mlp_work;
     size_t mlp_work_bytes;
 };
@@ -719,7 +721,8 @@ size_t sga_layout(const SgaDims& d, SgaWorkspace* w, void* base) {
     s.tmp_dose = reinterpret_cast<float*>(take(4 * (size_t)d.N * K));
     s.tmp_gap = reinterpret_cast<int32_t*>(take(4 * (size_t)d.N * K));
     s.tmp_fit = reinterpret_cast<float*>(take(4 * (size_t)d.N));
-    s.mlp_work_bytes = gga::mlp_work_bytes(d.C);
+    s.loss = reinterpret_cast<float*>(take(sizeof(float)));
+    s.mlp_work_bytes = gga::mlp_work_bytes(std::max<int32_t>(d.C, d.N + d.S));
     s.mlp_work = take(s.mlp_work_bytes);
     if (w) *w = s;
     return off;
@@ -730,6 +733,8 @@ int check_sga(const gga_sga_cfg* sga, int32_t N, int32_t K, int32_t R, SgaDims* 
     if (sga->struct_size != sizeof(gga_sga_cfg)) return GGA_E_ABI;
     if (sga->n_candidates < 2 || sga->n_simulated < 1 || sga->n_simulated > sga->n_candidates) return GGA_E_ARG;
     if (sga->screen != 0 && sga->screen != 1) return GGA_E_ARG;
+    if (sga->refine_steps < 0 || sga->refine_steps > 64 || (sga->refine_steps > 0 && !sga->screen)) return GGA_E_ARG;
+    if (sga->refine_steps > 0 && !(sga->refine_lr > 0.0f && std::isfinite(sga->refine_lr))) return GGA_E_ARG;
     if (N < 2 || K < 1 || K > GGA_KMAX || R < 1) return GGA_E_ARG;
     if ((long long)sga->n_candidates * gga::MLP_HID > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
     if ((long long)(N + sga->n_simulated) * R > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
@@ -753,7 +758,7 @@ hipError_t sim_rows(const gga_params* params, const gga_sim_cfg* cfg, const floa
 }
 
 hipError_t enqueue_sga(const gga_params* params, const gga_sim_cfg* cfg, gga::GaArgs ga_args, const gga_sga_cfg* sga,
-                       const void* net, float* pop_dose, int32_t* pop_gap, float* pop_fit, const SgaDims& d,
+                       void* net, float* pop_dose, int32_t* pop_gap, float* pop_fit, const SgaDims& d,
                        const SgaWorkspace& w, float* hist, int32_t hist_cap, float* best_dose, int32_t* best_gap,
                        hipStream_t stream) {
     const int N = d.N, K = d.K, C = d.C, S = d.S;
@@ -772,7 +777,7 @@ hipError_t enqueue_sga(const gga_params* params, const gga_sim_cfg* cfg, gga::Ga
     if (e == hipSuccess) e = gga::launch_offspring(ga_args, stream);
     // screen: surrogate prediction (or random keys for the ablation), keep the best S
     if (e == hipSuccess) {
-        e = sga->screen ? gga::mlp_forward(gga::mlp_net(const_cast<void*>(net)), w.cand_dose, w.cand_gap, w.nfrac, C, K,
+        e = sga->screen ? gga::mlp_forward(gga::mlp_net(net), w.cand_dose, w.cand_gap, w.nfrac, C, K,
                                            gga::mlp_work(w.mlp_work, C), w.pred, true, stream)
                         : gga::launch_random_keys(C, w.generation, ((uint64_t)ga_args.seed_hi << 32) | ga_args.seed_lo,
                                                   w.pred, stream);
@@ -786,6 +791,15 @@ hipError_t enqueue_sga(const gga_params* params, const gga_sim_cfg* cfg, gga::Ga
     if (e == hipSuccess)
         e = sim_rows(params, cfg, pop_dose + (size_t)N * K, pop_gap + (size_t)N * K, w.nfrac, S, K, w.sim_key,
                      w.live, pop_fit + N, stream);
+    // online refinement: Adam steps on the N + S simulated protocols (the
+    // population and the new candidates), where the search now is
+    for (int k = 0; k < sga->refine_steps && e == hipSuccess; ++k) {
+        const gga::MlpNet mnet = gga::mlp_net(net);
+        const gga::MlpWork mw = gga::mlp_work(w.mlp_work, N + S);
+        e = gga::mlp_forward(mnet, pop_dose, pop_gap, w.nfrac, N + S, K, mw, mw.y, false, stream);
+        if (e == hipSuccess) e = gga::mlp_backward(mnet, N + S, pop_fit, mw, w.loss, stream);
+        if (e == hipSuccess) e = gga::mlp_adam_refresh(mnet, 0, sga->refine_lr, stream);
+    }
     // keep the best N of the N + S evaluated protocols
     if (e == hipSuccess) e = gga::launch_rank(pop_fit, N + S, w.order_p, w.pos_p, stream);
     if (e == hipSuccess)
@@ -826,7 +840,7 @@ int gga_sga_init(const gga_params* params, const gga_sim_cfg* cfg, const gga_sga
 }
 
 int gga_sga_generation(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga,
-                       const gga_alphabet* a, const gga_sga_cfg* sga, const void* net_d, float* pop_dose_d,
+                       const gga_alphabet* a, const gga_sga_cfg* sga, void* net_d, float* pop_dose_d,
                        int32_t* pop_gap_d, float* pop_fit_d, int32_t N, int32_t K, void* ws_d, size_t ws_bytes,
                        float* hist_d, int32_t hist_cap, hipStream_t stream) {
     int rc = check_params(params);
@@ -846,7 +860,7 @@ int gga_sga_generation(const gga_params* params, const gga_sim_cfg* cfg, const g
 }
 
 int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga, const gga_alphabet* a,
-                const gga_sga_cfg* sga, const void* net_d, float* pop_dose_d, int32_t* pop_gap_d, float* pop_fit_d,
+                const gga_sga_cfg* sga, void* net_d, float* pop_dose_d, int32_t* pop_gap_d, float* pop_fit_d,
                 int32_t N, int32_t K, int32_t g0, int32_t n_gen, int32_t use_graph, void* ws_d, size_t ws_bytes,
                 float* hist_d, float* best_dose_d, int32_t* best_gap_d, float* gen_ms_h, hipStream_t stream) {
     int rc = check_params(params);

@@ -163,6 +163,7 @@ struct MlpGemm {
 // Views into a net buffer (see mlp_net()).
 struct MlpNet {
     float* norm;                 // [2]: mu, sigma of the training targets
+    int32_t* step;               // Adam step count (after norm in the same block)
     float *p, *m, *v, *g;        // [MLP_PARAMS] each
     float* Wf[3];                // fp32 master weights of the MFMA layers (views into p)
     const float* b[3];

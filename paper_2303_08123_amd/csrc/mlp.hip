@@ -185,9 +185,11 @@ __global__ void out_wgrad_kernel(const bf16* H3, const float* dy, int B, float* 
 }
 
 // Adam with bias correction over the flat parameter vector.
-__global__ void adam_kernel(float* p, float* m, float* v, const float* g, long n, float lr, float c1, float c2) {
+__global__ void adam_kernel(float* p, float* m, float* v, const float* g, long n, float lr, const int32_t* step) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const float t = (float)*step;                       // bias corrections of step t
+    const float c1 = 1.0f - powf(0.9f, t), c2 = 1.0f - powf(0.999f, t);
     const float gi = g[i];
     const float mi = 0.9f * m[i] + 0.1f * gi;
     const float vi = 0.999f * v[i] + 0.001f * gi * gi;
@@ -331,10 +333,12 @@ hipError_t mlp_backward(const MlpNet& net, int B, const float* target, const Mlp
 
 hipError_t mlp_adam_refresh(const MlpNet& net, int step, float lr, hipStream_t s) {
     const long n = MLP_PARAMS;
-    const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+    // the net's step counter: set to `step`, or advanced by one when step is 0
+    hipError_t e = launch_counter(net.step, step > 0 ? step : 1, step > 0 ? 0 : 1, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, net.p, net.m, net.v, net.g, n, lr,
-                       c1, c2);
-    hipError_t e = hipGetLastError();
+                       net.step);
+    e = hipGetLastError();
     for (int l = 0; l < 3 && e == hipSuccess; ++l) e = mlp_refresh_layer(net, l, s);
     return e;
 }

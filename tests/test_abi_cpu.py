@@ -47,6 +47,7 @@ int main(void) {
          offsetof(gga_params, P_div), offsetof(gga_params, m), offsetof(gga_sim_cfg, seed),
          offsetof(gga_alphabet, gaps), sizeof(gga_ga_cfg), offsetof(gga_ga_cfg, seed));
   printf("%zu %zu %zu\n", offsetof(gga_ga_cfg, selection), offsetof(gga_ga_cfg, q), offsetof(gga_ga_cfg, roulette_base));
+  printf("%zu %zu\n", sizeof(gga_sga_cfg), offsetof(gga_sga_cfg, refine_lr));
   return 0;
 }
 """
@@ -63,7 +64,8 @@ def test_struct_layout_matches_python_mirror(gga, tmp_path):
     assert vals == [ctypes.sizeof(gga.Params), ctypes.sizeof(gga.SimCfg), ctypes.sizeof(gga.Alphabet),
                     gga.Params.P_div.offset, gga.Params.m.offset, gga.SimCfg.seed.offset,
                     gga.Alphabet.gaps.offset, ctypes.sizeof(gga.GaCfg), gga.GaCfg.seed.offset,
-                    gga.GaCfg.selection.offset, gga.GaCfg.q.offset, gga.GaCfg.roulette_base.offset]
+                    gga.GaCfg.selection.offset, gga.GaCfg.q.offset, gga.GaCfg.roulette_base.offset,
+                    ctypes.sizeof(gga.SgaCfg), gga.SgaCfg.refine_lr.offset]
 
 
 def test_version_and_errors(gga):

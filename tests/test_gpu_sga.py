@@ -57,16 +57,20 @@ def test_graph_equals_host_driven(gga, model_dict):
     dose, gap = _pop(N, K, 4)
     cfg = gga.make_cfg(L, H, R, seed=2, dose_cap=20.0)
     ga_cfg = gga.make_ga(n_elite=0, tournament_k=4, p_cross=0.8, p_mut=0.05, seed=6)
-    net = gga.mlp_net(seed=1)
+    net0 = gga.mlp_net(seed=1)
     out = []
     for use_graph in (False, True):
-        s = gga.SurrogateGA(model_dict, cfg, ga_cfg, _alphabet(gga), gga.make_sga(C, S, screen=True), net,
+        net = net0.clone()                  # online refinement trains the net during the run
+        s = gga.SurrogateGA(model_dict, cfg, ga_cfg, _alphabet(gga),
+                            gga.make_sga(C, S, screen=True, refine_steps=2, refine_lr=1e-4), net,
                             torch.from_numpy(dose).cuda(), torch.from_numpy(gap).cuda(), archive=True)
         s.init()
         s.run(3, use_graph)
         torch.cuda.synchronize()
         s.run(2, use_graph)
-        out.append([x.cpu().numpy() for x in (s.dose[:N], s.gap[:N], s.fit[:N], s.hist, *s.archive)])
+        out.append([x.cpu().numpy() for x in (s.dose[:N], s.gap[:N], s.fit[:N], s.hist, *s.archive,
+                                              gga.mlp_block(net, "p"))])
+        assert not torch.equal(gga.mlp_block(net, "p"), gga.mlp_block(net0, "p"))   # the net was refined
         assert np.array_equal(out[-1][4][-1], out[-1][0][0]) and np.array_equal(out[-1][5][-1], out[-1][1][0])
     for a, b in zip(*out):
         assert np.array_equal(a, b, equal_nan=True)
@@ -109,7 +113,8 @@ def test_surrogate_screen_beats_random_screen(gga, model_dict):
     ga_cfg = gga.make_ga(n_elite=0, tournament_k=4, p_cross=0.8, p_mut=0.05, seed=8)
     res = {}
     for screen in (True, False):
-        s = gga.SurrogateGA(model_dict, cfg, ga_cfg, alpha, gga.make_sga(C, S, screen=screen), net, d0, g0)
+        sga = gga.make_sga(C, S, screen=screen, refine_steps=2 if screen else 0, refine_lr=1e-4)
+        s = gga.SurrogateGA(model_dict, cfg, ga_cfg, alpha, sga, net.clone(), d0, g0)
         s.init()
         s.run(G, use_graph=True)
         res[screen] = s.fit[:N].cpu().numpy()

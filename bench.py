@@ -32,6 +32,23 @@ OPS_PER_SITE_SUBSTEP = 17
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 
 
+def measured_traffic():
+    """HBM bytes per launch of the simulation kernel from the stored counter
+    record, or None when the kernel's sources changed since it was taken."""
+    import hashlib
+    pkg = os.path.join(ROOT, "paper_2303_08123_amd")
+    try:
+        rec = json.load(open(os.path.join(pkg, "data", "traffic.json")))
+        h = hashlib.sha1()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(pkg, f), "rb").read())
+    except (OSError, KeyError, ValueError):
+        return None
+    if h.hexdigest() != rec["sources_sha1"]:
+        return None
+    return 1024.0 * (rec["fetch_size_kib"] * rec["fetch_scale"] + rec["write_size_kib"] * rec["write_scale"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -347,6 +364,8 @@ def main():
     ap.add_argument("--refine-lr", type=float, default=1e-4, help="surrogate workload: their learning rate")
     ap.add_argument("--sga-population", type=int, default=256,
                     help="surrogate workload: simulated protocols kept by the screened GA")
+    ap.add_argument("--substeps", type=int, default=None,
+                    help="diffusion sub-steps per hour (default: the workload's 10; other values split the time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy, to scale HBM counters")
@@ -387,6 +406,8 @@ def main():
         wl = dict(workloads.CONFIG1)
         dose, gap, nfrac = workloads.config1_protocols()
         wl["P"], wl["K"] = 1, dose.shape[1]
+    if args.substeps is not None:
+        wl["substeps"] = args.substeps
     P, R, L, N, S = wl["P"], wl["R"], wl["L"], wl["horizon"], wl["substeps"]
     cfg = gga.make_cfg(L, N, R, seed=wl["seed"], substeps=S, dose_cap=wl["dose_cap"])
     params = gga.make_params(md)
@@ -441,7 +462,8 @@ def main():
         "site_steps_per_s": site_steps / (ms_per_step / 1000.0),
         "mean_fitness": float(fit.mean()),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "Top/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "unit": "Top/s", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": measured_traffic() if args.workload == "batched" else None,
                      "kernel": "sim_kernel", "kernel_ms": kernel_s * 1000.0},
     }
     if not args.no_cpu_baseline:

@@ -295,6 +295,55 @@ def surrogate_bench(gga, workloads, md, args):
     }
 
 
+def mlp_bench(gga, workloads, md, args):
+    """The surrogate's kernels: inference on 65,536 protocols and training
+    steps on batches of 4,096, random protocols of the batched workload's
+    alphabets.  FLOPs counted are the three MFMA layers' GEMMs (forward
+    2 B (128 + 512 + 512) 512; a training step 3x that, less the input-gradient
+    GEMM of the first layer, which is not computed)."""
+    import torch
+    K = 10
+    alpha = gga.make_alphabet(0.5, [1, 2, 3, 4, 5], list(range(6, 61, 6)), K, K, 20.0)
+    net = gga.mlp_net(seed=1)
+    out = {}
+    for label, B, train in (("inference", 65536, False), ("training", 4096, True)):
+        d, g, n = gga.population_random(alpha, B, K, seed=B)
+        t = torch.rand(B, device="cuda") * 100.0
+        work = gga.mlp_work(B)
+        pred = torch.empty(B, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        def once(step):
+            if train:
+                gga.mlp_train_step(net, d, g, n, t, step, 1e-4, work=work, loss=loss)
+            else:
+                gga.mlp_predict(net, d, g, n, work=work, out=pred)
+        for i in range(3):
+            once(i + 1)
+        torch.cuda.synchronize()
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(reps):
+            once(i + 4)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        fwd = 2.0 * B * (128 + 512 + 512) * 512
+        flops = fwd * (3.0 - 128.0 / (128 + 512 + 512)) if train else fwd
+        out[label] = {"batch": B, "ms": ms, "tflops": flops / ms / 1e9, "samples_per_s": B / ms * 1e3}
+        log(f"{label}: {ms:.3f} ms per call, {flops / ms / 1e9:.1f} TFLOP/s")
+    peak = 2.5e3
+    return {
+        "metric": "surrogate MLP throughput (bf16 MFMA, fp32 accumulate)", "value": out["inference"]["samples_per_s"],
+        "unit": "predictions/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic", "config": {"workload": "mlp-128x512x512x512x1"},
+        "inference": out["inference"], "training": out["training"],
+        "roofline": {"bound": "mfma", "achieved": out["inference"]["tflops"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": out["inference"]["tflops"] / peak, "traffic": None,
+                     "kernel": "whole forward pass (GEMMs and elementwise kernels)"},
+    }
+
+
 def uneven_bench(gga, workloads, md, args):
     """The uneven batch: 8192 protocols x 8 replicas, lattice side 64, 128 or
     256 and horizon 10-40 days per protocol, 3-40 fractions.  The autotuner
@@ -354,7 +403,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "ga", "surrogate", "uneven"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "ga", "surrogate", "uneven", "mlp"])
     ap.add_argument("--generations", type=int, default=200, help="GA workload: generations")
     ap.add_argument("--chunk", type=int, default=20, help="GA workload: generations per progress line")
     ap.add_argument("--candidates", type=int, default=5000, help="surrogate workload: candidates per generation")
@@ -392,6 +441,9 @@ def main():
     md = gga.load_model()
     if args.workload == "ga":
         print(json.dumps(ga_bench(gga, workloads, md, args)), flush=True)
+        return
+    if args.workload == "mlp":
+        print(json.dumps(mlp_bench(gga, workloads, md, args)), flush=True)
         return
     if args.workload == "uneven":
         print(json.dumps(uneven_bench(gga, workloads, md, args)), flush=True)

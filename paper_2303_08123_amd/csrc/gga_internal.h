@@ -60,6 +60,8 @@ constexpr SimVariant SIM_VARIANTS[] = {
     {128, 2, 4, 16, "L128 slabs of 64 rows, 4x2 x16 waves"},
     {256, 4, 4, 16, "L256 slabs of 64 rows, 4x4 x16 waves"},
     {256, 4, 8, 8, "L256 slabs of 64 rows, 8x4 x8 waves"},
+    {64, 1, 8, 8, "L64 resident 8x1 x8 waves"},
+    {64, 1, 16, 4, "L64 resident 16x1 x4 waves"},
 };
 constexpr int N_SIM_VARIANTS = sizeof(SIM_VARIANTS) / sizeof(SIM_VARIANTS[0]);
 constexpr bool variant_is_slab(int v) { return SIM_VARIANTS[v].rpt * SIM_VARIANTS[v].nw < SIM_VARIANTS[v].L; }

@@ -54,6 +54,8 @@ hipError_t launch_variant(int v, const SimArgs& a, int n_blocks, hipStream_t str
         case 0: return launch_sim<1, 4, 16>(a, n_blocks, stream);
         case 2: return launch_sim<2, 8, 16>(a, n_blocks, stream);
         case 3: return launch_sim<2, 16, 8>(a, n_blocks, stream);
+        case 7: return launch_sim<1, 8, 8>(a, n_blocks, stream);
+        case 8: return launch_sim<1, 16, 4>(a, n_blocks, stream);
         default:
             if (v >= 0 && v < N_SIM_VARIANTS && variant_is_slab(v)) return launch_slab_variant(v, a, n_blocks, stream);
             return hipErrorInvalidValue;

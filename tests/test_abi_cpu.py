@@ -124,8 +124,8 @@ def test_mlp_layout_matches_library(gga):
 
 def test_variant_table_and_choices(gga):
     vs = gga.variants()
-    assert [v[1] for v in vs] == [64, 64, 128, 128, 128, 256, 256]
-    assert [v[2] for v in vs] == [False, True, False, False, True, True, True]
+    assert [v[1] for v in vs] == [64, 64, 128, 128, 128, 256, 256, 64, 64]
+    assert [v[2] for v in vs] == [False, True, False, False, True, True, True, False, False]
     assert gga.get_variant(64) == 0 and gga.get_variant(128) == 2 and gga.get_variant(256) == 5
     assert gga.get_variant(128, resident_only=True) == 2
     with pytest.raises(gga.GGAError):

@@ -53,7 +53,7 @@ PROTOS = (np.array([[2.0, 3.0, 1.0], [1.5, 0.0, 2.5]], np.float32),
           np.array([3, 3], np.int32))
 
 
-@pytest.mark.parametrize("L,variant,reference", [(64, 1, 0), (128, 4, 2), (128, 3, 2)])
+@pytest.mark.parametrize("L,variant,reference", [(64, 1, 0), (64, 7, 0), (64, 8, 0), (128, 4, 2), (128, 3, 2)])
 def test_variants_agree_bit_for_bit(gga, model_dict, L, variant, reference):
     md = high_uptake(model_dict)
     prm = Params.from_dict(md)
@@ -201,8 +201,10 @@ def test_autotune_picks_a_variant_of_the_side(gga, model_dict):
     cfg = gga.make_cfg(64, 24, 2, seed=0, dose_cap=100.0)
     before = gga.simulate(model_dict, cfg, *dd)[0].cpu().numpy()
     v, ms = gga.autotune(model_dict, cfg, *dd)
-    assert gga.variants()[v][1] == 64 and set(ms) == {0, 1} and all(t > 0 for t in ms.values())
-    assert gga.get_variant(64) == v and gga.get_variant(64, resident_only=True) == 0
+    assert gga.variants()[v][1] == 64 and set(ms) == {0, 1, 7, 8} and all(t > 0 for t in ms.values())
+    res = min((t, i) for i, t in ms.items() if not gga.variants()[i][2])[1]
+    assert gga.get_variant(64) == v and gga.get_variant(64, resident_only=True) == res
     after = gga.simulate(model_dict, cfg, *dd)[0].cpu().numpy()
     assert np.array_equal(before, after)
     gga.set_variant(64, 0)
+    assert gga.get_variant(64, resident_only=True) == 0

@@ -567,7 +567,7 @@ MlpNet mlp_net(void* base) {
 size_t mlp_work_bytes(int B) {
     const size_t b = static_cast<size_t>(B);
     return align256(2 * b * MLP_IN) + 3 * align256(4 * b * MLP_HID) + 3 * align256(2 * b * MLP_HID) +
-           2 * align256(4 * b) + 2 * align256(2 * b * MLP_HID);
+           2 * align256(4 * b) + 2 * align256(2 * b * MLP_HID) + align256(4 * MLP_RED_CHUNKS * (MLP_HID + 1));
 }
 
 MlpWork mlp_work(void* base, int B) {
@@ -583,6 +583,7 @@ MlpWork mlp_work(void* base, int B) {
     w.dy = reinterpret_cast<float*>(c);
     c += align256(4 * b);
     for (int l = 0; l < 2; ++l) { w.dZ[l] = reinterpret_cast<__bf16*>(c); c += align256(2 * b * MLP_HID); }
+    w.part = reinterpret_cast<float*>(c);
     return w;
 }
 

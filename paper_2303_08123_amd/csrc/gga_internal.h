@@ -173,12 +173,14 @@ struct MlpNet {
     float *gW[3], *gb[3], *gw4, *gb4;
     __bf16 *W[3], *WT[3];        // bf16 copies, [K][N] and [N][K]
 };
+constexpr int MLP_RED_CHUNKS = 16;   // row chunks of the batch reductions (bias gradients)
 struct MlpWork {
     __bf16* X;
     float* Z[3];
     __bf16* H[3];
     float *y, *dy;
     __bf16* dZ[2];
+    float* part;                 // [MLP_RED_CHUNKS][MLP_HID + 1] partial column sums
 };
 size_t mlp_net_bytes();
 MlpNet mlp_net(void* base);

@@ -23,75 +23,94 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 32, PADK = 8;   // LDS rows of BK + PADK bf16
+constexpr int PADK = 8;   // LDS rows of BK + PADK bf16 (the pad spreads banks)
 
 __device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float x) {
     return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
+// One bf16x8 vector of an operand tile: elements (r, k0..k0+7) of a matrix
+// X(r, k) = X[r*s_r + k*s_k] with `rows` x `K` bounds, zero outside.
+__device__ __forceinline__ bf16x8 load8(const bf16* X, int s_r, int s_k, int rows, int K, int r, int k0) {
+    bf16x8 v;
+    if (s_k == 1 && r < rows && k0 + 8 <= K && ((s_r & 7) == 0)) {
+        v = *reinterpret_cast<const bf16x8*>(X + (size_t)r * s_r + k0);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + e;
+            v[e] = (r < rows && k < K) ? X[(size_t)r * s_r + (size_t)k * s_k] : (bf16)0.0f;
+        }
+    }
+    return v;
+}
+
 // C = A (M x K) * B (K x N) with element A(m,k) = A[m*sa_m + k*sa_k] and
-// B(k,n) = B[k*sb_k + n*sb_n]; 256 threads compute a 64 x 64 tile, each wave a
-// 32 x 32 quarter as 2 x 2 MFMA 16x16x32 blocks.
+// B(k,n) = B[k*sb_k + n*sb_n].  256 threads (2 x 2 waves) compute a
+// (32 WT) x (32 WT) tile, each wave WT x WT blocks of MFMA 16x16x32, over
+// k-tiles of BK.  The operand tiles are double-buffered in LDS: the global
+// loads of k-tile t + 1 are in flight while the MFMAs of k-tile t run.
+template <int WT, int BK>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(MlpGemm g) {
-    __shared__ bf16 As[BM][BK + PADK];
-    __shared__ bf16 Bs[BN][BK + PADK];      // stored as [n][k]
+    constexpr int TM = 32 * WT;                          // tile rows (= tile columns)
+    constexpr int VPT = TM * BK / 8 / 256;               // bf16x8 vectors per thread per operand
+    __shared__ bf16 As[2][TM][BK + PADK];
+    __shared__ bf16 Bs[2][TM][BK + PADK];                // stored as [n][k]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    floatx4 acc[2][2];
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
+    const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TM / 2);
+    floatx4 acc[WT][WT];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int lr = tid >> 2, lk = (tid & 3) * 8;   // loader: row 0..63, k offset 0..24
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
-        {   // A tile
-            const int m = m0 + lr;
-            bf16x8 v;
-            if (g.sa_k == 1 && m < g.M && k0 + lk + 8 <= g.K && ((g.sa_m & 7) == 0)) {
-                v = *reinterpret_cast<const bf16x8*>(g.A + (size_t)m * g.sa_m + k0 + lk);
-            } else {
+        for (int j = 0; j < WT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 ra[VPT], rb[VPT];
+    auto fetch = [&](int k0) {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int k = k0 + lk + e;
-                    v[e] = (m < g.M && k < g.K) ? g.A[(size_t)m * g.sa_m + (size_t)k * g.sa_k] : (bf16)0.0f;
-                }
-            }
-            *reinterpret_cast<bf16x8*>(&As[lr][lk]) = v;
+        for (int v = 0; v < VPT; ++v) {
+            const int idx = tid + v * 256, r = idx / (BK / 8), k = (idx % (BK / 8)) * 8;
+            ra[v] = load8(g.A, g.sa_m, g.sa_k, g.M, g.K, m0 + r, k0 + k);
+            rb[v] = load8(g.B, g.sb_n, g.sb_k, g.N, g.K, n0 + r, k0 + k);   // B^T(n, k) = B(k, n)
         }
-        {   // B tile, transposed into [n][k]
-            const int n = n0 + lr;
-            bf16x8 v;
-            if (g.sb_k == 1 && n < g.N && k0 + lk + 8 <= g.K && ((g.sb_n & 7) == 0)) {
-                v = *reinterpret_cast<const bf16x8*>(g.B + (size_t)n * g.sb_n + k0 + lk);
-            } else {
+    };
+    auto stash = [&](int buf) {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int k = k0 + lk + e;
-                    v[e] = (n < g.N && k < g.K) ? g.B[(size_t)k * g.sb_k + (size_t)n * g.sb_n] : (bf16)0.0f;
-                }
-            }
-            *reinterpret_cast<bf16x8*>(&Bs[lr][lk]) = v;
+        for (int v = 0; v < VPT; ++v) {
+            const int idx = tid + v * 256, r = idx / (BK / 8), k = (idx % (BK / 8)) * 8;
+            *reinterpret_cast<bf16x8*>(&As[buf][r][k]) = ra[v];
+            *reinterpret_cast<bf16x8*>(&Bs[buf][r][k]) = rb[v];
         }
-        __syncthreads();
-        const int fr = lane & 15, fk = (lane >> 4) * 8;
+    };
+    const int nk = (g.K + BK - 1) / BK;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int t = 0; t < nk; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < nk) fetch((t + 1) * BK);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + fr][fk]);
+        for (int kk = 0; kk < BK; kk += 32) {
+            bf16x8 b[WT];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + fr][fk]);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            for (int j = 0; j < WT; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + j * 16 + fr][kk + fk]);
+#pragma unroll
+            for (int i = 0; i < WT; ++i) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[buf][wm + i * 16 + fr][kk + fk]);
+#pragma unroll
+                for (int j = 0; j < WT; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
             }
         }
+        if (t + 1 < nk) stash(buf ^ 1);                  // the other buffer: last read before the previous barrier
         __syncthreads();
     }
     // D[4*(lane/16) + r][lane%16] of every 16x16 block
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WT; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
@@ -163,25 +182,39 @@ __global__ void out_bwd_kernel(const float* dy, const float* w4, const float* Z3
 }
 
 // Column sums of a [B][N] bf16 matrix (bias gradients), and dw4 / db4.
-__global__ void colsum_kernel(const bf16* D, int B, int N, float* out) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += (float)D[(size_t)b * N + n];
-    out[n] = s;
+// Column sums over the batch, in two deterministic passes: block (x, c) adds
+// rows of chunk c for 64 columns (4 row groups of one wave each, combined in
+// LDS in a fixed order); the final pass adds the chunks in order.  Row b is
+// weighted by w[b] when w is given, and column N then holds the sum of w.
+__global__ __launch_bounds__(256) void colsum_partial_kernel(const bf16* D, const float* w, int B, int N,
+                                                             float* part) {
+    __shared__ float red[4][64];
+    __shared__ float redw[4];
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + lane, c = blockIdx.y;
+    const int rows = (B + MLP_RED_CHUNKS - 1) / MLP_RED_CHUNKS;
+    const int b0 = c * rows, b1 = min(B, b0 + rows);
+    float s = 0.0f, sw = 0.0f;
+    for (int b = b0 + grp; b < b1; b += 4) {
+        const float wb = w ? w[b] : 1.0f;
+        if (col < N) s += (float)D[(size_t)b * N + col] * wb;
+        sw += wb;
+    }
+    red[grp][lane] = s;
+    if (lane == 0) redw[grp] = sw;
+    __syncthreads();
+    if (grp == 0) {
+        if (col < N) part[(size_t)c * (N + 1) + col] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        if (w && blockIdx.x == 0 && lane == 0) part[(size_t)c * (N + 1) + N] = ((redw[0] + redw[1]) + redw[2]) + redw[3];
+    }
 }
-__global__ void out_wgrad_kernel(const bf16* H3, const float* dy, int B, float* dw4, float* db4) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < MLP_HID) {
-        float s = 0.0f;
-        for (int b = 0; b < B; ++b) s += (float)H3[(size_t)b * MLP_HID + k] * dy[b];
-        dw4[k] = s;
-    }
-    if (k == MLP_HID) {
-        float s = 0.0f;
-        for (int b = 0; b < B; ++b) s += dy[b];
-        db4[0] = s;
-    }
+__global__ void colsum_final_kernel(const float* part, int N, int with_w, float* out, float* out_w) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n > N || (n == N && !with_w)) return;
+    float s = 0.0f;
+    for (int c = 0; c < MLP_RED_CHUNKS; ++c) s += part[(size_t)c * (N + 1) + n];
+    if (n < N) out[n] = s;
+    else out_w[0] = s;
 }
 
 // Adam with bias correction over the flat parameter vector.
@@ -261,7 +294,13 @@ unsigned blocks_for(long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 hipError_t launch_gemm(const MlpGemm& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gemm_bf16_kernel, dim3(blocks_for(g.N, BN), blocks_for(g.M, BM)), dim3(256), 0, s, g);
+    // 128 x 128 tiles when they still give the chip two workgroups per CU, else 64 x 64
+    if ((long)blocks_for(g.N, 128) * blocks_for(g.M, 128) >= 512)
+        hipLaunchKernelGGL((gemm_bf16_kernel<4, 32>), dim3(blocks_for(g.N, 128), blocks_for(g.M, 128)), dim3(256), 0, s,
+                           g);
+    else
+        hipLaunchKernelGGL((gemm_bf16_kernel<2, 32>), dim3(blocks_for(g.N, 64), blocks_for(g.M, 64)), dim3(256), 0, s,
+                           g);
     return hipGetLastError();
 }
 
@@ -296,7 +335,10 @@ hipError_t mlp_backward(const MlpNet& net, int B, const float* target, const Mlp
     hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, s, w.y, target, net.norm, B, w.dy, loss);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(out_wgrad_kernel, dim3(blocks_for(MLP_HID + 1, 256)), dim3(256), 0, s, w.H[2], w.dy, B,
+    // dw4 = H3^T dy, db4 = sum dy
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3(MLP_HID / 64, MLP_RED_CHUNKS), dim3(256), 0, s, w.H[2], w.dy, B,
+                       MLP_HID, w.part);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(blocks_for(MLP_HID + 1, 256)), dim3(256), 0, s, w.part, MLP_HID, 1,
                        net.gw4, net.gb4);
     hipLaunchKernelGGL(out_bwd_kernel, dim3(blocks_for((long)B * MLP_HID, 256)), dim3(256), 0, s, w.dy, net.w4,
                        w.Z[2], B, w.dZ[0]);
@@ -314,8 +356,10 @@ hipError_t mlp_backward(const MlpNet& net, int B, const float* target, const Mlp
         g.C = net.gW[l]; g.ldc = MLP_HID;
         e = launch_gemm(g, s);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(colsum_kernel, dim3(blocks_for(MLP_HID, 256)), dim3(256), 0, s, w.dZ[cur], B, MLP_HID,
-                           net.gb[l]);
+        hipLaunchKernelGGL(colsum_partial_kernel, dim3(MLP_HID / 64, MLP_RED_CHUNKS), dim3(256), 0, s, w.dZ[cur],
+                           nullptr, B, MLP_HID, w.part);
+        hipLaunchKernelGGL(colsum_final_kernel, dim3(blocks_for(MLP_HID, 256)), dim3(256), 0, s, w.part, MLP_HID, 0,
+                           net.gb[l], nullptr);
         e = hipGetLastError();
         if (l == 0 || e != hipSuccess) break;
         MlpGemm d{};

@@ -38,6 +38,12 @@ def protocols(B, K, seed):
     return dose, gap, nfrac
 
 
+@pytest.mark.parametrize("M,N,K,ta,tb", [(16390, 512, 512, False, True), (16390, 512, 200, True, False)])
+def test_gemm_large_tiles_match_float64(gga, M, N, K, ta, tb):
+    """Shapes with at least 512 tiles of 128 x 128 take the large-tile kernel."""
+    test_gemm_matches_float64(gga, M, N, K, ta, tb)
+
+
 @pytest.mark.parametrize("M,N,K", [(64, 64, 32), (100, 70, 45), (128, 512, 512), (513, 512, 1000)])
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
 def test_gemm_matches_float64(gga, M, N, K, ta, tb):
@@ -60,9 +66,10 @@ def _oracle_params(gga, net):
     return p
 
 
-def test_forward_matches_oracle(gga):
+@pytest.mark.parametrize("B", [300, 17000])          # 17000 rows: the large-tile GEMM
+def test_forward_matches_oracle(gga, B):
     net = gga.mlp_net(seed=3)
-    dose, gap, nfrac = protocols(300, 10, 1)
+    dose, gap, nfrac = protocols(B, 10, 1)
     dd = [torch.from_numpy(x).cuda() for x in (dose, gap, nfrac)]
     pred = gga.mlp_predict(net, *dd).cpu().numpy().astype(np.float64)
     params = _oracle_params(gga, net)

@@ -512,6 +512,7 @@ def main():
         "config": {"workload": wl["name"], "protocols": P, "replicas": R, "lattice": L,
                    "horizon_h": N, "substeps_per_h": S, "fractions": wl["K"], "dose_cap_gy": wl["dose_cap"]},
         "site_steps_per_s": site_steps / (ms_per_step / 1000.0),
+        "site_substeps_per_s_kernel": site_steps * S / kernel_s,
         "mean_fitness": float(fit.mean()),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "Top/s", "frac": achieved / VALU_PEAK_OPS,

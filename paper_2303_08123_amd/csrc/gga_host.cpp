@@ -1033,7 +1033,8 @@ hipError_t enqueue_uneven(const gga::SimArgs& base, const UnevenPlan& plan, char
             a.cells = (n & 1) ? cb : ca;
             a.fields_out = (n & 1) ? fa : fb;
             a.cells_out = (n & 1) ? ca : cb;
-            e = gga::launch_variant(g.variant, a, active * a.n_slabs, stream);
+            a.n_active = active;
+            e = gga::launch_variant(g.variant, a, gga::slab_blocks(active, a.n_slabs), stream);
         }
     }
     if (e == hipSuccess) e = gga::launch_fitness(live_d, P, R, fitness_d, stream);
@@ -1170,7 +1171,8 @@ int gga_state_run_variant(const gga_params* params, const gga_sim_cfg* cfg, int3
         a.cells = odd ? cells2_d : cells_d;
         a.fields_out = odd ? fields_d : fields2_d;
         a.cells_out = odd ? cells_d : cells2_d;
-        e = gga::launch_variant(variant, a, P * cfg->R * a.n_slabs, stream);
+        a.n_active = P * cfg->R;
+        e = gga::launch_variant(variant, a, gga::slab_blocks(a.n_active, a.n_slabs), stream);
     }
     if (e == hipSuccess && (nsteps & 1)) {         // the result is in the second buffers
         const size_t plane = (size_t)cfg->L * cfg->L, inst = (size_t)P * cfg->R;

@@ -27,8 +27,9 @@ struct SimArgs {
     const int32_t* generation;
     uint64_t seed;
     // Uneven batches.  Resident form: instance of block b = inst_list[b] (or b),
-    // steps = horizon[p] (or nsteps).  Slab form: instance = inst_list[b / n_slabs],
-    // slab b % n_slabs, one step n0 from fields/cells (state row b / n_slabs) to
+    // steps = horizon[p] (or nsteps).  Slab form: list position k and slab s of
+    // block b (XCD-grouped, see the kernel), instance inst_list[k], one step n0
+    // from fields/cells (state row k) to
     // fields_out/cells_out, the event table below instead of decoding the
     // protocol, and the live count added into live[inst] at step horizon[p] - 1.
     const int32_t* inst_list;
@@ -36,6 +37,7 @@ struct SimArgs {
     float* fields_out;
     uint16_t* cells_out;
     int32_t n_slabs;
+    int32_t n_active;         // slab form: list positions 0 .. n_active-1 run this launch
     int32_t slab_ys[16], slab_i0[16], slab_i1[16];   // first lattice row; own rows [i0, i1) of the slab
     const int32_t* ev_valid;  // [P]
     const int32_t* ev_count;  // [P]
@@ -69,7 +71,8 @@ constexpr bool variant_is_slab(int v) { return SIM_VARIANTS[v].rpt * SIM_VARIANT
 bool sim_supported(int L);
 // resident launch with the variant chosen for L (gga_simulate's path)
 hipError_t launch_simulation(const SimArgs& a, int L, int n_inst, hipStream_t stream);
-// launch variant v over n_blocks workgroups (slab form: n_blocks = instances * n_slabs)
+// launch variant v over n_blocks workgroups (slab form: n_blocks = slab_blocks(n_active, n_slabs))
+inline int slab_blocks(int n_active, int n_slabs) { return ((n_active + 7) / 8) * 8 * n_slabs; }
 hipError_t launch_variant(int v, const SimArgs& a, int n_blocks, hipStream_t stream);
 hipError_t launch_slab_variant(int v, const SimArgs& a, int n_blocks, hipStream_t stream);
 // process-wide variant choice per lattice side: resident (gga_simulate) and any (uneven batches)

@@ -177,10 +177,19 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     // instance (and slab) of this workgroup
-    int inst, slab = 0;
+    int inst, slab = 0, slab_row = 0;
     if constexpr (SLAB) {
-        inst = a.inst_list ? a.inst_list[blockIdx.x / a.n_slabs] : (int)(blockIdx.x / a.n_slabs);
-        slab = blockIdx.x - (blockIdx.x / a.n_slabs) * a.n_slabs;
+        // Workgroups are dealt to the 8 XCDs in turn (block b to XCD b mod 8), so
+        // all slabs of list position k go to XCD k mod 8: slab rows shared by
+        // neighbouring slabs come from that XCD's L2.  b = (y * 8 + x) with
+        // x = k mod 8 and y = (k / 8) * n_slabs + slab; positions past the list
+        // are idle workgroups.
+        const int x = (int)(blockIdx.x & 7u), y = (int)(blockIdx.x >> 3);
+        const int kq = y / a.n_slabs;
+        slab = y - kq * a.n_slabs;
+        slab_row = kq * 8 + x;
+        if (slab_row >= a.n_active) return;              // uniform across the workgroup
+        inst = a.inst_list ? a.inst_list[slab_row] : slab_row;
     } else {
         inst = a.inst_list ? a.inst_list[blockIdx.x] : (int)blockIdx.x;
     }
@@ -188,7 +197,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     const int r = inst - p * a.R;
     // state buffer row: the slab's list position; a library tumour (replica r
     // starts from library state r mod lib_n); or the instance
-    const int slot = SLAB ? (int)(blockIdx.x / a.n_slabs) : (a.lib_n ? r % a.lib_n : inst);
+    const int slot = SLAB ? slab_row : (a.lib_n ? r % a.lib_n : inst);
     // the slab's first lattice row, and its own (non-halo) rows [iy0, iy1) of the slab
     const int ys = SLAB ? a.slab_ys[slab] : 0;
     const int iy0 = SLAB ? a.slab_i0[slab] : 0, iy1 = SLAB ? a.slab_i1[slab] : RR;

@@ -145,7 +145,7 @@ hipError_t launch_fill(int32_t* p, int n, int32_t v, hipStream_t s);
 
 
 // ---- surrogate MLP
-enum : int { MLP_FWD = 0, MLP_BWD = 1, MLP_PLAIN = 2 };
+enum : int { MLP_FWD = 0, MLP_BWD = 1, MLP_PLAIN = 2, MLP_INFER = 3 };
 constexpr int MLP_IN = 128, MLP_HID = 512, MLP_FRAC = 40;
 constexpr long MLP_PARAMS = (long)MLP_IN * MLP_HID + MLP_HID + 2L * ((long)MLP_HID * MLP_HID + MLP_HID) + MLP_HID + 1;
 
@@ -192,7 +192,7 @@ MlpWork mlp_work(void* base, int B);
 
 hipError_t launch_gemm(const MlpGemm& g, hipStream_t s);
 hipError_t mlp_forward(const MlpNet& net, const float* dose, const int32_t* gap, const int32_t* nfrac, int B,
-                       int K, const MlpWork& w, float* pred, bool denorm, hipStream_t s);
+                       int K, const MlpWork& w, float* pred, bool predict, hipStream_t s);
 hipError_t mlp_backward(const MlpNet& net, int B, const float* target, const MlpWork& w, float* loss,
                         hipStream_t s);
 hipError_t mlp_adam_refresh(const MlpNet& net, int step, float lr, hipStream_t s);

@@ -25,9 +25,29 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int PADK = 8;   // LDS rows of BK + PADK bf16 (the pad spreads banks)
 
-__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// Phi(x), the standard normal CDF, through erf(|x| / sqrt 2) in the rational
+// form of Abramowitz & Stegun 7.1.26 (Hastings): erf(a) = 1 - p(t) exp(-a^2),
+// t = 1 / (1 + 0.3275911 a), |error| <= 1.5e-7, so Phi is within 7.5e-8 (plus
+// fp32 rounding) everywhere.  Branch-free: one reciprocal and one exp2 against
+// the two-branch polynomial of the library erff.  e receives exp(-x^2 / 2),
+// which the derivative also needs.
+__device__ __forceinline__ float phi_as(float x, float& e) {
+    const float a = fabsf(x) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
+    const float p =
+        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+    e = __builtin_amdgcn_exp2f(-a * a * 1.4426950408889634f);
+    return 0.5f + copysignf(0.5f * fmaf(-p, e, 1.0f), x);
+}
+// GELU(x) = x Phi(x); GELU'(x) = Phi(x) + x phi(x), phi(x) = exp(-x^2 / 2) / sqrt(2 pi)
+__device__ __forceinline__ float gelu_f(float x) {
+    float e;
+    return x * phi_as(x, e);
+}
 __device__ __forceinline__ float gelu_grad_f(float x) {
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+    float e;
+    const float p = phi_as(x, e);
+    return fmaf(x * 0.39894228040143268f, e, p);
 }
 
 // One bf16x8 vector of an operand tile: elements (r, k0..k0+7) of a matrix
@@ -117,8 +137,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(MlpGemm g) {
                 const int col = n0 + wn + j * 16 + (lane & 15);
                 if (row >= g.M || col >= g.N) continue;
                 float v = acc[i][j][r] + (g.bias ? g.bias[col] : 0.0f);
-                if (g.mode == MLP_FWD) {
-                    g.Z[(size_t)row * g.ldz + col] = v;
+                if (g.mode == MLP_FWD || g.mode == MLP_INFER) {
+                    if (g.mode == MLP_FWD) g.Z[(size_t)row * g.ldz + col] = v;
                     g.H[(size_t)row * g.ldh + col] = (bf16)gelu_f(v);
                 } else if (g.mode == MLP_BWD) {
                     g.H[(size_t)row * g.ldh + col] = (bf16)(v * gelu_grad_f(g.Z[(size_t)row * g.ldz + col]));
@@ -126,6 +146,112 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(MlpGemm g) {
                     g.C[(size_t)row * g.ldc + col] = v;
                 }
             }
+}
+
+// The same product when both operands run along K in memory (A [M][sa_m],
+// B^T [N][sb_n]; every layer of the forward pass and the data gradient of the
+// backward pass), K a multiple of 32 and N of the tile width: unguarded
+// 16-byte loads (rows beyond M clamp to row M - 1 and are not stored), and the
+// MFMA operands swapped so that each lane ends with four consecutive columns
+// of one row, stored as one 16-byte (f32) or 8-byte (bf16) write.  The tile
+// epilogue is fixed at compile time (MODE).  Workgroups are numbered so that
+// the N / TM column tiles of one row block run on one XCD (blocks are dealt
+// round-robin over the 8 XCDs), which then reads that row block once into its
+// L2.
+template <int WT, int MODE>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(MlpGemm g) {
+    constexpr int TM = 32 * WT, BK = 32, VPT = TM * BK / 8 / 256, CPR = BK / 8;
+    __shared__ bf16 As[2][TM][BK + PADK];
+    __shared__ bf16 Bs[2][TM][BK + PADK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ntn = g.N / TM;
+    int bid = blockIdx.x;
+    if ((gridDim.x & 7) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
+    const int m0 = (bid / ntn) * TM, n0 = (bid - (bid / ntn) * ntn) * TM;
+    const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TM / 2);
+    floatx4 acc[WT][WT];                                  // [column block][row block]
+#pragma unroll
+    for (int i = 0; i < WT; ++i)
+#pragma unroll
+        for (int j = 0; j < WT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bf16* pa[VPT];
+    const bf16* pb[VPT];
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) {
+        const int idx = tid + v * 256, r = idx / CPR, k = (idx % CPR) * 8;
+        pa[v] = g.A + (size_t)min(m0 + r, g.M - 1) * g.sa_m + k;
+        pb[v] = g.B + (size_t)(n0 + r) * g.sb_n + k;
+    }
+    bf16x8 ra[VPT], rb[VPT];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+            ra[v] = *reinterpret_cast<const bf16x8*>(pa[v] + k0);
+            rb[v] = *reinterpret_cast<const bf16x8*>(pb[v] + k0);
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+            const int idx = tid + v * 256, r = idx / CPR, k = (idx % CPR) * 8;
+            *reinterpret_cast<bf16x8*>(&As[buf][r][k]) = ra[v];
+            *reinterpret_cast<bf16x8*>(&Bs[buf][r][k]) = rb[v];
+        }
+    };
+    const int nk = g.K / BK;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int t = 0; t < nk; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < nk) fetch((t + 1) * BK);
+        bf16x8 a[WT];
+#pragma unroll
+        for (int j = 0; j < WT; ++j) a[j] = *reinterpret_cast<const bf16x8*>(&As[buf][wm + j * 16 + fr][fk]);
+#pragma unroll
+        for (int i = 0; i < WT; ++i) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + i * 16 + fr][fk]);
+#pragma unroll
+            for (int j = 0; j < WT; ++j)                    // D^T block: rows n, columns m
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a[j], acc[i][j], 0, 0, 0);
+        }
+        if (t + 1 < nk) stash(buf ^ 1);
+        __syncthreads();
+    }
+    typedef bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    // lane: row m0 + wm + 16 j + (lane & 15), columns n .. n + 3, n = n0 + wn + 16 i + 4 (lane >> 4)
+#pragma unroll
+    for (int j = 0; j < WT; ++j) {
+        const int row = m0 + wm + j * 16 + (lane & 15);
+        if (row >= g.M) continue;
+#pragma unroll
+        for (int i = 0; i < WT; ++i) {
+            const int col = n0 + wn + i * 16 + (lane >> 4) * 4;
+            float o[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
+            if (g.bias) {
+                const float4 bb = *reinterpret_cast<const float4*>(g.bias + col);
+                o[0] += bb.x; o[1] += bb.y; o[2] += bb.z; o[3] += bb.w;
+            }
+            if (MODE == MLP_PLAIN) {
+                *reinterpret_cast<float4*>(g.C + (size_t)row * g.ldc + col) = make_float4(o[0], o[1], o[2], o[3]);
+                continue;
+            }
+            if (MODE == MLP_FWD)
+                *reinterpret_cast<float4*>(g.Z + (size_t)row * g.ldz + col) = make_float4(o[0], o[1], o[2], o[3]);
+            if (MODE == MLP_BWD) {
+                const float4 z = *reinterpret_cast<const float4*>(g.Z + (size_t)row * g.ldz + col);
+                o[0] *= gelu_grad_f(z.x); o[1] *= gelu_grad_f(z.y); o[2] *= gelu_grad_f(z.z); o[3] *= gelu_grad_f(z.w);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) o[q] = gelu_f(o[q]);
+            }
+            bf16x4 h;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) h[q] = (bf16)o[q];
+            *reinterpret_cast<bf16x4*>(g.H + (size_t)row * g.ldh + col) = h;
+        }
+    }
 }
 
 // Features of protocol b: for fraction j < 40, (dose/5, gap/60, 1) if present.
@@ -292,10 +418,42 @@ unsigned blocks_for(long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
+namespace {
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Operands that run along K, K a multiple of 32, N of the tile width, and
+// 16-byte alignment of every row the epilogue and the loads touch.
+bool nt_eligible(const MlpGemm& g, int TM) {
+    if (g.sa_k != 1 || g.sb_k != 1 || g.K <= 0 || g.K % 32 || g.N % TM) return false;
+    if (g.sa_m % 8 || g.sb_n % 8 || !aligned16(g.A) || !aligned16(g.B)) return false;
+    if (g.bias && !aligned16(g.bias)) return false;
+    if (g.mode == MLP_PLAIN) return aligned16(g.C) && g.ldc % 4 == 0;
+    if (g.mode != MLP_INFER && (!aligned16(g.Z) || g.ldz % 4)) return false;
+    return aligned16(g.H) && g.ldh % 4 == 0;
+}
+
+template <int WT>
+void launch_nt(const MlpGemm& g, hipStream_t s) {
+    const dim3 grid(blocks_for(g.M, 32 * WT) * (g.N / (32 * WT)));
+    switch (g.mode) {
+        case MLP_FWD: hipLaunchKernelGGL((gemm_nt_kernel<WT, MLP_FWD>), grid, dim3(256), 0, s, g); break;
+        case MLP_INFER: hipLaunchKernelGGL((gemm_nt_kernel<WT, MLP_INFER>), grid, dim3(256), 0, s, g); break;
+        case MLP_BWD: hipLaunchKernelGGL((gemm_nt_kernel<WT, MLP_BWD>), grid, dim3(256), 0, s, g); break;
+        default: hipLaunchKernelGGL((gemm_nt_kernel<WT, MLP_PLAIN>), grid, dim3(256), 0, s, g); break;
+    }
+}
+}  // namespace
+
 hipError_t launch_gemm(const MlpGemm& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     // 128 x 128 tiles when they still give the chip two workgroups per CU, else 64 x 64
-    if ((long)blocks_for(g.N, 128) * blocks_for(g.M, 128) >= 512)
+    const bool large = (long)blocks_for(g.N, 128) * blocks_for(g.M, 128) >= 512;
+    if (nt_eligible(g, large ? 128 : 64)) {
+        if (large) launch_nt<4>(g, s);
+        else launch_nt<2>(g, s);
+        return hipGetLastError();
+    }
+    if (large)
         hipLaunchKernelGGL((gemm_bf16_kernel<4, 32>), dim3(blocks_for(g.N, 128), blocks_for(g.M, 128)), dim3(256), 0, s,
                            g);
     else
@@ -305,7 +463,7 @@ hipError_t launch_gemm(const MlpGemm& g, hipStream_t s) {
 }
 
 hipError_t mlp_forward(const MlpNet& net, const float* dose, const int32_t* gap, const int32_t* nfrac, int B,
-                       int K, const MlpWork& w, float* pred, bool denorm, hipStream_t s) {
+                       int K, const MlpWork& w, float* pred, bool predict, hipStream_t s) {
     hipLaunchKernelGGL(encode_kernel, dim3(blocks_for((long)B * MLP_IN, 256)), dim3(256), 0, s, dose, gap, nfrac,
                        B, K, w.X);
     hipError_t e = hipGetLastError();
@@ -317,7 +475,7 @@ hipError_t mlp_forward(const MlpNet& net, const float* dose, const int32_t* gap,
         g.A = in; g.sa_m = kin; g.sa_k = 1;
         g.B = net.WT[l]; g.sb_k = 1; g.sb_n = kin;           // B(k, n) = W^T[n][k]
         g.bias = net.b[l];
-        g.mode = MLP_FWD;
+        g.mode = predict ? MLP_INFER : MLP_FWD;          // a prediction keeps no pre-activations
         g.Z = w.Z[l]; g.ldz = MLP_HID;
         g.H = w.H[l]; g.ldh = MLP_HID;
         e = launch_gemm(g, s);
@@ -326,7 +484,7 @@ hipError_t mlp_forward(const MlpNet& net, const float* dose, const int32_t* gap,
     }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(out_fwd_kernel, dim3(blocks_for(B, 4)), dim3(256), 0, s, w.H[2], net.w4, net.b4, B, pred,
-                       denorm ? net.norm : nullptr);
+                       predict ? net.norm : nullptr);
     return hipGetLastError();
 }
 

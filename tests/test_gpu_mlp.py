@@ -5,8 +5,9 @@ and accumulates in fp32, so its error is a few fp32 roundings of the sum of
 |products|; the network also rounds every hidden activation (and, backwards,
 every dZ) to bf16, a relative error of at most 2^-9 per value.  Forward
 outputs are compared against the first-order bound of those roundings carried
-through the layers (|gelu'| <= 1.13); gradients per tensor at 5 % relative
-Frobenius error with cosine similarity above 0.998.
+through the layers (|gelu'| <= 1.13), plus the error of the rational erf the
+kernels evaluate Phi with; gradients per tensor at 5 % relative Frobenius
+error with cosine similarity above 0.998.
 """
 import numpy as np
 import pytest
@@ -66,7 +67,9 @@ def _oracle_params(gga, net):
     return p
 
 
-@pytest.mark.parametrize("B", [300, 17000])          # 17000 rows: the large-tile GEMM
+# 17000 and 16600 rows take the 128 x 128 tiles (16600: an even number of row
+# blocks, so the XCD-grouped block order); 300 the 64 x 64 ones
+@pytest.mark.parametrize("B", [300, 16600, 17000])
 def test_forward_matches_oracle(gga, B):
     net = gga.mlp_net(seed=3)
     dose, gap, nfrac = protocols(B, 10, 1)
@@ -74,20 +77,23 @@ def test_forward_matches_oracle(gga, B):
     pred = gga.mlp_predict(net, *dd).cpu().numpy().astype(np.float64)
     params = _oracle_params(gga, net)
     X = bf16(omlp.encode(dose, gap, nfrac))
-    y, (_, _, H1, _, H2, _, H3) = omlp.forward(params, X)
+    y, (_, Z1, H1, Z2, H2, Z3, H3) = omlp.forward(params, X)
     u = 2.0 ** -9                                    # bf16 rounding, relative
-    e1 = u * np.abs(H1)
-    e2 = u * np.abs(H2) + 1.13 * (e1 @ np.abs(params[2]))
-    e3 = u * np.abs(H3) + 1.13 * (e2 @ np.abs(params[4]))
+    # the kernels take Phi from a rational erf with |error| <= 1.5e-7 (Phi
+    # within 7.5e-8; 2e-7 with the fp32 roundings): GELU(z) within dphi |z|
+    dphi = 2e-7
+    e1 = u * np.abs(H1) + dphi * np.abs(Z1)
+    e2 = u * np.abs(H2) + dphi * np.abs(Z2) + 1.13 * (e1 @ np.abs(params[2]))
+    e3 = u * np.abs(H3) + dphi * np.abs(Z3) + 1.13 * (e2 @ np.abs(params[4]))
     bound = e3 @ np.abs(params[6]) + 1e-6 * (np.abs(H3) @ np.abs(params[6]))
     err = np.abs(pred - y)
     assert np.all(err <= bound), (err.max(), bound.min())
     assert err.max() < 0.3 * bound.max()             # the bound is not vacuous here
 
 
-def test_gradients_match_oracle(gga):
+@pytest.mark.parametrize("B", [256, 16600])          # both tile sizes of the forward and data-gradient GEMMs
+def test_gradients_match_oracle(gga, B):
     net = gga.mlp_net(seed=5)
-    B = 256
     dose, gap, nfrac = protocols(B, 10, 2)
     rng = np.random.default_rng(9)
     target = rng.normal(0.0, 1.0, size=B).astype(np.float32)

@@ -296,6 +296,8 @@ int gga_ga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cf
  * bf16 copies W1 [128][512], W1^T, W2 [512][512], W2^T, W3, W3^T.  Parameter
  * order: W1 [128][512], b1[512], W2 [512][512], b2, W3 [512][512], b3,
  * w4[512], b4[1].  Work buffer: gga_mlp_work_bytes(B) bytes for batch B.
+ * Net and work buffers (and the screened GA's workspace) must be 16-byte
+ * aligned, as hipMalloc returns them: GGA_E_ARG otherwise.
  */
 size_t gga_mlp_net_bytes(void);
 size_t gga_mlp_work_bytes(int32_t B);

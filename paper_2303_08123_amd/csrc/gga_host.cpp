@@ -590,9 +590,11 @@ MlpWork mlp_work(void* base, int B) {
 }  // namespace gga
 
 namespace {
+bool misaligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) != 0; }
+
 int mlp_check(const void* net, int32_t B, int32_t K, const float* dose, const int32_t* gap, const int32_t* nfrac,
               const void* work, size_t work_bytes) {
-    if (!net || B < 0 || K < 0 || K > GGA_KMAX) return GGA_E_ARG;
+    if (!net || misaligned16(net) || misaligned16(work) || B < 0 || K < 0 || K > GGA_KMAX) return GGA_E_ARG;
     if (B > 0 && (!nfrac || !work || (K > 0 && (!dose || !gap)))) return GGA_E_ARG;
     if ((long long)B * gga::MLP_HID > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
     if (B > 0 && work_bytes < gga::mlp_work_bytes(B)) return GGA_E_ARG;
@@ -607,7 +609,7 @@ size_t gga_mlp_net_bytes(void) { return gga::mlp_net_bytes(); }
 size_t gga_mlp_work_bytes(int32_t B) { return B < 0 ? 0 : gga::mlp_work_bytes(B); }
 
 int gga_mlp_init(void* net_d, uint64_t seed, hipStream_t stream) {
-    if (!net_d) return GGA_E_ARG;
+    if (!net_d || misaligned16(net_d)) return GGA_E_ARG;
     const gga::MlpNet net = gga::mlp_net(net_d);
     hipError_t e = gga::mlp_init(net, seed, stream);
     // normalisation defaults to (0, 1) until gga_mlp_set_norm; Adam step 0
@@ -618,7 +620,7 @@ int gga_mlp_init(void* net_d, uint64_t seed, hipStream_t stream) {
 }
 
 int gga_mlp_set_norm(void* net_d, const float* target_d, int32_t n, hipStream_t stream) {
-    if (!net_d || n < 1 || !target_d) return GGA_E_ARG;
+    if (!net_d || misaligned16(net_d) || n < 1 || !target_d) return GGA_E_ARG;
     const hipError_t e = gga::mlp_set_norm(gga::mlp_net(net_d), target_d, n, stream);
     return e == hipSuccess ? GGA_OK : hip_fail(e);
 }
@@ -852,6 +854,7 @@ int gga_sga_generation(const gga_params* params, const gga_sim_cfg* cfg, const g
     gga::GaArgs ga_args;
     if ((rc = check_ga(ga, a, N, K, &ga_args))) return rc;
     if (!pop_dose_d || !pop_gap_d || !pop_fit_d || !ws_d || (sga->screen && !net_d)) return GGA_E_ARG;
+    if (misaligned16(ws_d) || (sga->screen && misaligned16(net_d))) return GGA_E_ARG;
     if (ws_bytes < sga_layout(d, nullptr, nullptr) || hist_cap < 0 || (hist_cap > 0 && !hist_d)) return GGA_E_ARG;
     SgaWorkspace w;
     sga_layout(d, &w, ws_d);
@@ -874,6 +877,7 @@ int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_c
     if ((rc = check_ga(ga, a, N, K, &ga_args))) return rc;
     if (!pop_dose_d || !pop_gap_d || !pop_fit_d || !ws_d || (sga->screen && !net_d) || n_gen < 0 || g0 < 0)
         return GGA_E_ARG;
+    if (misaligned16(ws_d) || (sga->screen && misaligned16(net_d))) return GGA_E_ARG;
     if ((long long)g0 + n_gen > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
     if (ws_bytes < sga_layout(d, nullptr, nullptr) || (n_gen > 0 && !hist_d)) return GGA_E_ARG;
     SgaWorkspace w;

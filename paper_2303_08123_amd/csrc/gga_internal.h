@@ -145,7 +145,7 @@ hipError_t launch_fill(int32_t* p, int n, int32_t v, hipStream_t s);
 
 
 // ---- surrogate MLP
-enum : int { MLP_FWD = 0, MLP_BWD = 1, MLP_PLAIN = 2, MLP_INFER = 3 };
+enum : int { MLP_FWD = 0, MLP_BWD = 1, MLP_PLAIN = 2, MLP_INFER = 3, MLP_OUT = 4 };
 constexpr int MLP_IN = 128, MLP_HID = 512, MLP_FRAC = 40;
 constexpr long MLP_PARAMS = (long)MLP_IN * MLP_HID + MLP_HID + 2L * ((long)MLP_HID * MLP_HID + MLP_HID) + MLP_HID + 1;
 
@@ -163,6 +163,7 @@ struct MlpGemm {
     long ldh;
     float* C;
     long ldc;
+    const float* w4;             // MLP_OUT: output weights; C receives partial dot products
 };
 
 // Views into a net buffer (see mlp_net()).

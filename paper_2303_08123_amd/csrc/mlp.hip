@@ -157,7 +157,9 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(MlpGemm g) {
 // epilogue is fixed at compile time (MODE).  Workgroups are numbered so that
 // the N / TM column tiles of one row block run on one XCD (blocks are dealt
 // round-robin over the 8 XCDs), which then reads that row block once into its
-// L2.
+// L2.  MLP_OUT (the last hidden layer of a prediction) stores no activations:
+// it writes, per row and per chunk of TM / 2 columns, the partial dot product
+// of the bf16-rounded GELU outputs with w4 into C[row][chunk].
 template <int WT, int MODE>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(MlpGemm g) {
     constexpr int TM = 32 * WT, BK = 32, VPT = TM * BK / 8 / 256, CPR = BK / 8;
@@ -224,7 +226,8 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(MlpGemm g) {
 #pragma unroll
     for (int j = 0; j < WT; ++j) {
         const int row = m0 + wm + j * 16 + (lane & 15);
-        if (row >= g.M) continue;
+        if (row >= g.M) continue;                         // the four lanes of a row share its fate
+        float dot = 0.0f;
 #pragma unroll
         for (int i = 0; i < WT; ++i) {
             const int col = n0 + wn + i * 16 + (lane >> 4) * 4;
@@ -235,6 +238,14 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(MlpGemm g) {
             }
             if (MODE == MLP_PLAIN) {
                 *reinterpret_cast<float4*>(g.C + (size_t)row * g.ldc + col) = make_float4(o[0], o[1], o[2], o[3]);
+                continue;
+            }
+            if (MODE == MLP_OUT) {                        // this lane's share of H3 . w4 (H3 rounded to bf16)
+                const float4 w = *reinterpret_cast<const float4*>(g.w4 + col);
+                dot = fmaf((float)(bf16)gelu_f(o[0]), w.x, dot);
+                dot = fmaf((float)(bf16)gelu_f(o[1]), w.y, dot);
+                dot = fmaf((float)(bf16)gelu_f(o[2]), w.z, dot);
+                dot = fmaf((float)(bf16)gelu_f(o[3]), w.w, dot);
                 continue;
             }
             if (MODE == MLP_FWD)
@@ -251,22 +262,36 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(MlpGemm g) {
             for (int q = 0; q < 4; ++q) h[q] = (bf16)o[q];
             *reinterpret_cast<bf16x4*>(g.H + (size_t)row * g.ldh + col) = h;
         }
+        if (MODE == MLP_OUT) {
+            // lanes l, l + 16, l + 32, l + 48 hold one row: their sum is the
+            // wave's partial over its TM / 2 columns, chunk (n0 + wn) / (TM / 2)
+            dot += __shfl_xor(dot, 16, 64);
+            dot += __shfl_xor(dot, 32, 64);
+            if ((lane >> 4) == 0) g.C[(size_t)row * g.ldc + (n0 + wn) / (TM / 2)] = dot;
+        }
     }
 }
 
 // Features of protocol b: for fraction j < 40, (dose/5, gap/60, 1) if present.
+// One thread per 8 consecutive features, stored as one 16-byte vector.
 __global__ void encode_kernel(const float* dose, const int32_t* gap, const int32_t* nfrac, int B, int K,
                               bf16* X) {
+    constexpr int V = MLP_IN / 8;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= B * MLP_IN) return;
-    const int b = idx / MLP_IN, f = idx - b * MLP_IN;
-    const int j = f / 3, part = f - 3 * j;
-    float v = 0.0f;
-    if (j < MLP_FRAC && j < K && j < nfrac[b]) {
-        v = part == 0 ? dose[(size_t)b * K + j] * (1.0f / 5.0f)
-                      : part == 1 ? (float)gap[(size_t)b * K + j] * (1.0f / 60.0f) : 1.0f;
+    if (idx >= B * V) return;
+    const int b = idx / V, f0 = (idx - b * V) * 8;
+    const int nf = min(min(MLP_FRAC, K), nfrac[b]);
+    bf16x8 x;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int f = f0 + e, j = f / 3, part = f - 3 * j;
+        float v = 0.0f;
+        if (j < nf)
+            v = part == 0 ? dose[(size_t)b * K + j] * (1.0f / 5.0f)
+                          : part == 1 ? (float)gap[(size_t)b * K + j] * (1.0f / 60.0f) : 1.0f;
+        x[e] = (bf16)v;
     }
-    X[idx] = (bf16)v;
+    *reinterpret_cast<bf16x8*>(X + (size_t)b * MLP_IN + f0) = x;
 }
 
 // y[b] = H3[b] . w4 + b4 (one wave per sample); optionally de-normalised.
@@ -278,6 +303,16 @@ __global__ void out_fwd_kernel(const bf16* H3, const float* w4, const float* b4,
     for (int k = lane; k < MLP_HID; k += 64) s += (float)H3[(size_t)b * MLP_HID + k] * w4[k];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) y[b] = norm ? (s + b4[0]) * norm[1] + norm[0] : s + b4[0];
+}
+
+// y[b] = sum over chunks c (in order) of part[b][c] + b4; optionally de-normalised.
+__global__ void out_sum_kernel(const float* part, int nchunk, int ld, const float* b4, int B, float* y,
+                               const float* norm) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float s = 0.0f;
+    for (int c = 0; c < nchunk; ++c) s += part[(size_t)b * ld + c];
+    y[b] = norm ? (s + b4[0]) * norm[1] + norm[0] : s + b4[0];
 }
 
 // dy = 2 (y - t') / B with t' = (t - mu) / sigma; loss = mean (y - t')^2.
@@ -428,6 +463,7 @@ bool nt_eligible(const MlpGemm& g, int TM) {
     if (g.sa_m % 8 || g.sb_n % 8 || !aligned16(g.A) || !aligned16(g.B)) return false;
     if (g.bias && !aligned16(g.bias)) return false;
     if (g.mode == MLP_PLAIN) return aligned16(g.C) && g.ldc % 4 == 0;
+    if (g.mode == MLP_OUT) return g.C && g.w4 && aligned16(g.w4) && g.ldc >= g.N / (TM / 2);
     if (g.mode != MLP_INFER && (!aligned16(g.Z) || g.ldz % 4)) return false;
     return aligned16(g.H) && g.ldh % 4 == 0;
 }
@@ -439,20 +475,24 @@ void launch_nt(const MlpGemm& g, hipStream_t s) {
         case MLP_FWD: hipLaunchKernelGGL((gemm_nt_kernel<WT, MLP_FWD>), grid, dim3(256), 0, s, g); break;
         case MLP_INFER: hipLaunchKernelGGL((gemm_nt_kernel<WT, MLP_INFER>), grid, dim3(256), 0, s, g); break;
         case MLP_BWD: hipLaunchKernelGGL((gemm_nt_kernel<WT, MLP_BWD>), grid, dim3(256), 0, s, g); break;
+        case MLP_OUT: hipLaunchKernelGGL((gemm_nt_kernel<WT, MLP_OUT>), grid, dim3(256), 0, s, g); break;
         default: hipLaunchKernelGGL((gemm_nt_kernel<WT, MLP_PLAIN>), grid, dim3(256), 0, s, g); break;
     }
 }
 }  // namespace
 
+// 128 x 128 tiles when they still give the chip two workgroups per CU, else 64 x 64
+int gemm_tile(const MlpGemm& g) { return (long)blocks_for(g.N, 128) * blocks_for(g.M, 128) >= 512 ? 128 : 64; }
+
 hipError_t launch_gemm(const MlpGemm& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    // 128 x 128 tiles when they still give the chip two workgroups per CU, else 64 x 64
-    const bool large = (long)blocks_for(g.N, 128) * blocks_for(g.M, 128) >= 512;
+    const bool large = gemm_tile(g) == 128;
     if (nt_eligible(g, large ? 128 : 64)) {
         if (large) launch_nt<4>(g, s);
         else launch_nt<2>(g, s);
         return hipGetLastError();
     }
+    if (g.mode == MLP_OUT) return hipErrorInvalidValue;    // only the K-contiguous kernel fuses the output layer
     if (large)
         hipLaunchKernelGGL((gemm_bf16_kernel<4, 32>), dim3(blocks_for(g.N, 128), blocks_for(g.M, 128)), dim3(256), 0, s,
                            g);
@@ -464,11 +504,11 @@ hipError_t launch_gemm(const MlpGemm& g, hipStream_t s) {
 
 hipError_t mlp_forward(const MlpNet& net, const float* dose, const int32_t* gap, const int32_t* nfrac, int B,
                        int K, const MlpWork& w, float* pred, bool predict, hipStream_t s) {
-    hipLaunchKernelGGL(encode_kernel, dim3(blocks_for((long)B * MLP_IN, 256)), dim3(256), 0, s, dose, gap, nfrac,
-                       B, K, w.X);
+    hipLaunchKernelGGL(encode_kernel, dim3(blocks_for((long)B * (MLP_IN / 8), 256)), dim3(256), 0, s, dose, gap,
+                       nfrac, B, K, w.X);
     hipError_t e = hipGetLastError();
     const bf16* in = w.X;
-    int kin = MLP_IN;
+    int kin = MLP_IN, nchunk = 0;
     for (int l = 0; l < 3 && e == hipSuccess; ++l) {
         MlpGemm g{};
         g.M = B; g.N = MLP_HID; g.K = kin;
@@ -478,13 +518,23 @@ hipError_t mlp_forward(const MlpNet& net, const float* dose, const int32_t* gap,
         g.mode = predict ? MLP_INFER : MLP_FWD;          // a prediction keeps no pre-activations
         g.Z = w.Z[l]; g.ldz = MLP_HID;
         g.H = w.H[l]; g.ldh = MLP_HID;
+        if (predict && l == 2) {                          // output layer fused: partial dot products in Z[0]
+            g.mode = MLP_OUT;
+            g.w4 = net.w4;
+            g.C = w.Z[0]; g.ldc = 16;
+            nchunk = MLP_HID / (gemm_tile(g) / 2);
+        }
         e = launch_gemm(g, s);
         in = w.H[l];
         kin = MLP_HID;
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(out_fwd_kernel, dim3(blocks_for(B, 4)), dim3(256), 0, s, w.H[2], net.w4, net.b4, B, pred,
-                       predict ? net.norm : nullptr);
+    if (predict)
+        hipLaunchKernelGGL(out_sum_kernel, dim3(blocks_for(B, 256)), dim3(256), 0, s, w.Z[0], nchunk, 16, net.b4, B,
+                           pred, net.norm);
+    else
+        hipLaunchKernelGGL(out_fwd_kernel, dim3(blocks_for(B, 4)), dim3(256), 0, s, w.H[2], net.w4, net.b4, B, pred,
+                           nullptr);
     return hipGetLastError();
 }
 

@@ -198,3 +198,18 @@ def test_ga_operator_settings_are_checked_before_any_launch(gga):
                                 fake, fake, None) == -1
     g = gga.make_ga(mutation=("gene", "swap", "raise"), crossover="uniform")
     assert g.mutation == 7 and g.crossover == 3
+
+
+def test_mlp_buffers_must_be_16_byte_aligned(gga):
+    """Net, work and screened-GA workspace pointers off a 16-byte boundary are
+    refused before any launch (the MLP kernels load and store 16 bytes at a time)."""
+    ok, off = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x10008)
+    B, K = 4, 10
+    wb = gga.LIB.gga_mlp_work_bytes(B)
+    assert gga.LIB.gga_mlp_init(off, 1, None) == -1
+    assert gga.LIB.gga_mlp_set_norm(off, ok, 4, None) == -1
+    assert gga.LIB.gga_mlp_predict(off, ok, ok, ok, B, K, ok, wb, ok, None) == -1
+    assert gga.LIB.gga_mlp_predict(ok, ok, ok, ok, B, K, off, wb, ok, None) == -1
+    assert gga.LIB.gga_mlp_grad(ok, ok, ok, ok, ok, B, K, off, wb, None, None) == -1
+    assert gga.LIB.gga_mlp_train_step(off, ok, ok, ok, ok, B, K, 1, ctypes.c_float(1e-3), ok, wb, None,
+                                      None) == -1

@@ -10,6 +10,8 @@
 // Parameter order: W1 [128][512], b1, W2 [512][512], b2, W3 [512][512], b3,
 // w4 [512], b4 [1].
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -272,6 +274,98 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(MlpGemm g) {
     }
 }
 
+// C = A (M x K) * B (K x N) when both operands run along M and N in memory
+// (A(m, k) = A[k sa_k + m], B(k, n) = B[k sb_k + n]: the weight gradients
+// H^T dZ), over the k range [k0, k1) of split blockIdx.y, M and N multiples of
+// the tile.  16-byte loads of 8 consecutive rows (or columns) at one k are
+// transposed into the [row][k] LDS tiles the MFMA fragments read; rows of k
+// past k1 load as zero.  Each split writes its own f32 slice C + split * ldp
+// (a fixed-order sum over the splits follows when there are several).
+template <int WT>
+__global__ __launch_bounds__(256) void gemm_tn_kernel(MlpGemm g, int kchunk, long ldp) {
+    constexpr int TM = 32 * WT, BK = 32, VPT = TM * BK / 8 / 256, VPR = TM / 8;
+    __shared__ bf16 As[2][TM][BK + PADK];
+    __shared__ bf16 Bs[2][TM][BK + PADK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ntn = g.N / TM;
+    const int m0 = (blockIdx.x / ntn) * TM, n0 = (blockIdx.x - (blockIdx.x / ntn) * ntn) * TM;
+    const int kb = blockIdx.y * kchunk, ke = min(g.K, kb + kchunk);
+    const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TM / 2);
+    floatx4 acc[WT][WT];                                  // [column block][row block]
+#pragma unroll
+    for (int i = 0; i < WT; ++i)
+#pragma unroll
+        for (int j = 0; j < WT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 ra[VPT], rb[VPT];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+            const int idx = tid + v * 256, k = k0 + idx / VPR, r = (idx % VPR) * 8;
+            const bool in = k < ke;
+            const bf16x8 z = {};
+            ra[v] = in ? *reinterpret_cast<const bf16x8*>(g.A + (size_t)k * g.sa_k + m0 + r) : z;
+            rb[v] = in ? *reinterpret_cast<const bf16x8*>(g.B + (size_t)k * g.sb_k + n0 + r) : z;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) {
+            const int idx = tid + v * 256, k = idx / VPR, r = (idx % VPR) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                As[buf][r + e][k] = ra[v][e];
+                Bs[buf][r + e][k] = rb[v][e];
+            }
+        }
+    };
+    const int nk = (ke - kb + BK - 1) / BK;
+    if (nk > 0) {
+        fetch(kb);
+        stash(0);
+    }
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int t = 0; t < nk; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < nk) fetch(kb + (t + 1) * BK);
+        bf16x8 a[WT];
+#pragma unroll
+        for (int j = 0; j < WT; ++j) a[j] = *reinterpret_cast<const bf16x8*>(&As[buf][wm + j * 16 + fr][fk]);
+#pragma unroll
+        for (int i = 0; i < WT; ++i) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + i * 16 + fr][fk]);
+#pragma unroll
+            for (int j = 0; j < WT; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a[j], acc[i][j], 0, 0, 0);
+        }
+        if (t + 1 < nk) stash(buf ^ 1);
+        __syncthreads();
+    }
+    float* C = g.C + (size_t)blockIdx.y * ldp;
+#pragma unroll
+    for (int j = 0; j < WT; ++j) {
+        const int row = m0 + wm + j * 16 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < WT; ++i) {
+            const int col = n0 + wn + i * 16 + (lane >> 4) * 4;
+            *reinterpret_cast<float4*>(C + (size_t)row * g.ldc + col) =
+                make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+        }
+    }
+}
+
+// out[i] = sum over splits s = 0 .. S-1 (in order) of part[s * n + i], 4 per thread
+__global__ void split_sum_kernel(const float* part, int S, long n, float* out) {
+    const long i = ((long)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i >= n) return;
+    float4 acc = *reinterpret_cast<const float4*>(part + i);
+    for (int s = 1; s < S; ++s) {
+        const float4 v = *reinterpret_cast<const float4*>(part + (size_t)s * n + i);
+        acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+    }
+    *reinterpret_cast<float4*>(out + i) = acc;
+}
+
 // Features of protocol b: for fraction j < 40, (dose/5, gap/60, 1) if present.
 // One thread per 8 consecutive features, stored as one 16-byte vector.
 __global__ void encode_kernel(const float* dose, const int32_t* gap, const int32_t* nfrac, int B, int K,
@@ -481,6 +575,13 @@ void launch_nt(const MlpGemm& g, hipStream_t s) {
 }
 }  // namespace
 
+// Both operands along M and N, M and N multiples of 64, 16-byte aligned rows.
+bool tn_eligible(const MlpGemm& g) {
+    if (g.mode != MLP_PLAIN || g.sa_m != 1 || g.sb_n != 1 || g.K <= 0 || g.M % 64 || g.N % 64) return false;
+    if (g.sa_k % 8 || g.sb_k % 8 || !aligned16(g.A) || !aligned16(g.B) || g.bias) return false;
+    return aligned16(g.C) && g.ldc % 4 == 0;
+}
+
 // 128 x 128 tiles when they still give the chip two workgroups per CU, else 64 x 64
 int gemm_tile(const MlpGemm& g) { return (long)blocks_for(g.N, 128) * blocks_for(g.M, 128) >= 512 ? 128 : 64; }
 
@@ -493,6 +594,10 @@ hipError_t launch_gemm(const MlpGemm& g, hipStream_t s) {
         return hipGetLastError();
     }
     if (g.mode == MLP_OUT) return hipErrorInvalidValue;    // only the K-contiguous kernel fuses the output layer
+    if (tn_eligible(g)) {
+        hipLaunchKernelGGL((gemm_tn_kernel<2>), dim3((g.M / 64) * (g.N / 64), 1), dim3(256), 0, s, g, g.K, 0L);
+        return hipGetLastError();
+    }
     if (large)
         hipLaunchKernelGGL((gemm_bf16_kernel<4, 32>), dim3(blocks_for(g.N, 128), blocks_for(g.M, 128)), dim3(256), 0, s,
                            g);
@@ -538,6 +643,26 @@ hipError_t mlp_forward(const MlpNet& net, const float* dose, const int32_t* gap,
     return hipGetLastError();
 }
 
+// A weight gradient (K = batch rows): K split over S workgroups per tile so
+// that the 16-64 tiles of a 512-wide layer fill the chip, S = B / 512 up to 8,
+// partials in `part` (part_floats >= S M N; the caller's spent Z3 buffer),
+// then summed in split order.
+hipError_t launch_wgrad(const MlpGemm& g, float* part, long part_floats, hipStream_t s) {
+    if (!tn_eligible(g)) return launch_gemm(g, s);
+    const long mn = (long)g.M * g.N;
+    int S = std::min(8, std::max(1, g.K / 512));
+    while (S > 1 && (long)S * mn > part_floats) --S;
+    const int kchunk = ((g.K + S - 1) / S + 31) / 32 * 32;
+    S = (g.K + kchunk - 1) / kchunk;
+    MlpGemm p = g;
+    if (S > 1) { p.C = part; p.ldc = g.N; }
+    hipLaunchKernelGGL((gemm_tn_kernel<2>), dim3((g.M / 64) * (g.N / 64), S), dim3(256), 0, s, p, kchunk, mn);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || S == 1) return e;
+    hipLaunchKernelGGL(split_sum_kernel, dim3(blocks_for(mn / 4, 256)), dim3(256), 0, s, part, S, mn, g.C);
+    return hipGetLastError();
+}
+
 hipError_t mlp_backward(const MlpNet& net, int B, const float* target, const MlpWork& w, float* loss,
                         hipStream_t s) {
     hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, s, w.y, target, net.norm, B, w.dy, loss);
@@ -562,7 +687,7 @@ hipError_t mlp_backward(const MlpNet& net, int B, const float* target, const Mlp
         g.B = w.dZ[cur]; g.sb_k = MLP_HID; g.sb_n = 1;
         g.mode = MLP_PLAIN;
         g.C = net.gW[l]; g.ldc = MLP_HID;
-        e = launch_gemm(g, s);
+        e = launch_wgrad(g, w.Z[2], (long)B * MLP_HID, s);
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(colsum_partial_kernel, dim3(MLP_HID / 64, MLP_RED_CHUNKS), dim3(256), 0, s, w.dZ[cur],
                            nullptr, B, MLP_HID, w.part);

@@ -45,7 +45,8 @@ def test_gemm_large_tiles_match_float64(gga, M, N, K, ta, tb):
     test_gemm_matches_float64(gga, M, N, K, ta, tb)
 
 
-@pytest.mark.parametrize("M,N,K", [(64, 64, 32), (100, 70, 45), (128, 512, 512), (513, 512, 1000)])
+@pytest.mark.parametrize("M,N,K", [(64, 64, 32), (100, 70, 45), (128, 512, 512), (513, 512, 1000), (128, 512, 300),
+                                   (512, 512, 4096)])
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
 def test_gemm_matches_float64(gga, M, N, K, ta, tb):
     g = torch.Generator().manual_seed(M * 7 + N + K)

@@ -177,7 +177,7 @@ struct MlpNet {
     float *gW[3], *gb[3], *gw4, *gb4;
     __bf16 *W[3], *WT[3];        // bf16 copies, [K][N] and [N][K]
 };
-constexpr int MLP_RED_CHUNKS = 16;   // row chunks of the batch reductions (bias gradients)
+constexpr int MLP_RED_CHUNKS = 64;   // row chunks of the batch reductions (bias gradients)
 struct MlpWork {
     __bf16* X;
     float* Z[3];

@@ -437,31 +437,39 @@ __global__ void out_bwd_kernel(const float* dy, const float* w4, const float* Z3
 }
 
 // Column sums of a [B][N] bf16 matrix (bias gradients), and dw4 / db4.
-// Column sums over the batch, in two deterministic passes: block (x, c) adds
-// rows of chunk c for 64 columns (4 row groups of one wave each, combined in
-// LDS in a fixed order); the final pass adds the chunks in order.  Row b is
-// weighted by w[b] when w is given, and column N then holds the sum of w.
+// Column sums over the batch, in two deterministic passes: block c adds the
+// rows of chunk c, each lane 8 consecutive columns (one 16-byte load per row)
+// in 4 row groups of one wave each, combined in LDS in a fixed order; the
+// final pass adds the chunks in order.  Row b is weighted by w[b] when w is
+// given, and column N then holds the sum of w.  N <= 512, N % 8 == 0.
 __global__ __launch_bounds__(256) void colsum_partial_kernel(const bf16* D, const float* w, int B, int N,
                                                              float* part) {
-    __shared__ float red[4][64];
+    __shared__ float red[4][MLP_HID];
     __shared__ float redw[4];
-    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-    const int col = blockIdx.x * 64 + lane, c = blockIdx.y;
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6, c = blockIdx.x;
+    const int col = lane * 8;
     const int rows = (B + MLP_RED_CHUNKS - 1) / MLP_RED_CHUNKS;
     const int b0 = c * rows, b1 = min(B, b0 + rows);
-    float s = 0.0f, sw = 0.0f;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float sw = 0.0f;
     for (int b = b0 + grp; b < b1; b += 4) {
         const float wb = w ? w[b] : 1.0f;
-        if (col < N) s += (float)D[(size_t)b * N + col] * wb;
+        if (col < N) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8*>(D + (size_t)b * N + col);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += (float)v[e] * wb;
+        }
         sw += wb;
     }
-    red[grp][lane] = s;
+    if (col < N) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) red[grp][col + e] = s[e];
+    }
     if (lane == 0) redw[grp] = sw;
     __syncthreads();
-    if (grp == 0) {
-        if (col < N) part[(size_t)c * (N + 1) + col] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-        if (w && blockIdx.x == 0 && lane == 0) part[(size_t)c * (N + 1) + N] = ((redw[0] + redw[1]) + redw[2]) + redw[3];
-    }
+    for (int n = threadIdx.x; n < N; n += blockDim.x)
+        part[(size_t)c * (N + 1) + n] = ((red[0][n] + red[1][n]) + red[2][n]) + red[3][n];
+    if (w && threadIdx.x == 0) part[(size_t)c * (N + 1) + N] = ((redw[0] + redw[1]) + redw[2]) + redw[3];
 }
 __global__ void colsum_final_kernel(const float* part, int N, int with_w, float* out, float* out_w) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -669,7 +677,7 @@ hipError_t mlp_backward(const MlpNet& net, int B, const float* target, const Mlp
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // dw4 = H3^T dy, db4 = sum dy
-    hipLaunchKernelGGL(colsum_partial_kernel, dim3(MLP_HID / 64, MLP_RED_CHUNKS), dim3(256), 0, s, w.H[2], w.dy, B,
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3(MLP_RED_CHUNKS), dim3(256), 0, s, w.H[2], w.dy, B,
                        MLP_HID, w.part);
     hipLaunchKernelGGL(colsum_final_kernel, dim3(blocks_for(MLP_HID + 1, 256)), dim3(256), 0, s, w.part, MLP_HID, 1,
                        net.gw4, net.gb4);
@@ -689,7 +697,7 @@ hipError_t mlp_backward(const MlpNet& net, int B, const float* target, const Mlp
         g.C = net.gW[l]; g.ldc = MLP_HID;
         e = launch_wgrad(g, w.Z[2], (long)B * MLP_HID, s);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(colsum_partial_kernel, dim3(MLP_HID / 64, MLP_RED_CHUNKS), dim3(256), 0, s, w.dZ[cur],
+        hipLaunchKernelGGL(colsum_partial_kernel, dim3(MLP_RED_CHUNKS), dim3(256), 0, s, w.dZ[cur],
                            nullptr, B, MLP_HID, w.part);
         hipLaunchKernelGGL(colsum_final_kernel, dim3(blocks_for(MLP_HID, 256)), dim3(256), 0, s, w.part, MLP_HID, 0,
                            net.gb[l], nullptr);

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "gga_internal.h"
+#include "mlp_internal.h"
 
 namespace {
 

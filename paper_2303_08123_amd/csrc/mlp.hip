@@ -17,6 +17,7 @@
 
 #include "gga_device.h"
 #include "gga_internal.h"
+#include "mlp_internal.h"
 
 namespace gga {
 namespace {

@@ -61,7 +61,8 @@ typedef struct gga_params {
     uint32_t struct_size;
     float lambda[3];        /* FTCS numbers D dtau / h^2 for O, G, H; each in [0, 1/4] */
     float kappa[3];         /* O and G uptake, H production per sub-step at activity 1;
-                               O uptake must be > 0, the others >= 0                    */
+                               all > 0, kappa[1] / kappa[0] and kappa[2] / kappa[0]
+                               in [1e-12, 1e12]                                        */
     float ghost[3];         /* Dirichlet values outside the lattice                      */
     float init[3];          /* initial uniform field values                              */
     float activity[4];      /* activity of EMPTY, PROLIF, QUIESC, DEAD sites             */
@@ -162,6 +163,12 @@ int gga_simulate(const gga_params* params, const gga_sim_cfg* cfg,
  * Write the initial state of P * cfg->R instances: fields_d[P*R][3][L][L]
  * (float32) and cells_d[P*R][L][L] (uint16 words).  Same kernel as
  * gga_simulate, run for zero steps.
+ *
+ * State buffers (here, gga_state_run, the tumour library and the variant
+ * runs) hold each field f in the kernel's units c^ = (c - ghost[f]) / rho_f,
+ * rho_f = kappa'_f / kappa'_O with kappa' = (-kappa[0], -kappa[1], +kappa[2]):
+ * shifted by its boundary value and scaled so that all three fields share one
+ * reaction term.  Physical values are c = rho_f c^ + ghost[f].
  * Errors: as gga_simulate.
  */
 int gga_state_init(const gga_params* params, const gga_sim_cfg* cfg, int32_t P,

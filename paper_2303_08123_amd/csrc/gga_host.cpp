@@ -26,8 +26,12 @@ int check_params(const gga_params* p) {
     if (p->struct_size != sizeof(gga_params)) return GGA_E_ABI;
     for (int f = 0; f < 3; ++f) {
         if (!finite_in(p->lambda[f], 0.0f, 0.25f)) return GGA_E_PARAM;
-        if (!finite_in(p->kappa[f], f == 0 ? 1e-30f : 0.0f, 1e30f)) return GGA_E_PARAM;
+        if (!finite_in(p->kappa[f], 1e-30f, 1e30f)) return GGA_E_PARAM;   // positive: the field units divide by them
         if (!std::isfinite(p->ghost[f]) || !std::isfinite(p->init[f])) return GGA_E_PARAM;
+    }
+    for (int f = 1; f < 3; ++f) {   // rho_f = kappa_f / kappa_O, the field units' scale, well inside float range
+        const double r = (double)p->kappa[f] / (double)p->kappa[0];
+        if (!(r >= 1e-12 && r <= 1e12)) return GGA_E_PARAM;
     }
     for (int s = 0; s < 4; ++s)
         if (!finite_in(p->activity[s], 0.0f, 1e30f)) return GGA_E_PARAM;

@@ -91,6 +91,23 @@ __device__ __forceinline__ void store_words(uint16_t* p, const uint32_t (&w)[CPL
     }
 }
 
+// Fields are held in kernel units c^ = (c - g_f) / rho_f: shifted by the
+// field's Dirichlet boundary value g_f and scaled by rho_f = kappa'_f / kappa'_O
+// (kappa' the signed reaction rate: -uptake for O and G, +production for H).
+// In these units the boundary is 0 and every field's reaction term is the
+// oxygen one, kappa'_O a, so one per-site term serves all three fields.  The
+// FTCS update keeps its form: c' = lam S + (1 - 4 lam) c + r carries over to
+// c^' = lam S^ + (1 - 4 lam) c^ + r / rho_f, because the shift g_f cancels
+// (4 lam + (1 - 4 lam) - 1 = 0) and a neighbour on the boundary is g_f, i.e. 0.
+__device__ __forceinline__ double field_rho(const gga_params& P, int f) {
+    const double k0 = -(double)P.kappa[0];
+    const double kf = f < 2 ? -(double)P.kappa[f] : (double)P.kappa[f];
+    return kf / k0;
+}
+__device__ __forceinline__ float to_field_units(const gga_params& P, int f, double c) {
+    return (float)((c - (double)P.ghost[f]) / field_rho(P, f));
+}
+
 // Constants of the cell update.  They sit in LDS and are read at their point
 // of use after a barrier, so they do not occupy scalar registers across the
 // diffusion loop.
@@ -259,8 +276,11 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             s_nev = nev;
         }
         const gga_params& Q = a.prm;
-        s_k.thOq = Q.theta_O_quiesce; s_k.thGq = Q.theta_G_quiesce;
-        s_k.thOd = Q.theta_O_death; s_k.thGd = Q.theta_G_death; s_k.thHd = Q.theta_H_death;
+        // thresholds in field units (rho_O = 1, rho_G > 0, rho_H < 0: the host
+        // requires positive rates, so "H above its threshold" reads H^ < th^)
+        s_k.thOq = to_field_units(Q, 0, Q.theta_O_quiesce); s_k.thGq = to_field_units(Q, 1, Q.theta_G_quiesce);
+        s_k.thOd = to_field_units(Q, 0, Q.theta_O_death); s_k.thGd = to_field_units(Q, 1, Q.theta_G_death);
+        s_k.thHd = to_field_units(Q, 2, Q.theta_H_death);
         s_k.T_min = Q.T_min; s_k.T_lys = Q.T_lys;
         s_k.ca0 = Q.class_age[0]; s_k.ca1 = Q.class_age[1];
         s_k.T_div = (Q.P_div >= 1.0) ? 0xFFFFFFFFu : (uint32_t)floor(Q.P_div * 4294967296.0);
@@ -301,12 +321,15 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     } else {
         const int ctr = L / 2;
         const int rad2 = P.seed_radius * P.seed_radius;
+        float f0[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) f0[f] = to_field_units(P, f, P.init[f]);
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) F[f][i][c] = P.init[f];
+                for (int c = 0; c < CPL; ++c) F[f][i][c] = f0[f];
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
 #pragma unroll
@@ -322,32 +345,19 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             }
     }
 
-    // Per-field constants.
-    float lam[3], cen[3], kap[3], gst[3];
+    // Per-field constants (field units, see to_field_units): the update, the
+    // lower clamp of O and G (c >= 0 reads c^ >= -g / rho, rho_O = 1 and
+    // rho_G > 0), and the one reaction rate kappa'_O.
+    float lam[3], cen[3], lo[2];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
         lam[f] = P.lambda[f];
         cen[f] = 1.0f - 4.0f * P.lambda[f];
-        kap[f] = (f < 2) ? -P.kappa[f] : P.kappa[f];
-        gst[f] = P.ghost[f];
     }
+#pragma unroll
+    for (int f = 0; f < 2; ++f) lo[f] = to_field_units(P, f, 0.0);
+    const float kapO = -P.kappa[0];
     const float actv[4] = {P.activity[0], P.activity[1], P.activity[2], P.activity[3]};
-    // Ghost flux through the left / right lattice edge, folded into the
-    // reaction constant of the edge columns (the lane shifts deliver 0 there).
-    const bool left_edge = (lane == 0), right_edge = (lane == 63);
-    // R_f = rho_f Ro + e_f:  rho_f = kappa_f' / kappa_O' (signed uptake; the
-    // host requires kappa_O > 0), and e_f = lam_f g_f - rho_f lam_O g_O on an
-    // edge column, 0 elsewhere.
-    float rho[3], eoff[3][CPL];
-#pragma unroll
-    for (int f = 0; f < 3; ++f) rho[f] = kap[f] / kap[0];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-        const bool edge = (c == 0 && left_edge) || (c == CPL - 1 && right_edge);
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-            eoff[f][c] = edge ? lam[f] * gst[f] - rho[f] * (lam[0] * gst[0]) : 0.0f;
-    }
 
     int ev = 0;
     int count = 0;
@@ -386,19 +396,13 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             ++ev;
         }
 
-        // (2) reaction constants for the hour.  Only oxygen's term is kept per
-        // site, Ro = -kappa_O a (+ lam_O g_O on an edge column); the glucose and
-        // acid terms are affine in it, R_f = rho_f Ro + e_f with per-lane
-        // constants, which saves two VGPRs per site for one FMA each.
+        // (2) reaction term for the hour, one per site for all three fields in
+        // field units: Ro = -kappa_O a.
         float Ro[RPT][CPL];
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const bool edge = (c == 0 && left_edge) || (c == CPL - 1 && right_edge);
-                const float act = actv[cellp[i * L + c] & 3];
-                Ro[i][c] = fmaf(kap[0], act, edge ? lam[0] * gst[0] : 0.0f);
-            }
+            for (int c = 0; c < CPL; ++c) Ro[i][c] = kapO * actv[cellp[i * L + c] & 3];
 
         // (3) diffusion sub-steps.  Within a chunk of RPT + 1 sub-steps the rows
         // rotate through the RPT + 1 register slots: new row i is written over
@@ -435,9 +439,8 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         };
         auto update = [&](int f, int i, int c, float up, float below, float west, float east, float cur) {
             const float sum = (up + below) + (west + east);
-            const float rx = (f == 0) ? Ro[i][c] : fmaf(rho[f], Ro[i][c], eoff[f][c]);
-            float v = fmaf(lam[f], sum, fmaf(cur, cen[f], rx));
-            if (f < 2) v = fmaxf(v, 0.0f);
+            float v = fmaf(lam[f], sum, fmaf(cur, cen[f], Ro[i][c]));
+            if (f < 2) v = fmaxf(v, lo[f]);
             return v;
         };
         auto rotating_substep = [&](auto KC, int par) {
@@ -496,7 +499,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         // first sub-step's barrier orders these writes before any read
         for (int k = tid; k < (G::NBUF + 1) * G::BLK; k += G::NT) {
             const int blk = k / G::BLK, off = k - blk * G::BLK;
-            reinterpret_cast<float*>(s_pool)[blk * (NWAVE + 1) * G::BLK + off] = gst[(off / L) % 3];
+            reinterpret_cast<float*>(s_pool)[blk * (NWAVE + 1) * G::BLK + off] = 0.0f;   // the boundary, in field units
         }
         int s = 0;
         for (; s + RPT + 1 <= a.substeps; s += RPT + 1)
@@ -562,7 +565,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                         const int idx = i * CPL + c;
                         const float O = F[0][i][c], Gl = F[1][i][c], H = F[2][i][c];
                         nec_m |= ((__float_as_uint(Gl - thGd) | __float_as_uint(O - thOd) |
-                                   __float_as_uint(thHd - H)) >> 31) << idx;
+                                   __float_as_uint(H - thHd)) >> 31) << idx;
                         starv_m |= ((__float_as_uint(O - thOq) | __float_as_uint(Gl - thGq)) >> 31) << idx;
                         asm volatile("" : "+v"(nec_m), "+v"(starv_m));   // fold each site in now
                     }

@@ -59,7 +59,7 @@ __global__ void slab_init_kernel(SimArgs a, int L, int n, float* fields, uint16_
         k0 = (uint32_t)key;
         k1 = (uint32_t)(key >> 32);
     }
-    for (int f = 0; f < 3; ++f) fields[(size_t)k * 3 * plane + f * plane + site] = a.prm.init[f];
+    for (int f = 0; f < 3; ++f) fields[(size_t)k * 3 * plane + f * plane + site] = to_field_units(a.prm, f, a.prm.init[f]);
     const int y = site / L, x = site - y * L, ctr = L / 2;
     uint16_t w = 0;
     if ((x - ctr) * (x - ctr) + (y - ctr) * (y - ctr) <= a.prm.seed_radius * a.prm.seed_radius) {

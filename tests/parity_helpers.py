@@ -20,6 +20,27 @@ WINDOW = 4e-5
 MAX_COUNTED_FRACTION = 1e-3
 
 
+def field_units(prm):
+    """(g, rho) of the HIP path's field representation: its state buffers hold
+    c^ = (c - g_f) / rho_f with g_f the Dirichlet boundary value and
+    rho_f = kappa'_f / kappa'_O, kappa' = (-kappa_O, -kappa_G, +kappa_H)."""
+    k = np.array(prm.kappa, np.float64)
+    kp = np.array([-k[0], -k[1], k[2]])
+    return np.array(prm.ghost, np.float64).reshape(3, 1, 1), (kp / kp[0]).reshape(3, 1, 1)
+
+
+def to_field_units(fields, prm):
+    """Physical fields [..., 3, L, L] -> the HIP path's float32 representation."""
+    g, rho = field_units(prm)
+    return ((np.asarray(fields, np.float64) - g) / rho).astype(np.float32)
+
+
+def from_field_units(fields, prm):
+    """The HIP path's representation -> physical fields, float64."""
+    g, rho = field_units(prm)
+    return np.asarray(fields, np.float64) * rho + g
+
+
 def field_error(got, ref):
     return float(np.max(np.abs(got.astype(np.float64) - ref) / np.maximum(np.abs(ref), FIELD_FLOOR)))
 

@@ -103,6 +103,10 @@ def test_abi_argument_errors(gga):
     prm.lambda_[0] = 0.3
     n = ctypes.c_void_p(0)
     assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfg), n, n, n, 1, 1, n, n, n, n) == -5
+    for f, v in ((1, 0.0), (2, 0.0), (2, 1e-20), (1, 1e20)):   # rates must be positive, ratios in [1e-12, 1e12]
+        prm = gga.make_params(gga.load_model())
+        prm.kappa[f] = v
+        assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfg), n, n, n, 1, 1, n, n, n, n) == -5, (f, v)
     prm = gga.make_params(gga.load_model())
     assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfg), n, n, n, 1, 1, n, n, n, n) == -1
     cfg96 = gga.make_cfg(96, 10, 1)

@@ -9,8 +9,8 @@ from oracle import protocol, sim
 from oracle.model import Params
 from oracle.philox import philox4x32_10
 from paper_2303_08123_amd import workloads
-from parity_helpers import (FIELD_RTOL, MAX_COUNTED_FRACTION, compare_cells, field_error,
-                            oracle_certain_prefix, oracle_step_detail)
+from parity_helpers import (FIELD_RTOL, MAX_COUNTED_FRACTION, compare_cells, field_error, from_field_units,
+                            oracle_certain_prefix, oracle_step_detail, to_field_units)
 
 pytestmark = pytest.mark.gpu
 
@@ -61,7 +61,7 @@ def test_initial_state_is_bit_exact(gga, model_dict, L):
         for r in range(R):
             f_ref, c_ref = sim.init_state(prm, L, p, r, seed)
             assert np.array_equal(cells[p * R + r].astype(np.int64), c_ref)
-            assert np.array_equal(fields[p * R + r].astype(np.float64), f_ref)
+            assert np.array_equal(fields[p * R + r], to_field_units(f_ref, prm))
 
 
 def _oracle_states(prm, L, steps, P, R, seed, dose, gap, nfrac, substeps=10):
@@ -95,13 +95,14 @@ def test_single_step_parity(gga, model_dict, L, preset, warm, event):
     # states: oracle run of `warm` steps with no fractions
     zero = (np.zeros((P, 2), np.float32), np.zeros((P, 2), np.int32), np.zeros(P, np.int32))
     states = _oracle_states(prm, L, warm, P, R, seed, *zero, substeps=substeps)
-    fields = np.stack([s[0] for s in states])
+    fields = to_field_units(np.stack([s[0] for s in states]), prm)
+    start = from_field_units(fields, prm)           # the state the HIP path holds, in physical units
     cells = np.stack([s[1] for s in states])
     f_d, c_d = _dev(fields, cells.view(np.int16))
     cfg = gga.make_cfg(L, warm + 1, R, seed=seed, substeps=substeps, dose_cap=100.0)
     d_d, g_d, n_d = _dev(dose, gap, nfrac)
     live, _ = gga.state_run(md, cfg, d_d, g_d, n_d, warm, 1, f_d, c_d)
-    got_f = f_d.cpu().numpy()
+    got_f = from_field_units(f_d.cpu().numpy(), prm)
     got_c = c_d.cpu().numpy().view(np.uint16)
     live = live.cpu().numpy()
     worst_field, worst_counted = 0.0, 0.0
@@ -111,7 +112,7 @@ def test_single_step_parity(gga, model_dict, L, preset, warm, event):
             assert warm in ev
         for r in range(R):
             i = p * R + r
-            f_ref, c_ref, counted = oracle_step_detail(fields[i].astype(np.float64), cells[i].astype(np.int64),
+            f_ref, c_ref, counted = oracle_step_detail(start[i], cells[i].astype(np.int64),
                                                        warm, ev.get(warm), p, r, seed, prm, substeps)
             worst_field = max(worst_field, field_error(got_f[i], f_ref))
             bad, frac = compare_cells(got_c[i], c_ref, counted)
@@ -140,15 +141,16 @@ def test_single_step_parity_white_noise_fields(gga, model_dict):
         f, c = workloads.random_state(L, 100 + r)
         fields.append(f)
         cells.append(c)
-    fields, cells = np.stack(fields), np.stack(cells)
+    fields, cells = to_field_units(np.stack(fields), prm), np.stack(cells)
+    start = from_field_units(fields, prm)
     f_d, c_d = _dev(fields, cells.view(np.int16))
     dose, gap, nfrac = np.array([[2.5]], np.float32), np.array([[77]], np.int32), np.array([1], np.int32)
     cfg = gga.make_cfg(L, 100, R, seed=seed, dose_cap=20.0)
     gga.state_run(model_dict, cfg, *_dev(dose, gap, nfrac), 77, 1, f_d, c_d)
-    got_f, got_c = f_d.cpu().numpy(), c_d.cpu().numpy().view(np.uint16)
+    got_f, got_c = from_field_units(f_d.cpu().numpy(), prm), c_d.cpu().numpy().view(np.uint16)
     thr = protocol.events(dose[0], gap[0], 1, 100, prm)[0][1]
     for r in range(R):
-        f_ref, c_ref, counted = oracle_step_detail(fields[r].astype(np.float64), cells[r].astype(np.int64),
+        f_ref, c_ref, counted = oracle_step_detail(start[r], cells[r].astype(np.int64),
                                                    77, thr, 0, r, seed, prm, 10, abs_window=2e-6)
         assert np.max(np.abs(got_f[r] - f_ref)) < 2e-6
         bad, frac = compare_cells(got_c[r], c_ref, counted)

@@ -14,7 +14,8 @@ import torch
 from oracle import protocol, sim
 from oracle.model import Params
 from paper_2303_08123_amd import workloads
-from parity_helpers import FIELD_RTOL, MAX_COUNTED_FRACTION, compare_cells, field_error, oracle_step_detail
+from parity_helpers import (FIELD_RTOL, MAX_COUNTED_FRACTION, compare_cells, field_error, from_field_units,
+                            oracle_step_detail, to_field_units)
 
 pytestmark = pytest.mark.gpu
 
@@ -39,11 +40,12 @@ def high_uptake(md):
 
 
 def _oracle_init(prm, L, P, R, seed):
+    """Initial states in the HIP path's field units."""
     fields, cells = [], []
     for p in range(P):
         for r in range(R):
             f, c = sim.init_state(prm, L, p, r, seed)
-            fields.append(f.astype(np.float32))
+            fields.append(to_field_units(f, prm))
             cells.append(c.astype(np.uint16))
     return np.stack(fields), np.stack(cells)
 
@@ -96,18 +98,19 @@ def test_L256_single_step_parity(gga, model_dict, variant, event):
     prm = Params.from_dict(md)
     L, P, R, seed, warm = 256, 1, 2, 5, 200
     states = [sim.run_instance(prm, L, warm, 10, [], 0, r, seed)[:2] for r in range(R)]
-    fields = np.stack([s[0].astype(np.float32) for s in states])
+    fields = to_field_units(np.stack([s[0] for s in states]), prm)
+    start = from_field_units(fields, prm)           # the state the HIP path holds, in physical units
     cells = np.stack([s[1].astype(np.uint16) for s in states])
     dose, gap, nfrac = (np.array([[2.5]], np.float32), np.array([[warm if event else warm + 5]], np.int32),
                         np.array([1], np.int32))
     cfg = gga.make_cfg(L, warm + 1, R, seed=seed, dose_cap=20.0)
     f_d, c_d = _dev(fields, cells.view(np.int16))
     live = gga.state_run_variant(md, cfg, variant, *_dev(dose, gap, nfrac), warm, 1, f_d, c_d).cpu().numpy()
-    got_f, got_c = f_d.cpu().numpy(), c_d.cpu().numpy().view(np.uint16)
+    got_f, got_c = from_field_units(f_d.cpu().numpy(), prm), c_d.cpu().numpy().view(np.uint16)
     ev = dict(protocol.events(dose[0], gap[0], 1, warm + 1, prm))
     assert (warm in ev) == event
     for r in range(R):
-        f_ref, c_ref, counted = oracle_step_detail(fields[r].astype(np.float64), cells[r].astype(np.int64), warm,
+        f_ref, c_ref, counted = oracle_step_detail(start[r], cells[r].astype(np.int64), warm,
                                                    ev.get(warm), 0, r, seed, prm, 10)
         assert field_error(got_f[r], f_ref) <= FIELD_RTOL
         bad, frac = compare_cells(got_c[r], c_ref, counted)

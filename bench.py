@@ -32,6 +32,18 @@ OPS_PER_SITE_SUBSTEP = 17
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 
 
+# The paper's own throughput (Materials and Methods, "GPU implementation:
+# acceleration, fidelity & normality"), quoted as context: its calibrated
+# model and workload differ from the synthetic ones measured here.
+PAPER_CONTEXT = {
+    "simulations_per_h": 80000, "hardware": "4x NVIDIA V100", "simulations_per_s_per_gpu": 80000 / 3600 / 4,
+    "simulation": "one library tumour under one protocol: 5 days of treatment and 5 of regrowth at 600 CA steps/h "
+                  "(144,000 steps) on the paper's calibrated EMT6/Ro model; lattice size not stated",
+    "cpu_prior_work_simulations_per_h": 111, "cpu_prior_work_hardware": "13 x 10-core CPUs (Matlab)",
+    "note": "context only: a different model, lattice and step count",
+}
+
+
 def measured_traffic():
     """HBM bytes per launch of the simulation kernel from the stored counter
     record, or None when the kernel's sources changed since it was taken."""
@@ -552,6 +564,8 @@ def main():
                      "unit": "Top/s", "frac": achieved / VALU_PEAK_OPS,
                      "traffic": measured_traffic() if args.workload == "batched" else None,
                      "kernel": "sim_kernel", "kernel_ms": kernel_s * 1000.0},
+        "instance_simulations_per_s": P * R / (ms_per_step / 1000.0),
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")

@@ -42,10 +42,18 @@ __device__ __forceinline__ float phi_as(float x, float& e) {
     e = __builtin_amdgcn_exp2f(-a * a * 1.4426950408889634f);
     return 0.5f + copysignf(0.5f * fmaf(-p, e, 1.0f), x);
 }
-// GELU(x) = x Phi(x); GELU'(x) = Phi(x) + x phi(x), phi(x) = exp(-x^2 / 2) / sqrt(2 pi)
+// GELU(x) = x Phi(x) = relu(x) - |x| p(t) exp(-x^2 / 2) / 2 with the same
+// rational erf (x Phi(x) = x/2 + |x| erf(|x| / sqrt 2) / 2): 11 VALU operations
+// and two transcendentals, the 1/2 and 1/sqrt 2 folded into the constants.
+// GELU'(x) = Phi(x) + x phi(x), phi(x) = exp(-x^2 / 2) / sqrt(2 pi).
 __device__ __forceinline__ float gelu_f(float x) {
-    float e;
-    return x * phi_as(x, e);
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.2316418882f, ax, 1.0f));
+    const float q =
+        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 0.5307027145f, -0.7265760135f), 0.7107068705f), -0.142248368f),
+                 0.127414796f);
+    const float e = __builtin_amdgcn_exp2f(x * x * -0.7213475204f);
+    return fmaf(-ax * q, e, fmaxf(x, 0.0f));
 }
 __device__ __forceinline__ float gelu_grad_f(float x) {
     float e;
@@ -160,11 +168,12 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(MlpGemm g) {
 // epilogue is fixed at compile time (MODE).  Workgroups are numbered so that
 // the N / TM column tiles of one row block run on one XCD (blocks are dealt
 // round-robin over the 8 XCDs), which then reads that row block once into its
-// L2.  MLP_OUT (the last hidden layer of a prediction) stores no activations:
+// L2.  The accumulators start from the bias.  At most 122 VGPRs (no AGPRs),
+// so four workgroups share a CU (their LDS tiles fill its 160 KB).  MLP_OUT (the last hidden layer of a prediction) stores no activations:
 // it writes, per row and per chunk of TM / 2 columns, the partial dot product
 // of the bf16-rounded GELU outputs with w4 into C[row][chunk].
 template <int WT, int MODE>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(MlpGemm g) {
+__global__ __launch_bounds__(256, 2) void gemm_nt_kernel(MlpGemm g) {
     constexpr int TM = 32 * WT, BK = 32, VPT = TM * BK / 8 / 256, CPR = BK / 8;
     __shared__ bf16 As[2][TM][BK + PADK];
     __shared__ bf16 Bs[2][TM][BK + PADK];
@@ -174,11 +183,17 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(MlpGemm g) {
     if ((gridDim.x & 7) == 0) bid = (bid & 7) * (gridDim.x >> 3) + (bid >> 3);
     const int m0 = (bid / ntn) * TM, n0 = (bid - (bid / ntn) * ntn) * TM;
     const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TM / 2);
-    floatx4 acc[WT][WT];                                  // [column block][row block]
+    floatx4 acc[WT][WT];                                  // [column block][row block], from the bias
 #pragma unroll
-    for (int i = 0; i < WT; ++i)
+    for (int i = 0; i < WT; ++i) {
+        floatx4 b0 = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (g.bias) {
+            const float4 bb = *reinterpret_cast<const float4*>(g.bias + n0 + wn + i * 16 + (lane >> 4) * 4);
+            b0 = floatx4{bb.x, bb.y, bb.z, bb.w};
+        }
 #pragma unroll
-        for (int j = 0; j < WT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < WT; ++j) acc[i][j] = b0;
+    }
     const bf16* pa[VPT];
     const bf16* pb[VPT];
 #pragma unroll
@@ -235,10 +250,6 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(MlpGemm g) {
         for (int i = 0; i < WT; ++i) {
             const int col = n0 + wn + i * 16 + (lane >> 4) * 4;
             float o[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
-            if (g.bias) {
-                const float4 bb = *reinterpret_cast<const float4*>(g.bias + col);
-                o[0] += bb.x; o[1] += bb.y; o[2] += bb.z; o[3] += bb.w;
-            }
             if (MODE == MLP_PLAIN) {
                 *reinterpret_cast<float4*>(g.C + (size_t)row * g.ldc + col) = make_float4(o[0], o[1], o[2], o[3]);
                 continue;

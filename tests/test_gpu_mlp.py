@@ -80,9 +80,11 @@ def test_forward_matches_oracle(gga, B):
     X = bf16(omlp.encode(dose, gap, nfrac))
     y, (_, Z1, H1, Z2, H2, Z3, H3) = omlp.forward(params, X)
     u = 2.0 ** -9                                    # bf16 rounding, relative
-    # the kernels take Phi from a rational erf with |error| <= 1.5e-7 (Phi
-    # within 7.5e-8; 2e-7 with the fp32 roundings): GELU(z) within dphi |z|
-    dphi = 2e-7
+    # the kernels take GELU from a rational erf with |error| <= 1.5e-7, i.e.
+    # 7.5e-8 |z|, plus the fp32 roundings of its evaluation (rcp, exp2 and five
+    # Horner steps, each within an ulp: at most 3e-7 of the term |z| p e / 2):
+    # GELU(z) within dphi |z|
+    dphi = 4e-7
     e1 = u * np.abs(H1) + dphi * np.abs(Z1)
     e2 = u * np.abs(H2) + dphi * np.abs(Z2) + 1.13 * (e1 @ np.abs(params[2]))
     e3 = u * np.abs(H3) + dphi * np.abs(Z3) + 1.13 * (e2 @ np.abs(params[4]))

@@ -379,23 +379,30 @@ __global__ void split_sum_kernel(const float* part, int S, long n, float* out) {
 }
 
 // Features of protocol b: for fraction j < 40, (dose/5, gap/60, 1) if present.
-// One thread per 8 consecutive features, stored as one 16-byte vector.
+// One thread per 8 consecutive features (fractions j0 .. j0 + 3), stored as one
+// 16-byte vector; the dose and delay loads depend only on K, so they are in
+// flight together with the load of nfrac[b].
 __global__ void encode_kernel(const float* dose, const int32_t* gap, const int32_t* nfrac, int B, int K,
                               bf16* X) {
     constexpr int V = MLP_IN / 8;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= B * V) return;
-    const int b = idx / V, f0 = (idx - b * V) * 8;
-    const int nf = min(min(MLP_FRAC, K), nfrac[b]);
+    const int b = idx / V, f0 = (idx - b * V) * 8, j0 = f0 / 3;
+    const int jmax = min(MLP_FRAC, K);
+    float d[4], g[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool in = j0 + q < jmax;
+        d[q] = in ? dose[(size_t)b * K + j0 + q] * (1.0f / 5.0f) : 0.0f;
+        g[q] = in ? (float)gap[(size_t)b * K + j0 + q] * (1.0f / 60.0f) : 0.0f;
+    }
+    const int nf = min(jmax, nfrac[b]);
     bf16x8 x;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        const int f = f0 + e, j = f / 3, part = f - 3 * j;
-        float v = 0.0f;
-        if (j < nf)
-            v = part == 0 ? dose[(size_t)b * K + j] * (1.0f / 5.0f)
-                          : part == 1 ? (float)gap[(size_t)b * K + j] * (1.0f / 60.0f) : 1.0f;
-        x[e] = (bf16)v;
+        const int f = f0 + e, j = f / 3, part = f - 3 * j, q = j - j0;
+        const float v = part == 0 ? d[q] : part == 1 ? g[q] : 1.0f;
+        x[e] = (bf16)(j < nf ? v : 0.0f);
     }
     *reinterpret_cast<bf16x8*>(X + (size_t)b * MLP_IN + f0) = x;
 }

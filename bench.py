@@ -44,6 +44,31 @@ PAPER_CONTEXT = {
 }
 
 
+# Bytes a site-substep would move if the three fp32 fields were streamed
+# (read and written once): the stencil's algorithmic traffic in a design that
+# keeps the state in memory rather than in registers.
+STREAM_BYTES_PER_SITE_SUBSTEP = 24
+HBM_PEAK_BYTES = 8.0e12
+
+
+def measured_peaks(gga, achieved_ops, site_substeps_per_s):
+    """The chip's VALU, LDS and HBM rates measured by the library's
+    microbenchmarks, the simulation kernel's VALU rate against the measured
+    one, and the equivalent streamed-state rate (24 B per site-substep)
+    against the HBM and LDS rates."""
+    pk = gga.measure_peaks()
+    stream = STREAM_BYTES_PER_SITE_SUBSTEP * site_substeps_per_s
+    return {
+        "valu_lane_ops_per_s": pk["valu_lane_ops_per_s"], "lds_read_bytes_per_s": pk["lds_read_bytes_per_s"],
+        "hbm_read_bytes_per_s": pk["hbm_read_bytes_per_s"],
+        "alu_frac_vs_measured": achieved_ops / pk["valu_lane_ops_per_s"],
+        "stream_equivalent": {"bytes_per_site_substep": STREAM_BYTES_PER_SITE_SUBSTEP, "bytes_per_s": stream,
+                              "vs_hbm_spec": stream / HBM_PEAK_BYTES,
+                              "vs_hbm_measured": stream / pk["hbm_read_bytes_per_s"],
+                              "vs_lds_measured": stream / pk["lds_read_bytes_per_s"]},
+    }
+
+
 def measured_traffic():
     """HBM bytes per launch of the simulation kernel from the stored counter
     record, or None when the kernel's sources changed since it was taken."""
@@ -565,6 +590,7 @@ def main():
                      "traffic": measured_traffic() if args.workload == "batched" else None,
                      "kernel": "sim_kernel", "kernel_ms": kernel_s * 1000.0},
         "instance_simulations_per_s": P * R / (ms_per_step / 1000.0),
+        "measured_peaks": measured_peaks(gga, achieved, site_steps * S / kernel_s),
         "paper_context": PAPER_CONTEXT,
     }
     if not args.no_cpu_baseline:

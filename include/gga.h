@@ -345,6 +345,19 @@ int gga_mlp_train_step(void* net_d, const float* dose_d, const int32_t* gap_h_d,
 int gga_mlp_gemm(int32_t M, int32_t N, int32_t K, const void* A_d, int32_t a_trans, const void* B_d,
                  int32_t b_trans, float* C_d, hipStream_t stream);
 
+/*
+ * Microbenchmarks of the resources the kernels are measured against, on the
+ * current device: valu_ops_h[0] = full-rate 32-bit VALU lane-operations per
+ * second (independent FMA chains, an FMA counted as one operation),
+ * lds_bytes_h[0] = LDS read bytes per second (conflict-free 16-byte reads),
+ * hbm_bytes_h[0] = HBM read bytes per second (one pass over buf_d).  buf_d:
+ * device buffer of `bytes` >= 256 MiB + 256, 16-byte aligned, contents
+ * ignored (its last 256 bytes are reserved).  Results are HOST doubles.
+ * Synchronous.  Errors: GGA_E_ARG, GGA_E_HIP.
+ */
+int gga_measure_peaks(void* buf_d, size_t bytes, double* valu_ops_h, double* lds_bytes_h, double* hbm_bytes_h,
+                      hipStream_t stream);
+
 /* Surrogate-screened GA settings.  Set struct_size = sizeof(gga_sga_cfg). */
 typedef struct gga_sga_cfg {
     uint32_t struct_size;

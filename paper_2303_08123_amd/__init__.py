@@ -131,6 +131,7 @@ def _load():
                                    ctypes.c_size_t, vp, vp], ctypes.c_int),
         "gga_autotune_workspace_bytes": ([i32, i32, i32, i32, i32], ctypes.c_size_t),
         "gga_autotune": ([vp, vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, vp, vp, vp], ctypes.c_int),
+        "gga_measure_peaks": ([vp, ctypes.c_size_t, vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -148,7 +149,8 @@ EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
            "gga_sga_workspace_bytes", "gga_sga_init", "gga_sga_generation", "gga_sga_run",
            "gga_variant_count", "gga_variant_side", "gga_variant_is_slab", "gga_variant_name", "gga_get_variant",
            "gga_set_variant", "gga_uneven_workspace_bytes", "gga_simulate_uneven", "gga_event_table_bytes",
-           "gga_state_run_variant", "gga_autotune_workspace_bytes", "gga_autotune", "gga_simulate_library")
+           "gga_state_run_variant", "gga_autotune_workspace_bytes", "gga_autotune", "gga_simulate_library",
+           "gga_measure_peaks")
 
 
 class GGAError(RuntimeError):
@@ -679,3 +681,16 @@ class SurrogateGA:
             self.archive = (arc[0][:rows], arc[1][:rows])
         self.g = rows
         return gen_ms[:n_gen]
+
+
+# ---------------------------------------------------------------- measurement
+
+def measure_peaks(nbytes=1 << 30, stream=None):
+    """Microbenchmarks on the current device: {"valu_lane_ops_per_s",
+    "lds_read_bytes_per_s", "hbm_read_bytes_per_s"} (gga_measure_peaks over a
+    buffer of nbytes)."""
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    v, l, h = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(LIB.gga_measure_peaks(_ptr(buf), nbytes, ctypes.byref(v), ctypes.byref(l), ctypes.byref(h),
+                                 _stream(stream)))
+    return {"valu_lane_ops_per_s": v.value, "lds_read_bytes_per_s": l.value, "hbm_read_bytes_per_s": h.value}

@@ -9,6 +9,7 @@
 
 #include "gga_internal.h"
 #include "mlp_internal.h"
+#include "peaks.h"
 
 namespace {
 
@@ -661,6 +662,15 @@ int gga_mlp_train_step(void* net_d, const float* dose_d, const int32_t* gap_h_d,
     int rc = gga_mlp_grad(net_d, dose_d, gap_h_d, nfrac_d, target_d, B, K, work_d, work_bytes, loss_d, stream);
     if (rc) return rc;
     const hipError_t e = gga::mlp_adam_refresh(gga::mlp_net(net_d), step, lr, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_measure_peaks(void* buf_d, size_t bytes, double* valu_ops_h, double* lds_bytes_h, double* hbm_bytes_h,
+                      hipStream_t stream) {
+    if (!buf_d || (reinterpret_cast<uintptr_t>(buf_d) & 15) || bytes < ((size_t)256 << 20) + 256 || !valu_ops_h ||
+        !lds_bytes_h || !hbm_bytes_h)
+        return GGA_E_ARG;
+    const hipError_t e = gga::measure_peaks(buf_d, bytes, valu_ops_h, lds_bytes_h, hbm_bytes_h, stream);
     return e == hipSuccess ? GGA_OK : hip_fail(e);
 }
 

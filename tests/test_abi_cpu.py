@@ -28,7 +28,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(gga):
     names = declared_functions()
-    assert len(names) == 39
+    assert len(names) == 40
     for n in names:
         assert hasattr(gga.LIB, n), n
     assert set(names) == set(gga.EXPORTS)
@@ -217,3 +217,13 @@ def test_mlp_buffers_must_be_16_byte_aligned(gga):
     assert gga.LIB.gga_mlp_grad(ok, ok, ok, ok, ok, B, K, off, wb, None, None) == -1
     assert gga.LIB.gga_mlp_train_step(off, ok, ok, ok, ok, B, K, 1, ctypes.c_float(1e-3), ok, wb, None,
                                       None) == -1
+
+
+def test_measure_peaks_checks_its_buffer_before_any_launch(gga):
+    d = ctypes.c_double()
+    ok, off = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x100008)
+    big = (256 << 20) + 256
+    assert gga.LIB.gga_measure_peaks(ok, big - 16, ctypes.byref(d), ctypes.byref(d), ctypes.byref(d), None) == -1
+    assert gga.LIB.gga_measure_peaks(off, big, ctypes.byref(d), ctypes.byref(d), ctypes.byref(d), None) == -1
+    assert gga.LIB.gga_measure_peaks(ok, big, None, ctypes.byref(d), ctypes.byref(d), None) == -1
+    assert gga.LIB.gga_measure_peaks(None, big, ctypes.byref(d), ctypes.byref(d), ctypes.byref(d), None) == -1

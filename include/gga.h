@@ -78,6 +78,21 @@ typedef struct gga_params {
     double m[4];            /* x = m[class] * dose; classes young, mid, old, quiescent   */
 } gga_params;
 
+/*
+ * Fill *out from a model file: a flat JSON object whose values are numbers or
+ * arrays of numbers, keys lambda[3], kappa[3], ghost[3], init_fields[3],
+ * activity[4], theta_O_quiesce, theta_G_quiesce, theta_O_death,
+ * theta_G_death, theta_H_death, T_min, T_lys, A0, seed_radius (integers),
+ * class_age[2] (integers), P_div, alpha, beta, m[4] (the package's
+ * data/model_default.json).  Other keys are ignored.  out->struct_size must
+ * be sizeof(gga_params) (GGA_E_ABI otherwise); *out is written only on
+ * success.  Host only, no device work.  Errors: GGA_E_ARG (null pointer,
+ * unreadable file or malformed JSON), GGA_E_ABI, GGA_E_PARAM (a key missing,
+ * of the wrong length or not integral where an integer is needed, or values
+ * the simulation calls would refuse).
+ */
+int gga_params_from_json(const char* path, gga_params* out);
+
 /* One simulation batch.  Set struct_size = sizeof(gga_sim_cfg). */
 typedef struct gga_sim_cfg {
     uint32_t struct_size;

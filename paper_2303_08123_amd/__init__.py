@@ -132,6 +132,7 @@ def _load():
         "gga_autotune_workspace_bytes": ([i32, i32, i32, i32, i32], ctypes.c_size_t),
         "gga_autotune": ([vp, vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, vp, vp, vp], ctypes.c_int),
         "gga_measure_peaks": ([vp, ctypes.c_size_t, vp, vp, vp, vp], ctypes.c_int),
+        "gga_params_from_json": ([ctypes.c_char_p, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -150,7 +151,7 @@ EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
            "gga_variant_count", "gga_variant_side", "gga_variant_is_slab", "gga_variant_name", "gga_get_variant",
            "gga_set_variant", "gga_uneven_workspace_bytes", "gga_simulate_uneven", "gga_event_table_bytes",
            "gga_state_run_variant", "gga_autotune_workspace_bytes", "gga_autotune", "gga_simulate_library",
-           "gga_measure_peaks")
+           "gga_measure_peaks", "gga_params_from_json")
 
 
 class GGAError(RuntimeError):
@@ -203,6 +204,14 @@ def make_params(d):
     p.class_age[:] = [int(v) for v in d["class_age"]]
     p.P_div, p.alpha, p.beta = float(d["P_div"]), float(d["alpha"]), float(d["beta"])
     p.m[:] = [float(v) for v in d["m"]]
+    return p
+
+
+def params_from_json(path):
+    """gga_params read by the library from a model file (gga_params_from_json)."""
+    p = Params()
+    p.struct_size = ctypes.sizeof(Params)
+    _check(LIB.gga_params_from_json(os.fsencode(path), ctypes.byref(p)))
     return p
 
 

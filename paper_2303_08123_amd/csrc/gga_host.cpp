@@ -79,6 +79,11 @@ gga::SimArgs make_args(const gga_params* prm, const gga_sim_cfg* cfg, const floa
 
 }  // namespace
 
+namespace gga {
+// The parameter check of the simulation calls, for the JSON reader.
+int check_params_host(const gga_params* p) { return check_params(p); }
+}  // namespace gga
+
 extern "C" {
 
 int gga_version(void) { return GGA_ABI_VERSION; }

@@ -28,7 +28,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(gga):
     names = declared_functions()
-    assert len(names) == 40
+    assert len(names) == 41
     for n in names:
         assert hasattr(gga.LIB, n), n
     assert set(names) == set(gga.EXPORTS)
@@ -227,3 +227,34 @@ def test_measure_peaks_checks_its_buffer_before_any_launch(gga):
     assert gga.LIB.gga_measure_peaks(off, big, ctypes.byref(d), ctypes.byref(d), ctypes.byref(d), None) == -1
     assert gga.LIB.gga_measure_peaks(ok, big, None, ctypes.byref(d), ctypes.byref(d), None) == -1
     assert gga.LIB.gga_measure_peaks(None, big, ctypes.byref(d), ctypes.byref(d), ctypes.byref(d), None) == -1
+
+
+def test_params_from_json_reads_the_model_file(gga, tmp_path):
+    """The library's own reader gives the same struct as the binding's, byte for
+    byte; malformed files, missing keys, non-integral integers and refused
+    values return the documented codes and leave the struct unwritten."""
+    import json
+    import os
+    path = os.path.join(gga.DATA, "model_default.json")
+    got = gga.params_from_json(path)
+    want = gga.make_params(gga.load_model())
+    assert bytes(got) == bytes(want)
+    p = gga.Params()
+    p.struct_size = ctypes.sizeof(gga.Params)
+    before = bytes(p)
+    bad = tmp_path / "bad.json"
+    model = gga.load_model()
+    cases = [("{ not json", -1), (json.dumps({k: v for k, v in model.items() if k != "kappa"}), -5),
+             (json.dumps(dict(model, T_min=12.5)), -5), (json.dumps(dict(model, lambda_=1)), 0),
+             (json.dumps(dict(model, **{"lambda": [0.3, 0.1, 0.1]})), -5), (json.dumps(dict(model, m=[1, 2])), -5),
+             (json.dumps(model) + " trailing", -1)]
+    for text, rc in cases:
+        bad.write_text(text)
+        assert gga.LIB.gga_params_from_json(str(bad).encode(), ctypes.byref(p)) == rc, text[:40]
+        if rc:
+            assert bytes(p) == before
+        p = gga.Params()
+        p.struct_size = ctypes.sizeof(gga.Params)
+    assert gga.LIB.gga_params_from_json(b"/nonexistent/model.json", ctypes.byref(p)) == -1
+    p.struct_size = 4
+    assert gga.LIB.gga_params_from_json(path.encode(), ctypes.byref(p)) == -2

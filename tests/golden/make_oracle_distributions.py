@@ -1,5 +1,7 @@
 """Write tests/golden/oracle_distributions.json: final live counts of many
-independent oracle replicas for a few protocols.
+independent oracle replicas for a few protocols (with --batched16:
+tests/golden/oracle_batched16.json, 16 batched-workload protocols as one
+batch).
 
 Calls only the oracle and the seeded input generators.  Run from the
 repository root:  python tests/golden/make_oracle_distributions.py
@@ -45,30 +47,51 @@ def cases():
     }
 
 
+# The batched family: 16 protocols of the batched workload's sample (indices
+# 32, 96, ..., 992), simulated as one batch of 16 (batch position j is the
+# Philox protocol index), 200 replicas each.
+FAMILY_INDICES = [32 + 64 * j for j in range(16)]
+FAMILY_R = 200
+
+
 def one(args):
     name, c, r = args
     prm = Params.from_dict(model(c["model"]))
     ev = protocol.events(np.array(c["dose"], np.float32), np.array(c["gap"]), c["nfrac"], c["horizon"], prm)
-    # protocol index 0 of the batch, replica r, under the oracle's own run seed
-    return name, r, int(sim.run_instance(prm, c["L"], c["horizon"], 10, ev, 0, r, ORACLE_SEED)[2][-1])
+    # protocol index c["p"] of the batch (0 unless given), replica r, under the oracle's own run seed
+    return name, r, int(sim.run_instance(prm, c["L"], c["horizon"], 10, ev, c.get("p", 0), r, ORACLE_SEED)[2][-1])
+
+
+def family_cases():
+    d2, g2, n2 = workloads.config2_protocols(1024, 10, seed=0, cap=20.0)
+    return {f"batched_{i}": dict(model="default", L=128, horizon=480, R=FAMILY_R, p=j, sample_index=i,
+                                 dose=d2[i].tolist(), gap=g2[i].tolist(), nfrac=int(n2[i]))
+            for j, i in enumerate(FAMILY_INDICES)}
 
 
 def main():
-    cs = cases()
+    family = "--batched16" in sys.argv
+    cs = family_cases() if family else cases()
     jobs = [(name, c, r) for name, c in cs.items() for r in range(c["R"])]
     t0 = time.time()
     with mp.Pool(os.cpu_count()) as pool:
         res = pool.map(one, jobs, chunksize=4)
-    out = {"_about": "final live counts of independent oracle replicas (protocol index 0, replica r = 0..R-1, "
-                     f"run seed {ORACLE_SEED}); written by tests/golden/make_oracle_distributions.py",
-           "seed": ORACLE_SEED}
+    if family:
+        about = ("final live counts of independent oracle replicas of 16 batched-workload protocols simulated "
+                 f"as one batch (batch position p, replica r = 0..R-1, run seed {ORACLE_SEED}); written by "
+                 "tests/golden/make_oracle_distributions.py --batched16")
+    else:
+        about = ("final live counts of independent oracle replicas (protocol index 0, replica r = 0..R-1, "
+                 f"run seed {ORACLE_SEED}); written by tests/golden/make_oracle_distributions.py")
+    out = {"_about": about, "seed": ORACLE_SEED}
     for name, c in cs.items():
         live = [0] * c["R"]
         for n, r, v in res:
             if n == name:
                 live[r] = v
         out[name] = dict(c, live=live)
-    with open(os.path.join(ROOT, "tests", "golden", "oracle_distributions.json"), "w") as fh:
+    fname = "oracle_batched16.json" if family else "oracle_distributions.json"
+    with open(os.path.join(ROOT, "tests", "golden", fname), "w") as fh:
         json.dump(out, fh, indent=1)
     print(f"done in {time.time() - t0:.0f} s")
 

@@ -157,6 +157,39 @@ def test_single_step_parity_white_noise_fields(gga, model_dict):
         assert bad == 0 and frac <= 2e-3
 
 
+@pytest.mark.parametrize("L,warm,event", [(64, 150, True), (128, 240, False)])
+def test_single_step_parity_from_gpu_state(gga, model_dict, L, warm, event):
+    """The other direction: the HIP path advances its own initial state `warm`
+    steps; the oracle takes that state (fields converted to physical units in
+    float64) and both sides step once.  Same bar as from oracle states."""
+    md = high_uptake(model_dict)
+    prm = Params.from_dict(md)
+    P, R, seed, substeps = 1, 3, 21, 10
+    dose = np.array([[2.0, 2.5]], np.float32)
+    gap = np.array([[warm if event else warm + 7, 30]], np.int32)
+    nfrac = np.array([2], np.int32)
+    cfg = gga.make_cfg(L, warm + 1, R, seed=seed, substeps=substeps, dose_cap=100.0)
+    dd = _dev(dose, gap, nfrac)
+    f_d, c_d = gga.state_init(md, cfg, P)
+    gga.state_run(md, cfg, *dd, 0, warm, f_d, c_d)
+    start = from_field_units(f_d.cpu().numpy(), prm)
+    cells = c_d.cpu().numpy().view(np.uint16).copy()
+    live, _ = gga.state_run(md, cfg, *dd, warm, 1, f_d, c_d)
+    got_f = from_field_units(f_d.cpu().numpy(), prm)
+    got_c, live = c_d.cpu().numpy().view(np.uint16), live.cpu().numpy()
+    ev = dict(protocol.events(dose[0], gap[0], nfrac[0], warm + 1, prm))
+    assert (warm in ev) == event
+    assert ((cells & 3) == 2).any()                 # quiescent cells: the environment rules act
+    for r in range(R):
+        f_ref, c_ref, counted = oracle_step_detail(start[r], cells[r].astype(np.int64), warm, ev.get(warm), 0, r,
+                                                   seed, prm, substeps)
+        assert field_error(got_f[r], f_ref) <= FIELD_RTOL
+        bad, frac = compare_cells(got_c[r], c_ref, counted)
+        assert bad == 0 and frac <= MAX_COUNTED_FRACTION, (r, bad, frac)
+        if not counted.any():
+            assert live[0, r] == sim.live_count(c_ref)
+
+
 def test_multi_step_state_run_equals_simulate(gga, model_dict):
     """Running 40 steps as 40 one-step calls from the initial state gives the
     same trajectory as one simulate call (same kernel, state round trip)."""

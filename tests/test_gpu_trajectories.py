@@ -6,8 +6,10 @@ Kolmogorov-Smirnov tests over replicate runs): final live counts of the HIP
 path under one run seed against stored oracle replicas under another seed;
 the 95 % confidence interval of the mean difference must contain 0 (Welch)
 and the two-sample KS p-value must exceed 0.05.  Three cases at level 0.05
-each (multiplicity stated: three tests).  Same seeds: the share of replicas
-whose final counts agree exactly is reported.
+each (multiplicity stated: three tests), and a family of 16 batched-workload
+protocols tested as one family at level 0.05 (combined statistics, with a
+Bonferroni bound per protocol).  Same seeds: the share of replicas whose
+final counts agree exactly is reported.
 
 Full size: the batched workload (1,024 protocols x 4 replicas, 128 x 128,
 480 steps) in bench.py's launch configuration, with sampled instances checked
@@ -45,6 +47,12 @@ def golden():
         return json.load(fh)
 
 
+@pytest.fixture(scope="module")
+def family():
+    with open(os.path.join(HERE, "golden", "oracle_batched16.json")) as fh:
+        return json.load(fh)
+
+
 def _model(md, name):
     if name == "high_uptake":
         md = copy.deepcopy(md)
@@ -77,6 +85,45 @@ def test_final_count_distribution_matches_oracle(gga, model_dict, golden, name):
     assert t.pvalue > 0.05 and ks.pvalue > 0.05
     if name == "plain_bmii_64":
         assert match == 1.0     # no site ever comes near a threshold in this case
+    assert match >= 0.25
+
+
+def test_batched_family_distributions_match_oracle(gga, model_dict, family):
+    """16 protocols of the batched workload run as one batch of 16, 200
+    replicas each, against stored oracle replicas under another run seed.
+    One family at family-wise level 0.05: the standardised mean differences'
+    sum of squares against chi2(16) and Fisher's combination of the 16 KS
+    p-values against chi2(32), each at 0.05, and every protocol's Welch and KS
+    p-values above the Bonferroni level 0.05 / 16.  Same seeds: at least a
+    quarter of all replicas end with the oracle's exact count."""
+    cases = sorted((v for k, v in family.items() if k.startswith("batched_")), key=lambda c: c["p"])
+    assert [c["p"] for c in cases] == list(range(16))
+    R = cases[0]["R"]
+    dd = [torch.tensor([c[k] for c in cases], dtype=dt, device="cuda")
+          for k, dt in (("dose", torch.float32), ("gap", torch.int32))]
+    nfrac = torch.tensor([c["nfrac"] for c in cases], dtype=torch.int32, device="cuda")
+
+    def run(seed):
+        cfg = gga.make_cfg(128, 480, R, seed=seed, substeps=10, dose_cap=100.0)
+        return gga.simulate(model_dict, cfg, *dd, nfrac)[0].cpu().numpy()
+
+    got, same = run(GPU_SEED), run(family["seed"])
+    z2, fisher, matches = 0.0, 0.0, 0
+    for j, c in enumerate(cases):
+        ref, g = np.array(c["live"], np.float64), got[j].astype(np.float64)
+        t = stats.ttest_ind(g, ref, equal_var=False)
+        ks = stats.ks_2samp(g, ref)
+        z = (g.mean() - ref.mean()) / np.sqrt(g.var(ddof=1) / len(g) + ref.var(ddof=1) / len(ref))
+        z2 += z * z
+        fisher += -2.0 * np.log(max(ks.pvalue, 1e-300))
+        matches += int(np.sum(same[j] == np.array(c["live"])))
+        print(f"protocol {c['sample_index']}: gpu mean {g.mean():.1f} | oracle mean {ref.mean():.1f} | "
+              f"Welch p {t.pvalue:.3f} KS p {ks.pvalue:.3f}")
+        assert t.pvalue > 0.05 / 16 and ks.pvalue > 0.05 / 16, c["sample_index"]
+    p_mean, p_ks = stats.chi2.sf(z2, 16), stats.chi2.sf(fisher, 32)
+    match = matches / (16 * R)
+    print(f"family: mean chi2(16) p {p_mean:.3f}, Fisher KS chi2(32) p {p_ks:.3f}, same-seed exact match {match:.3f}")
+    assert p_mean > 0.05 and p_ks > 0.05
     assert match >= 0.25
 
 

@@ -132,15 +132,9 @@ __device__ __forceinline__ void store_keys(uint32_t* p, const uint32_t (&k)[CPL]
 // the whole lattice (resident).  RR < L: a slab of a larger lattice advanced by
 // one step per launch (the rows within `substeps + 2` of a slab edge that is
 // not a lattice edge are a halo, recomputed by the neighbouring slab).
-// Register slot of row i after k sub-steps of a rotating chunk (S = RPT + 1 slots).
+// Register slot of row i after k forward rotating sub-steps (S = RPT + 1 slots).
 template <int S>
 constexpr int rot_slot(int i, int k) { return ((i - k) % S + S) % S; }
-
-// fn(integral_constant<int, K>) for K = 0, 1, ..., in order, at compile time
-template <int... Ks, class Fn>
-__device__ __forceinline__ void for_each_index(std::integer_sequence<int, Ks...>, Fn&& fn) {
-    (fn(std::integral_constant<int, Ks>{}), ...);
-}
 
 template <int CPL, int RPT, int NW>
 struct Geo {
@@ -404,16 +398,18 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) Ro[i][c] = kapO * actv[cellp[i * L + c] & 3];
 
-        // (3) diffusion sub-steps.  Within a chunk of RPT + 1 sub-steps the rows
-        // rotate through the RPT + 1 register slots: new row i is written over
-        // old row i - 1, which row i was the last to read, so no row is copied,
-        // and after the chunk every row is back in its own slot.  Leftover
-        // sub-steps run one at a time with a copy of the row above.
+        // (3) diffusion sub-steps, in pairs over the RPT + 1 register slots with
+        // no row copied: a forward sub-step (rows top to bottom) writes new row
+        // i over old row i - 1, which row i was the last to read, moving every
+        // row one slot down; the reverse sub-step that follows (rows bottom to
+        // top) writes new row i over old row i + 1 and moves them back, so after
+        // each pair every row is in its own slot again.  An odd last sub-step
+        // runs in the plain form with a copy of the row above.
         // Per field and column: the halo rows of this wave's neighbours, then
         // c' = lam (up + below + west + east) + (c cen + r).
         auto halo = [&](auto slot0, auto slotL, int par, float (&up)[3][CPL], float (&dn)[3][CPL]) {
-            // Keep the glucose / acid terms from being hoisted out of the loop
-            // (they would cost two live VGPRs per site): Ro is opaque here.
+            // Ro is opaque here, so nothing derived from it is hoisted out of
+            // the sub-step loop to hold VGPRs across it.
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
 #pragma unroll
@@ -471,6 +467,35 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                     }
             }
         };
+        // Reverse sub-step with the map of the forward one k (row i in slot
+        // rot_slot(i, k)); afterwards row i is in slot rot_slot(i, k - 1).
+        auto reverse_substep = [&](auto KC, int par) {
+            constexpr int k = decltype(KC)::value;
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int j = 0; j <= RPT; ++j)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) asm volatile("" : "+v"(F[f][j][c]));
+            float up[3][CPL], dn[3][CPL];
+            halo(std::integral_constant<int, rot_slot<RPT + 1>(0, k)>{},
+                 std::integral_constant<int, rot_slot<RPT + 1>(RPT - 1, k)>{}, par, up, dn);
+#pragma unroll
+            for (int i = RPT - 1; i >= 0; --i) {
+                const int si = rot_slot<RPT + 1>(i, k), sb = rot_slot<RPT + 1>(i + 1, k);
+#pragma unroll
+                for (int f = 0; f < 3; ++f)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const float above = (i == 0) ? up[f][c] : F[f][rot_slot<RPT + 1>(i - 1, k)][c];
+                        const float below = (i < RPT - 1) ? F[f][sb][c] : dn[f][c];
+                        const float west = (c > 0) ? F[f][si][c - 1] : lane_from_left(F[f][si][CPL - 1]);
+                        const float east = (c < CPL - 1) ? F[f][si][c + 1] : lane_from_right(F[f][si][0]);
+                        // old row i + 1 (slot sb; the spare slot for the last row) is dead once row i has read it
+                        F[f][sb][c] = update(f, i, c, above, below, west, east, F[f][si][c]);
+                    }
+            }
+        };
         auto plain_substep = [&](int par) {
             float up[3][CPL], dn[3][CPL];
             halo(std::integral_constant<int, 0>{}, std::integral_constant<int, RPT - 1>{}, par, up, dn);
@@ -502,11 +527,11 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             reinterpret_cast<float*>(s_pool)[blk * (NWAVE + 1) * G::BLK + off] = 0.0f;   // the boundary, in field units
         }
         int s = 0;
-        for (; s + RPT + 1 <= a.substeps; s += RPT + 1)
-            for_each_index(std::make_integer_sequence<int, RPT + 1>{}, [&](auto KC) {
-                rotating_substep(KC, (s + decltype(KC)::value) & 1);
-            });
-        for (; s < a.substeps; ++s) plain_substep(s & 1);
+        for (; s + 2 <= a.substeps; s += 2) {
+            rotating_substep(std::integral_constant<int, 0>{}, s & 1);
+            reverse_substep(std::integral_constant<int, 1>{}, (s + 1) & 1);
+        }
+        if (s < a.substeps) plain_substep(s & 1);
 
         // (4) cell update, bit-parallel over the thread's RPT x CPL sites
         // (bit idx = i * CPL + c of 32-bit masks).  Proposers claim an EMPTY

@@ -8,7 +8,8 @@ tests, on the same seeded inputs.
 
 Modules: philox (Philox4x32-10), model (constants), protocol (validation,
 events, LQ thresholds, counting and sampling of protocols), sim (the lattice
-automaton), ga (GA operators), mlp (float64 surrogate network), sga (one
-generation of the surrogate-screened GA with a random screen).
+automaton), ga (GA operators), ga_slots (the GA over the time-slot genome),
+mlp (float64 surrogate network), sga (one generation of the surrogate-screened
+GA with a random screen).
 """
-from . import ga, mlp, model, philox, protocol, sga, sim  # noqa: F401
+from . import ga, ga_slots, mlp, model, philox, protocol, sga, sim  # noqa: F401

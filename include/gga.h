@@ -304,6 +304,102 @@ int gga_ga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cf
                float* best_dose_d, int32_t* best_gap_d, float* gen_ms_h, hipStream_t stream);
 
 /*
+ * GA over the paper's sparse time-slot genome (Materials and Methods, "GA
+ * Resolution, constraints" and "Protocol Representation"; appendix "GA
+ * Operators: additional details").  A genome is S bytes, one per hour of the
+ * treatment window: the dose given at the start of that hour in quanta of
+ * `quantum` Gy (0: no dose).  Guarded genomes hold no dose above dmax_q, no two
+ * doses closer than g_min hours, and at most cap_q quanta in total.
+ * Set struct_size = sizeof(gga_slot_cfg).
+ */
+#define GGA_SLOTS_MAX 256
+#define GGA_SMUT_SWAP 1         /* a dose and another slot exchange contents          */
+#define GGA_SMUT_SPLIT 2        /* a dose of >= 2 quanta splits into two placed doses  */
+#define GGA_SMUT_TIME 4         /* a dose moves to another slot (what fits)            */
+#define GGA_SMUT_VALUE 8        /* a dose grows, while the total is under the cap      */
+typedef struct gga_slot_cfg {
+    uint32_t struct_size;
+    int32_t S;              /* slots (hours) in the window, 1 .. GGA_SLOTS_MAX        */
+    int32_t g_min;          /* minimal interval between doses in hours, 1 .. S         */
+    int32_t dmax_q;         /* maximal single dose in quanta, 1 .. 255                */
+    int32_t cap_q;          /* cap on the total in quanta, 0 .. 65535                 */
+    int32_t mutation;       /* GGA_SMUT_* bits, applied in the order swap, split, time,
+                               value; 0 = swap | split | time (the operators of the
+                               paper's final GA experiments)                         */
+    float quantum;          /* Gy per quantum, finite, > 0                             */
+    int32_t reserved;       /* 0                                                      */
+} gga_slot_cfg;
+
+/*
+ * One GA breeding step over slot genomes, stream-ordered: rank by (fitness,
+ * index) with NaN last, copy the ga->n_elite best to rows 0 .. n_elite - 1,
+ * and fill the other rows with children: parents by ga->selection (as
+ * gga_ga_breed), crossover by ga->crossover over slots (one point, the middle
+ * cut between 25 % and 75 % of the window, two points with the first in
+ * 25 .. 50 % and the second in 50 .. 75 %, or uniform), each mutation of
+ * sc->mutation with probability ga->p_mut, then the guards: clamp to dmax_q;
+ * a dose less than g_min after the last kept one moves to the first later
+ * slot with no dose within g_min - 1 hours, or is dropped when there is none;
+ * while the total exceeds cap_q the largest dose (first among equals) loses a
+ * quantum.  Random words: Philox blocks (pair, generation, 0x47414741, sub)
+ * keyed by ga->seed, generation read from *generation_d.
+ *   fitness_d[N], pop_d[N][S]      current population (device)
+ *   order_d[N], position_d[N]      rank outputs (device)
+ *   next_d[N][S]                   next population (device; not pop_d)
+ * Requires 2 <= N, ga->mutation == 0 (sc->mutation selects the operators).
+ * Errors: GGA_E_ARG, GGA_E_ABI, GGA_E_HIP.
+ */
+int gga_slots_breed(const gga_ga_cfg* ga, const gga_slot_cfg* sc, const float* fitness_d,
+                    const uint8_t* pop_d, int32_t N, const int32_t* generation_d, int32_t* order_d,
+                    int32_t* position_d, uint8_t* next_d, hipStream_t stream);
+
+/*
+ * Slot genomes to simulation protocols, stream-ordered: the doses in slot
+ * order, dose_d[p][j] = quanta x quantum (float32 product), delay_1 = slot of
+ * the first dose and later delays the slot differences; nfrac_d[p] = number of
+ * doses, at most K (a genome with more doses gives its first K; a guarded one
+ * holds at most ceil(S / g_min)).  Entries past nfrac are 0.
+ *   pop_d[P][S] (device) -> dose_d[P][K], gap_h_d[P][K], nfrac_d[P] (device)
+ * Requires 1 <= K <= GGA_KMAX.  Errors: GGA_E_ARG, GGA_E_ABI, GGA_E_HIP.
+ */
+int gga_slots_decode(const gga_slot_cfg* sc, const uint8_t* pop_d, int32_t P, int32_t K, float* dose_d,
+                     int32_t* gap_h_d, int32_t* nfrac_d, hipStream_t stream);
+
+/*
+ * Simulation protocols to guarded slot genomes, stream-ordered: fraction j
+ * (j < nfrac, nfrac clipped to 0 .. K) adds round(dose_j / quantum) quanta
+ * (float32 quotient, ties to even; 0 unless positive; a slot saturates at 255)
+ * at hour delay_1 + .. + delay_j, until that hour falls outside 0 .. S - 1;
+ * then the three guards run.
+ *   dose_d[P][K], gap_h_d[P][K], nfrac_d[P] (device) -> pop_d[P][S] (device)
+ * Requires 1 <= K <= GGA_KMAX.  Errors: GGA_E_ARG, GGA_E_ABI, GGA_E_HIP.
+ */
+int gga_slots_encode(const gga_slot_cfg* sc, const float* dose_d, const int32_t* gap_h_d,
+                     const int32_t* nfrac_d, int32_t P, int32_t K, uint8_t* pop_d, hipStream_t stream);
+
+/* Device workspace of gga_slots_run for N genomes x R replicas, K fractions. */
+size_t gga_slots_workspace_bytes(int32_t N, int32_t R, int32_t K);
+
+/*
+ * Run generations g0 .. g0 + n_gen - 1 of the slot GA from population A,
+ * alternating A -> B and B -> A (the last bred population is in A when n_gen
+ * is even, in B otherwise).  Each generation decodes its genomes (K fraction
+ * slots), simulates each R times (Philox key cfg->seed + g x
+ * 0x9E3779B97F4A7C15), reduces the fitness, records hist_d[g] = (best, mean)
+ * and the best protocol's decoded genes (best_dose_d / best_gap_d row g, both
+ * NULL or both [g0 + n_gen][K] device arrays), and breeds the next population
+ * as gga_slots_breed.  use_graph as gga_ga_run; gen_ms_h as gga_ga_run.
+ *   pop_a_d[N][S], pop_b_d[N][S] (device), hist_d[g0 + n_gen][2] (device)
+ * Requires K >= ceil(S / g_min) (every guarded dose is simulated).
+ * Synchronous.  Errors: as gga_simulate and gga_slots_breed; GGA_E_ARG for a
+ * small workspace.
+ */
+int gga_slots_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga,
+                  const gga_slot_cfg* sc, uint8_t* pop_a_d, uint8_t* pop_b_d, int32_t N, int32_t K,
+                  int32_t g0, int32_t n_gen, int32_t use_graph, void* ws_d, size_t ws_bytes, float* hist_d,
+                  float* best_dose_d, int32_t* best_gap_d, float* gen_ms_h, hipStream_t stream);
+
+/*
  * Surrogate of the simulation for pre-screening GA offspring (not part of the
  * paper's method): an MLP from an encoded protocol (40 fractions x (dose / 5
  * Gy, delay / 60 h, present), zero-padded to 128 features) through three

@@ -73,9 +73,19 @@ class GaCfg(ctypes.Structure):
     ]
 
 
+class SlotCfg(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("S", ctypes.c_int32), ("g_min", ctypes.c_int32),
+        ("dmax_q", ctypes.c_int32), ("cap_q", ctypes.c_int32), ("mutation", ctypes.c_int32),
+        ("quantum", ctypes.c_float), ("reserved", ctypes.c_int32),
+    ]
+
+
 SELECTIONS = {"tournament": 0, "rank": 1, "roulette": 2, "truncation": 3}
 CROSSOVERS = {"one_point": 0, "middle": 1, "two_point": 2, "uniform": 3}
 MUTATIONS = {"gene": 1, "swap": 2, "raise": 4}
+SLOT_MUTATIONS = {"swap": 1, "split": 2, "time": 4, "value": 8}
+SLOTS_MAX = 256
 
 
 def _load():
@@ -133,6 +143,12 @@ def _load():
         "gga_autotune": ([vp, vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, vp, vp, vp], ctypes.c_int),
         "gga_measure_peaks": ([vp, ctypes.c_size_t, vp, vp, vp, vp], ctypes.c_int),
         "gga_params_from_json": ([ctypes.c_char_p, vp], ctypes.c_int),
+        "gga_slots_breed": ([vp, vp, vp, vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
+        "gga_slots_decode": ([vp, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
+        "gga_slots_encode": ([vp, vp, vp, vp, i32, i32, vp, vp], ctypes.c_int),
+        "gga_slots_workspace_bytes": ([i32, i32, i32], ctypes.c_size_t),
+        "gga_slots_run": ([vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, ctypes.c_size_t, vp, vp, vp, vp,
+                           vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -151,7 +167,8 @@ EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
            "gga_variant_count", "gga_variant_side", "gga_variant_is_slab", "gga_variant_name", "gga_get_variant",
            "gga_set_variant", "gga_uneven_workspace_bytes", "gga_simulate_uneven", "gga_event_table_bytes",
            "gga_state_run_variant", "gga_autotune_workspace_bytes", "gga_autotune", "gga_simulate_library",
-           "gga_measure_peaks", "gga_params_from_json")
+           "gga_measure_peaks", "gga_params_from_json", "gga_slots_breed", "gga_slots_decode",
+           "gga_slots_encode", "gga_slots_workspace_bytes", "gga_slots_run")
 
 
 class GGAError(RuntimeError):
@@ -528,6 +545,90 @@ def ga_run(params, cfg, ga, alphabet, dose, gap, n_gen, use_graph, g0=0, hist=No
     if arc is not None:
         return final[0], final[1], h[:g0 + n_gen], gen_ms[:n_gen], (arc[0][:g0 + n_gen], arc[1][:g0 + n_gen])
     return final[0], final[1], h[:g0 + n_gen], gen_ms[:n_gen]
+
+
+# ---------------------------------------------------------------- time-slot GA
+
+def make_slots(S=120, g_min=6, dmax_q=20, cap_q=40, quantum=0.25, mutation=()):
+    """Slot-genome settings: S hourly slots, minimal interval g_min hours,
+    single doses up to dmax_q quanta, total up to cap_q quanta of `quantum`
+    Gy; mutation names GGA_SMUT_* operators (empty: swap, split, time)."""
+    c = SlotCfg()
+    c.struct_size = ctypes.sizeof(SlotCfg)
+    c.S, c.g_min, c.dmax_q, c.cap_q = int(S), int(g_min), int(dmax_q), int(cap_q)
+    c.mutation = sum(SLOT_MUTATIONS[m] for m in set(mutation))
+    c.quantum = float(quantum)
+    return c
+
+
+def _genomes(pop, sc):
+    if not (pop.is_cuda and pop.dtype == torch.uint8 and pop.is_contiguous() and pop.dim() == 2
+            and pop.shape[1] == sc.S):
+        raise ValueError("genomes must be a contiguous uint8 CUDA tensor of shape [P, S]")
+    return pop.shape[0]
+
+
+def slots_breed(ga, sc, fitness, pop, generation, stream=None):
+    """One breeding step over uint8 genomes pop [N][S]; generation is an int32
+    CUDA tensor of one element.  Returns (order, position, next_pop)."""
+    N = _genomes(pop, sc)
+    if not (fitness.is_cuda and fitness.dtype == torch.float32 and fitness.numel() == N and fitness.is_contiguous()):
+        raise ValueError("fitness must be a contiguous float32 CUDA tensor of N values")
+    if not (generation.is_cuda and generation.dtype == torch.int32 and generation.numel() >= 1):
+        raise ValueError("generation must be an int32 CUDA tensor")
+    order = torch.empty(N, dtype=torch.int32, device=pop.device)
+    pos = torch.empty(N, dtype=torch.int32, device=pop.device)
+    nxt = torch.empty_like(pop)
+    _check(LIB.gga_slots_breed(ctypes.byref(ga), ctypes.byref(sc), _ptr(fitness), _ptr(pop), N, _ptr(generation),
+                               _ptr(order), _ptr(pos), _ptr(nxt), _stream(stream)))
+    return order, pos, nxt
+
+
+def slots_decode(sc, pop, K, stream=None):
+    """(dose [P][K], gap [P][K], nfrac [P]) of genomes pop [P][S]."""
+    P = _genomes(pop, sc)
+    dose = torch.empty((P, K), dtype=torch.float32, device=pop.device)
+    gap = torch.empty((P, K), dtype=torch.int32, device=pop.device)
+    nfrac = torch.empty(P, dtype=torch.int32, device=pop.device)
+    _check(LIB.gga_slots_decode(ctypes.byref(sc), _ptr(pop), P, int(K), _ptr(dose), _ptr(gap), _ptr(nfrac),
+                                _stream(stream)))
+    return dose, gap, nfrac
+
+
+def slots_encode(sc, dose, gap, nfrac, stream=None):
+    """Guarded uint8 genomes [P][S] of protocols (dose, gap, nfrac)."""
+    P, K = _protocols(dose, gap, nfrac)
+    pop = torch.empty((P, sc.S), dtype=torch.uint8, device=dose.device)
+    _check(LIB.gga_slots_encode(ctypes.byref(sc), _ptr(dose), _ptr(gap), _ptr(nfrac), P, K, _ptr(pop),
+                                _stream(stream)))
+    return pop
+
+
+def slots_run(params, cfg, ga, sc, pop, K, n_gen, use_graph, g0=0, archive=False):
+    """Run slot-GA generations g0 .. g0+n_gen-1 from genomes pop (not
+    modified), simulating K fraction slots per protocol.  Returns (final pop,
+    hist[g0+n_gen, 2] (best, mean), gen_ms[n_gen]) and, with archive=True, a
+    fourth value (best_dose, best_gap) per generation."""
+    N = _genomes(pop, sc)
+    a, b = pop.clone(), torch.empty_like(pop)
+    ws = torch.empty(int(LIB.gga_slots_workspace_bytes(N, cfg.R, int(K))), dtype=torch.uint8, device=pop.device)
+    rows = max(g0 + n_gen, 1)
+    h = torch.full((rows, 2), float("nan"), dtype=torch.float32, device=pop.device)
+    gen_ms = np.zeros(max(n_gen, 1), dtype=np.float32)
+    arc = _archive(None, rows, int(K), pop.device) if archive else None
+    side = torch.cuda.Stream(device=pop.device)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        _check(LIB.gga_slots_run(ctypes.byref(_as_params(params)), ctypes.byref(cfg), ctypes.byref(ga),
+                                 ctypes.byref(sc), _ptr(a), _ptr(b), N, int(K), int(g0), int(n_gen),
+                                 int(bool(use_graph)), _ptr(ws), ws.numel(), _ptr(h),
+                                 _ptr(arc[0]) if arc else None, _ptr(arc[1]) if arc else None,
+                                 gen_ms.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(side.cuda_stream)))
+    torch.cuda.current_stream().wait_stream(side)
+    final = a if n_gen % 2 == 0 else b
+    if arc is not None:
+        return final, h[:g0 + n_gen], gen_ms[:n_gen], (arc[0][:g0 + n_gen], arc[1][:g0 + n_gen])
+    return final, h[:g0 + n_gen], gen_ms[:n_gen]
 
 
 # ---------------------------------------------------------------- surrogate MLP

@@ -10,6 +10,7 @@
 #include "gga_internal.h"
 #include "mlp_internal.h"
 #include "peaks.h"
+#include "slots.h"
 
 namespace {
 
@@ -309,18 +310,44 @@ uint32_t prob_threshold(double p) {
     return t >= 4294967295.0 ? 0xFFFFFFFFu : static_cast<uint32_t>(t);
 }
 
-int check_ga(const gga_ga_cfg* ga, const gga_alphabet* a, int32_t N, int32_t K, gga::GaArgs* out) {
-    if (!ga || !a) return GGA_E_ARG;
-    if (ga->struct_size != sizeof(gga_ga_cfg) || a->struct_size != sizeof(gga_alphabet)) return GGA_E_ABI;
-    if (N < 2 || K < 1 || K > GGA_KMAX) return GGA_E_ARG;
+// Selection, crossover and probability settings shared by both GAs; fills the
+// matching fields of *out (zeroing the rest).
+int check_ga_ops(const gga_ga_cfg* ga, int32_t N, gga::GaArgs* out) {
+    if (!ga) return GGA_E_ARG;
+    if (ga->struct_size != sizeof(gga_ga_cfg)) return GGA_E_ABI;
+    if (N < 2) return GGA_E_ARG;
     if (ga->n_elite < 0 || ga->n_elite > N || ga->tournament_k < 1 || ga->tournament_k > 64) return GGA_E_ARG;
     if (!(ga->p_cross >= 0.0 && ga->p_cross <= 1.0) || !(ga->p_mut >= 0.0 && ga->p_mut <= 1.0)) return GGA_E_ARG;
-    if (ga->selection < 0 || ga->selection > 3 || ga->crossover < 0 || ga->crossover > 3 || ga->mutation < 0 ||
-        ga->mutation > 7 || ga->reserved != 0)
+    if (ga->selection < 0 || ga->selection > 3 || ga->crossover < 0 || ga->crossover > 3 || ga->reserved != 0)
         return GGA_E_ARG;
     if (ga->selection == GGA_SEL_RANK && !(ga->q > 0.0 && ga->q <= 1.0)) return GGA_E_ARG;
     if (ga->selection == GGA_SEL_TRUNCATION && !(ga->trunc_frac > 0.0 && ga->trunc_frac <= 1.0)) return GGA_E_ARG;
     if (ga->selection == GGA_SEL_ROULETTE && !std::isfinite(ga->roulette_base)) return GGA_E_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->N = N;
+    out->n_out = N;
+    out->n_elite = ga->n_elite;
+    out->k = ga->tournament_k;
+    out->t_cross = prob_threshold(ga->p_cross);
+    out->t_mut = prob_threshold(ga->p_mut);
+    out->selection = ga->selection;
+    out->crossover = ga->crossover;
+    out->t_q = ga->selection == GGA_SEL_RANK ? prob_threshold(ga->q) : 0u;
+    out->trunc_m = ga->selection == GGA_SEL_TRUNCATION
+                       ? std::max(1, std::min(N, static_cast<int>(std::floor(ga->trunc_frac * N))))
+                       : 0;
+    out->roulette_base = ga->roulette_base;
+    out->seed_lo = static_cast<uint32_t>(ga->seed);
+    out->seed_hi = static_cast<uint32_t>(ga->seed >> 32);
+    return GGA_OK;
+}
+
+int check_ga(const gga_ga_cfg* ga, const gga_alphabet* a, int32_t N, int32_t K, gga::GaArgs* out) {
+    if (!ga || !a) return GGA_E_ARG;
+    if (ga->struct_size != sizeof(gga_ga_cfg) || a->struct_size != sizeof(gga_alphabet)) return GGA_E_ABI;
+    if (K < 1 || K > GGA_KMAX || ga->mutation < 0 || ga->mutation > 7) return GGA_E_ARG;
+    const int rc = check_ga_ops(ga, N, out);
+    if (rc) return rc;
     if (a->n_dose < 1 || a->n_dose > GGA_ALPHABET_MAX || a->n_gap < 1 || a->n_gap > GGA_ALPHABET_MAX)
         return GGA_E_ALPHABET;
     if (!(std::isfinite(a->dose_quantum) && a->dose_quantum > 0.0f) || !(std::isfinite(a->cap) && a->cap >= 0.0f))
@@ -331,31 +358,39 @@ int check_ga(const gga_ga_cfg* ga, const gga_alphabet* a, int32_t N, int32_t K, 
         if (a->gaps[i] < 1) return GGA_E_ALPHABET;
     const double capq = std::floor((double)a->cap / (double)a->dose_quantum + 1e-9);
     if (capq > 1e6 || (long long)K * a->dose_q[0] > capq) return GGA_E_ALPHABET;   // guard must succeed
-    std::memset(out, 0, sizeof(*out));
-    out->N = N;
-    out->n_out = N;
     out->K = K;
-    out->n_elite = ga->n_elite;
-    out->k = ga->tournament_k;
     out->n_dose = a->n_dose;
     out->n_gap = a->n_gap;
     out->cap_q = static_cast<int32_t>(capq);
-    out->t_cross = prob_threshold(ga->p_cross);
-    out->t_mut = prob_threshold(ga->p_mut);
-    out->selection = ga->selection;
-    out->crossover = ga->crossover;
     out->mutation = ga->mutation ? ga->mutation : GGA_MUT_GENE;
-    out->t_q = ga->selection == GGA_SEL_RANK ? prob_threshold(ga->q) : 0u;
-    out->trunc_m = ga->selection == GGA_SEL_TRUNCATION
-                       ? std::max(1, std::min(N, static_cast<int>(std::floor(ga->trunc_frac * N))))
-                       : 0;
-    out->roulette_base = ga->roulette_base;
-    out->seed_lo = static_cast<uint32_t>(ga->seed);
-    out->seed_hi = static_cast<uint32_t>(ga->seed >> 32);
     out->quantum = a->dose_quantum;
     std::memcpy(out->dose_q, a->dose_q, sizeof(out->dose_q));
     std::memcpy(out->gaps, a->gaps, sizeof(out->gaps));
     return GGA_OK;
+}
+
+int check_slots(const gga_slot_cfg* sc) {
+    if (!sc) return GGA_E_ARG;
+    if (sc->struct_size != sizeof(gga_slot_cfg)) return GGA_E_ABI;
+    if (sc->S < 1 || sc->S > GGA_SLOTS_MAX || sc->g_min < 1 || sc->g_min > sc->S) return GGA_E_ARG;
+    if (sc->dmax_q < 1 || sc->dmax_q > 255 || sc->cap_q < 0 || sc->cap_q > 65535) return GGA_E_ARG;
+    if (sc->mutation < 0 || sc->mutation > 15 || sc->reserved != 0) return GGA_E_ARG;
+    if (!(std::isfinite(sc->quantum) && sc->quantum > 0.0f)) return GGA_E_ARG;
+    return GGA_OK;
+}
+
+// Slot GA arguments from checked settings.
+gga::SlotArgs slot_args(const gga::GaArgs& ops, const gga_slot_cfg* sc) {
+    gga::SlotArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.sel = ops;
+    a.S = sc->S;
+    a.g_min = sc->g_min;
+    a.dmax = sc->dmax_q;
+    a.cap_q = sc->cap_q;
+    a.mutation = sc->mutation ? sc->mutation : (GGA_SMUT_SWAP | GGA_SMUT_SPLIT | GGA_SMUT_TIME);
+    a.quantum = sc->quantum;
+    return a;
 }
 
 // Enqueue one generation; all arguments already checked.
@@ -426,6 +461,60 @@ hipError_t run_generations(F enqueue, int32_t* counter, int32_t g0, int32_t n_ge
     }
     for (auto& x : ev)
         if (x) (void)hipEventDestroy(x);
+    return e;
+}
+
+struct SlotWorkspace {
+    GaWorkspace ga;
+    float* dose;
+    int32_t* gap;
+    int32_t* nfrac;
+};
+
+size_t slots_ws_bytes(int32_t N, int32_t R, int32_t K) {
+    return ga_ws_bytes(N, R) + 2 * align256(sizeof(int32_t) * (size_t)N * K) + align256(sizeof(int32_t) * (size_t)N);
+}
+
+SlotWorkspace slots_ws(void* ws, int32_t N, int32_t R, int32_t K) {
+    SlotWorkspace w;
+    w.ga = ga_ws(ws, N, R);
+    char* p = static_cast<char*>(ws) + ga_ws_bytes(N, R);
+    w.dose = reinterpret_cast<float*>(p);
+    p += align256(sizeof(int32_t) * (size_t)N * K);
+    w.gap = reinterpret_cast<int32_t*>(p);
+    p += align256(sizeof(int32_t) * (size_t)N * K);
+    w.nfrac = reinterpret_cast<int32_t*>(p);
+    return w;
+}
+
+// Enqueue one slot-GA generation (decode, simulate, fitness, rank, history,
+// breed); all arguments already checked.
+hipError_t enqueue_slot_generation(const gga_params* params, const gga_sim_cfg* cfg, gga::SlotArgs sl,
+                                   const uint8_t* pop, int32_t N, int32_t K, uint8_t* next, const SlotWorkspace& w,
+                                   float* hist, int32_t hist_cap, float* best_dose, int32_t* best_gap,
+                                   int32_t advance, hipStream_t stream) {
+    hipError_t e = gga::launch_slot_decode(pop, N, sl.S, K, sl.quantum, w.dose, w.gap, w.nfrac, stream);
+    gga::SimArgs sa = make_args(params, cfg, w.dose, w.gap, w.nfrac, K);
+    sa.n0 = 0;
+    sa.nsteps = cfg->horizon;
+    sa.mode = 0;
+    sa.live = w.ga.live;
+    sa.generation = w.ga.generation;
+    sa.seed = cfg->seed;
+    if (e == hipSuccess) e = gga::launch_simulation(sa, cfg->L, N * cfg->R, stream);
+    if (e == hipSuccess) e = gga::launch_fitness(w.ga.live, N, cfg->R, w.ga.fitness, stream);
+    if (e == hipSuccess) e = gga::launch_rank(w.ga.fitness, N, w.ga.order, w.ga.position, stream);
+    const gga::Archive arc{w.dose, w.gap, K, best_dose, best_gap};
+    if (e == hipSuccess)
+        e = gga::launch_history(w.ga.fitness, N, w.ga.order, w.ga.generation, hist, hist_cap, arc, stream);
+    sl.sel.fitness = w.ga.fitness;
+    sl.sel.order = w.ga.order;
+    sl.sel.position = w.ga.position;
+    sl.sel.generation = w.ga.generation;
+    sl.pop = pop;
+    sl.next = next;
+    if (e == hipSuccess) e = gga::launch_slot_offspring(sl, stream);
+    if (e == hipSuccess && advance) e = gga::launch_counter(w.ga.generation, 1, 1, stream);
     return e;
 }
 
@@ -509,6 +598,87 @@ int gga_ga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cf
                                   hist_d, hist_cap, best_dose_d, best_gap_d, 1, stream);
     };
     const hipError_t e = run_generations(enqueue, w.generation, g0, n_gen, use_graph, gen_ms_h, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_slots_breed(const gga_ga_cfg* ga, const gga_slot_cfg* sc, const float* fitness_d, const uint8_t* pop_d,
+                    int32_t N, const int32_t* generation_d, int32_t* order_d, int32_t* position_d, uint8_t* next_d,
+                    hipStream_t stream) {
+    int rc = check_slots(sc);
+    if (rc) return rc;
+    gga::GaArgs ops;
+    if ((rc = check_ga_ops(ga, N, &ops))) return rc;
+    if (ga->mutation != 0) return GGA_E_ARG;
+    if (!fitness_d || !pop_d || !generation_d || !order_d || !position_d || !next_d || next_d == pop_d)
+        return GGA_E_ARG;
+    gga::SlotArgs a = slot_args(ops, sc);
+    a.sel.fitness = fitness_d;
+    a.sel.order = order_d;
+    a.sel.position = position_d;
+    a.sel.generation = generation_d;
+    a.pop = pop_d;
+    a.next = next_d;
+    hipError_t e = gga::launch_rank(fitness_d, N, order_d, position_d, stream);
+    if (e == hipSuccess) e = gga::launch_slot_offspring(a, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_slots_decode(const gga_slot_cfg* sc, const uint8_t* pop_d, int32_t P, int32_t K, float* dose_d,
+                     int32_t* gap_h_d, int32_t* nfrac_d, hipStream_t stream) {
+    const int rc = check_slots(sc);
+    if (rc) return rc;
+    if (P < 0 || K < 1 || K > GGA_KMAX || (long long)P * std::max(sc->S, K) > std::numeric_limits<int32_t>::max())
+        return GGA_E_ARG;
+    if (P > 0 && (!pop_d || !dose_d || !gap_h_d || !nfrac_d)) return GGA_E_ARG;
+    const hipError_t e = gga::launch_slot_decode(pop_d, P, sc->S, K, sc->quantum, dose_d, gap_h_d, nfrac_d, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_slots_encode(const gga_slot_cfg* sc, const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d,
+                     int32_t P, int32_t K, uint8_t* pop_d, hipStream_t stream) {
+    const int rc = check_slots(sc);
+    if (rc) return rc;
+    if (P < 0 || K < 1 || K > GGA_KMAX || (long long)P * std::max(sc->S, K) > std::numeric_limits<int32_t>::max())
+        return GGA_E_ARG;
+    if (P > 0 && (!pop_d || !dose_d || !gap_h_d || !nfrac_d)) return GGA_E_ARG;
+    const hipError_t e = gga::launch_slot_encode(dose_d, gap_h_d, nfrac_d, P, K, sc->S, sc->quantum, sc->g_min,
+                                                 sc->dmax_q, sc->cap_q, pop_d, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+size_t gga_slots_workspace_bytes(int32_t N, int32_t R, int32_t K) {
+    if (N < 0 || R < 1 || K < 1 || K > GGA_KMAX) return 0;
+    return slots_ws_bytes(N, R, K);
+}
+
+int gga_slots_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga, const gga_slot_cfg* sc,
+                  uint8_t* pop_a_d, uint8_t* pop_b_d, int32_t N, int32_t K, int32_t g0, int32_t n_gen,
+                  int32_t use_graph, void* ws_d, size_t ws_bytes, float* hist_d, float* best_dose_d,
+                  int32_t* best_gap_d, float* gen_ms_h, hipStream_t stream) {
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((rc = check_cfg(cfg))) return rc;
+    if ((rc = check_slots(sc))) return rc;
+    if (K < 1 || (rc = check_batch(N, K, cfg->R))) return rc ? rc : GGA_E_ARG;
+    if ((long long)K * sc->g_min < sc->S) return GGA_E_ARG;              // K >= ceil(S / g_min)
+    if ((double)sc->cap_q * (double)sc->quantum > cfg->dose_cap + 1e-6) return GGA_E_ARG;
+    gga::GaArgs ops;
+    if ((rc = check_ga_ops(ga, N, &ops))) return rc;
+    if (ga->mutation != 0) return GGA_E_ARG;
+    if (!best_dose_d != !best_gap_d) return GGA_E_ARG;
+    if (!pop_a_d || !pop_b_d || pop_a_d == pop_b_d || !ws_d || n_gen < 0 || g0 < 0) return GGA_E_ARG;
+    if ((long long)g0 + n_gen > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
+    if ((long long)N * sc->S > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
+    const int32_t hist_cap = g0 + n_gen;
+    if (ws_bytes < slots_ws_bytes(N, cfg->R, K) || (n_gen > 0 && !hist_d)) return GGA_E_ARG;
+    const SlotWorkspace w = slots_ws(ws_d, N, cfg->R, K);
+    const gga::SlotArgs sl = slot_args(ops, sc);
+    uint8_t* pop[2] = {pop_a_d, pop_b_d};
+    auto enqueue = [&](int d) {
+        return enqueue_slot_generation(params, cfg, sl, pop[d], N, K, pop[1 - d], w, hist_d, hist_cap, best_dose_d,
+                                       best_gap_d, 1, stream);
+    };
+    const hipError_t e = run_generations(enqueue, w.ga.generation, g0, n_gen, use_graph, gen_ms_h, stream);
     return e == hipSuccess ? GGA_OK : hip_fail(e);
 }
 

@@ -28,7 +28,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(gga):
     names = declared_functions()
-    assert len(names) == 41
+    assert len(names) == 46
     for n in names:
         assert hasattr(gga.LIB, n), n
     assert set(names) == set(gga.EXPORTS)
@@ -48,6 +48,7 @@ int main(void) {
          offsetof(gga_alphabet, gaps), sizeof(gga_ga_cfg), offsetof(gga_ga_cfg, seed));
   printf("%zu %zu %zu\n", offsetof(gga_ga_cfg, selection), offsetof(gga_ga_cfg, q), offsetof(gga_ga_cfg, roulette_base));
   printf("%zu %zu\n", sizeof(gga_sga_cfg), offsetof(gga_sga_cfg, refine_lr));
+  printf("%zu %zu %zu\n", sizeof(gga_slot_cfg), offsetof(gga_slot_cfg, quantum), offsetof(gga_slot_cfg, reserved));
   return 0;
 }
 """
@@ -65,7 +66,8 @@ def test_struct_layout_matches_python_mirror(gga, tmp_path):
                     gga.Params.P_div.offset, gga.Params.m.offset, gga.SimCfg.seed.offset,
                     gga.Alphabet.gaps.offset, ctypes.sizeof(gga.GaCfg), gga.GaCfg.seed.offset,
                     gga.GaCfg.selection.offset, gga.GaCfg.q.offset, gga.GaCfg.roulette_base.offset,
-                    ctypes.sizeof(gga.SgaCfg), gga.SgaCfg.refine_lr.offset]
+                    ctypes.sizeof(gga.SgaCfg), gga.SgaCfg.refine_lr.offset,
+                    ctypes.sizeof(gga.SlotCfg), gga.SlotCfg.quantum.offset, gga.SlotCfg.reserved.offset]
 
 
 def test_version_and_errors(gga):
@@ -202,6 +204,52 @@ def test_ga_operator_settings_are_checked_before_any_launch(gga):
                                 fake, fake, None) == -1
     g = gga.make_ga(mutation=("gene", "swap", "raise"), crossover="uniform")
     assert g.mutation == 7 and g.crossover == 3
+
+
+def test_slot_ga_settings_are_checked_before_any_launch(gga):
+    """The slot GA's settings, sizes and pointers are refused on the host."""
+    fake = ctypes.c_void_p(0x1000)
+    g = gga.make_ga()
+    ok = gga.make_slots()
+
+    def breed(sc, ga=g, N=16, next_=ctypes.c_void_p(0x2000)):
+        return gga.LIB.gga_slots_breed(ctypes.byref(ga), ctypes.byref(sc), fake, fake, N, fake, fake, fake, next_,
+                                       None)
+
+    for field, value in (("S", 0), ("S", 257), ("g_min", 0), ("g_min", 121), ("dmax_q", 0), ("dmax_q", 256),
+                         ("cap_q", -1), ("cap_q", 65536), ("mutation", 16), ("reserved", 1),
+                         ("quantum", 0.0), ("quantum", float("nan"))):
+        sc = gga.make_slots()
+        setattr(sc, field, value)
+        assert breed(sc) == -1, field
+    sc = gga.make_slots()
+    sc.struct_size = 4
+    assert breed(sc) == -2
+    assert breed(ok, N=1) == -1                                   # a population of at least 2
+    assert breed(ok, next_=fake) == -1                            # next population may not alias the current one
+    gm = gga.make_ga(mutation=("swap",))
+    assert breed(ok, ga=gm) == -1                                 # operators of the slot GA live in gga_slot_cfg
+    for K in (0, 65):
+        assert gga.LIB.gga_slots_decode(ctypes.byref(ok), fake, 4, K, fake, fake, fake, None) == -1
+        assert gga.LIB.gga_slots_encode(ctypes.byref(ok), fake, fake, fake, 4, K, fake, None) == -1
+    assert gga.LIB.gga_slots_decode(ctypes.byref(ok), None, 4, 8, fake, fake, fake, None) == -1
+    assert gga.LIB.gga_slots_workspace_bytes(40, 8, 0) == 0
+    assert gga.LIB.gga_slots_workspace_bytes(40, 8, 20) >= gga.LIB.gga_ga_workspace_bytes(40, 8) + 2 * 40 * 20 * 4
+    # a run needs K >= ceil(S / g_min) fraction slots and a cap within the simulation's dose cap
+    params = gga.make_params(gga.load_model())
+    cfg = gga.make_cfg(L=64, horizon=24, R=2)
+    big = ctypes.c_size_t(1 << 30)
+
+    def run(sc, K):
+        return gga.LIB.gga_slots_run(ctypes.byref(params), ctypes.byref(cfg), ctypes.byref(g), ctypes.byref(sc),
+                                     fake, ctypes.c_void_p(0x3000), 16, K, 0, 1, 0, fake, big, fake, None, None,
+                                     None, None)
+
+    assert run(ok, 19) == -1
+    capped = gga.make_slots(cap_q=80)                               # 20 Gy against a 10 Gy cap
+    cfg.dose_cap = 10.0
+    assert run(capped, 20) == -1
+    assert gga.make_slots(mutation=("swap", "split", "time", "value")).mutation == 15
 
 
 def test_mlp_buffers_must_be_16_byte_aligned(gga):

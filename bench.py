@@ -207,6 +207,61 @@ def ga_bench(gga, workloads, md, args):
     }
 
 
+def slots_bench(gga, workloads, md, args):
+    """The paper's GA on its own genome: a generation of 40 protocols, each
+    simulated 80 times (128 x 128, 5-day treatment window of 120 hourly
+    slots plus 5 days of regrowth = 240 h), minimal interval 6 h, single doses
+    up to 4.5 Gy and a 10 Gy total in 0.25 Gy quanta, tournament k = 4,
+    two-point crossover 0.8, swap, split and dose-time mutations 0.1 each, 4
+    elites, 50 generations.  Each generation decodes the genomes, simulates
+    all 3,200 instances in one launch, reduces the fitness and breeds, as
+    replayed hipGraphs (and, for comparison, as a host-driven loop)."""
+    import torch
+    N, R, G, K = args.slot_population, args.slot_replicas, args.slot_generations, 20
+    L, H, S = 128, 240, 120
+    cfg = gga.make_cfg(L, H, R, seed=3, substeps=10, dose_cap=10.0)
+    sc = gga.make_slots(S=S, g_min=6, dmax_q=18, cap_q=40, quantum=0.25)
+    ga_cfg = gga.make_ga(n_elite=max(1, N // 10), tournament_k=4, p_cross=0.8, p_mut=0.1, seed=2,
+                         crossover="two_point", mutation=())
+    params = gga.make_params(md)
+    alpha = gga.make_alphabet(0.25, list(range(1, 19)), [6, 12, 18, 24, 36, 48], 2, 10, 10.0)
+    d0, g0, n0 = gga.population_random(alpha, N, K, seed=4)
+    pop0 = gga.slots_encode(sc, d0, g0, n0)
+    torch.cuda.synchronize()
+    out = {}
+    for mode, use_graph in (("batched_host_loop", False), ("batched", True)):
+        t0 = time.perf_counter()
+        pop, hist, gen_ms, (bd, bg) = gga.slots_run(params, cfg, ga_cfg, sc, pop0, K, G, use_graph, archive=True)
+        wall = time.perf_counter() - t0
+        h = hist.cpu().numpy()
+        times = gen_ms.astype(np.float64) / 1000.0
+        ttb, final, hit = time_to_best(h[:, 0], times)
+        best_g = int(np.argmin(h[:, 0]))
+        nb = int(np.count_nonzero(bd[best_g].cpu().numpy()))
+        log(f"{mode}: {G} generations in {wall:.2f} s, best {final:.1f} at generation {hit}")
+        out[mode] = {"s_per_generation": float(times[-1]) / G, "total_s": wall, "time_to_best_s": ttb,
+                     "generation_of_best": hit, "final_best_fitness": final,
+                     "best_first_generation": float(h[0, 0]), "mean_last_generation": float(h[-1, 1]),
+                     "best_protocol": {"dose_gy": [float(x) for x in bd[best_g].cpu().numpy()[:nb]],
+                                       "delay_h": [int(x) for x in bg[best_g].cpu().numpy()[:nb]]}}
+    inst = N * R
+    b = out["batched"]
+    return {
+        "metric": "slot-genome GA seconds per generation (40 protocols x 80 simulations, hipGraph replay)",
+        "value": b["s_per_generation"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"slots-{N}x{R}-{L}x{L}-{H // 24}d", "population": N, "replicas": R,
+                   "generations": G, "slots": S, "min_interval_h": 6, "dmax_gy": 4.5, "cap_gy": 10.0,
+                   "quantum_gy": 0.25, "selection": "tournament", "tournament_k": 4, "crossover": "two_point",
+                   "p_cross": 0.8, "mutations": ["swap", "split", "time"], "p_mut": 0.1,
+                   "elites": max(1, N // 10)},
+        "simulations_per_s": inst / b["s_per_generation"],
+        "batched": b, "batched_host_loop": out["batched_host_loop"],
+        "speedup_graph_vs_host_loop": out["batched_host_loop"]["s_per_generation"] / max(b["s_per_generation"],
+                                                                                          1e-12),
+    }
+
+
 def _reevaluate(gga, params, wl, best_dose, best_gap, R, seed):
     """Fitness of archived protocols re-simulated with R fresh replicas."""
     import torch
@@ -472,11 +527,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "ga", "surrogate", "uneven", "mlp"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "ga", "surrogate", "uneven", "mlp", "slots"])
     ap.add_argument("--generations", type=int, default=200, help="GA workload: generations")
     ap.add_argument("--chunk", type=int, default=20, help="GA workload: generations per progress line")
     ap.add_argument("--plain-generations", type=int, default=1,
                     help="GA workload: generations' worth of per-protocol calls timed for the plain rate")
+    ap.add_argument("--slot-population", type=int, default=40, help="slots workload: protocols per generation")
+    ap.add_argument("--slot-replicas", type=int, default=80, help="slots workload: simulations per protocol")
+    ap.add_argument("--slot-generations", type=int, default=50, help="slots workload: generations")
     ap.add_argument("--candidates", type=int, default=5000, help="surrogate workload: candidates per generation")
     ap.add_argument("--train-pairs", type=int, default=200000, help="surrogate workload: training pairs")
     ap.add_argument("--epochs", type=int, default=10, help="surrogate workload: training epochs")
@@ -515,6 +573,9 @@ def main():
         return
     if args.workload == "mlp":
         print(json.dumps(mlp_bench(gga, workloads, md, args)), flush=True)
+        return
+    if args.workload == "slots":
+        print(json.dumps(slots_bench(gga, workloads, md, args)), flush=True)
         return
     if args.workload == "uneven":
         print(json.dumps(uneven_bench(gga, workloads, md, args)), flush=True)

@@ -93,14 +93,22 @@ typedef struct gga_params {
  */
 int gga_params_from_json(const char* path, gga_params* out);
 
-/* One simulation batch.  Set struct_size = sizeof(gga_sim_cfg). */
+/* One simulation batch.  Set struct_size = sizeof(gga_sim_cfg).
+ * GGA_SIM_HALF_HOUR: protocol delays count 30-minute units, the paper's slot
+ * length (Materials and Methods, "GA Resolution, constraints"); the model
+ * still steps in hours.  A fraction at an odd half-hour 2n + 1 is applied in
+ * step n after substeps / 2 of its diffusion sub-steps (its survival words
+ * from the Philox block of step word n | 2^31), and the reaction term is
+ * rebuilt from the surviving cells for the rest of the hour.  Horizons are at
+ * most 2^30 steps. */
+#define GGA_SIM_HALF_HOUR 1u
 typedef struct gga_sim_cfg {
     uint32_t struct_size;
     int32_t L;              /* lattice side: 64 or 128 (uneven batches: 256 too)  */
     int32_t horizon;        /* steps (model hours) simulated by gga_simulate     */
     int32_t substeps;       /* diffusion sub-steps per step, 1 .. 64             */
     int32_t R;              /* replicas per protocol, >= 1                       */
-    uint32_t flags;         /* reserved, must be 0                               */
+    uint32_t flags;         /* 0 or GGA_SIM_HALF_HOUR                            */
     uint64_t seed;          /* Philox key (lo, hi words)                         */
     double dose_cap;        /* total-dose cap in Gy                              */
 } gga_sim_cfg;

@@ -69,18 +69,23 @@ def lq_threshold(d, m, alpha, beta):
     return min(int(math.floor(s * 4294967296.0)), 0xFFFFFFFF)
 
 
-def events(dose_row, gap_row, nfrac, horizon, params):
+def events(dose_row, gap_row, nfrac, horizon, params, half_hour=False):
     """Irradiation events of one protocol inside [0, horizon) steps.
 
-    Returns a list of (step, thresholds[4]) in time order; thresholds are per
+    Returns a list of (time, thresholds[4]) in time order; thresholds are per
     sensitivity class (young, mid and old proliferating, quiescent).  Fractions
-    with zero dose, or falling at or after the horizon, give no event.
+    with zero dose, or falling at or after the horizon, give no event.  Times
+    are steps (hours), or with half_hour=True half-hours: the delays are then
+    counted in 30-minute units (the paper's slot length, Materials and
+    Methods, "GA Resolution, constraints") and an event at half-hour tau falls
+    in step tau // 2, at its start (tau even) or its middle (tau odd).
     """
     out, t = [], 0
+    end = 2 * horizon if half_hour else horizon
     for j in range(int(nfrac)):
         t += int(gap_row[j])
         d = float(np.float32(dose_row[j]))
-        if d <= 0.0 or t >= horizon:
+        if d <= 0.0 or t >= end:
             continue
         thr = [lq_threshold(d, params.m[c], params.alpha, params.beta) for c in range(4)]
         out.append((t, thr))

@@ -15,13 +15,17 @@ Per instance (protocol p, replica r) and step n = 0 .. N-1 (one model hour):
   1. irradiation, if a fraction falls on step n: each live cell of sensitivity
      class c survives iff w1 < T_c (linear-quadratic threshold), else it is
      DEAD with age 0;
-  2. the activity map a = act[state] is frozen for the hour;
+  2. the activity map a = act[state] is frozen until the next fraction or the
+     end of the hour;
   3. `substeps` explicit FTCS updates of the three fields,
      c' = c + lam (c_N + c_S + c_E + c_W - 4 c) - kappa a   (O, G; then max(.,0))
      H' = H + lam (H_N + H_S + H_E + H_W - 4 H) + kappa a,
-     with Dirichlet ghost values outside the lattice;
-  4. a synchronous cell update from the snapshot taken after step 1 and the
-     fields after step 3 (see cell_update);
+     with Dirichlet ghost values outside the lattice; a fraction at the half
+     hour (protocols timed in 30-minute units) is applied as in 1 after
+     substeps // 2 of them, with w1 from the block of step word n | 2^31, and
+     the activity map is rebuilt from the surviving cells;
+  4. a synchronous cell update from the snapshot taken after the irradiation
+     and the fields after step 3 (see cell_update);
   5. the live count (PROLIF + QUIESC) is recorded.
 
 Cell words: bits 0-1 state (EMPTY, PROLIF, QUIESC, DEAD), bits 2-9 age in
@@ -194,35 +198,49 @@ def cell_update(cells, fields, draw, params: Params):
     return pack(new_state, new_age)
 
 
-def step(fields, cells, n, thresholds, p, r, seed, params: Params, substeps):
-    """Advance one instance by one step; `thresholds` is None without a fraction."""
+MID_STEP = 0x80000000   # step word bit of the draws of a fraction at the half hour
+
+
+def step(fields, cells, n, thresholds, p, r, seed, params: Params, substeps, thresholds_mid=None):
+    """Advance one instance by one step; `thresholds` (start of the hour) and
+    `thresholds_mid` (its middle) are None without a fraction."""
     draw = lambda sites: site_words(sites, n, r, p, seed)
     if thresholds is not None:
         cells = irradiate(cells, thresholds, draw, params)
     act = activity(cells, params)
-    for _ in range(substeps):
+    first = substeps // 2 if thresholds_mid is not None else substeps
+    for _ in range(first):
         fields = diffuse_substep(fields, act, params)
+    if thresholds_mid is not None:
+        cells = irradiate(cells, thresholds_mid, lambda sites: site_words(sites, MID_STEP | n, r, p, seed), params)
+        act = activity(cells, params)
+        for _ in range(substeps - first):
+            fields = diffuse_substep(fields, act, params)
     cells = cell_update(cells, fields, draw, params)
     return fields, cells
 
 
-def run_instance(params: Params, L, nsteps, substeps, ev, p, r, seed, state=None, n0=0):
-    """Run steps n0 .. n0+nsteps-1; returns (fields, cells, live count per step)."""
+def run_instance(params: Params, L, nsteps, substeps, ev, p, r, seed, state=None, n0=0, half_hour=False):
+    """Run steps n0 .. n0+nsteps-1; returns (fields, cells, live count per step).
+    `ev` holds (time, thresholds) with times in steps, or in half-hours when
+    half_hour is set."""
     if state is None:
         fields, cells = init_state(params, L, p, r, seed)
     else:
         fields, cells = state
-    evmap = {t: thr for t, thr in ev}
+    evmap = {(t if half_hour else 2 * t): thr for t, thr in ev}
     traj = np.zeros(nsteps, dtype=np.int64)
     for i in range(nsteps):
         n = n0 + i
-        fields, cells = step(fields, cells, n, evmap.get(n), p, r, seed, params, substeps)
+        fields, cells = step(fields, cells, n, evmap.get(2 * n), p, r, seed, params, substeps,
+                             thresholds_mid=evmap.get(2 * n + 1))
         traj[i] = live_count(cells)
     return fields, cells, traj
 
 
-def simulate(params: Params, L, horizon, substeps, R, seed, dose, gap, nfrac, K, cap):
-    """Whole batch: live[p, r] after `horizon` steps and fitness[p] = mean_r live.
+def simulate(params: Params, L, horizon, substeps, R, seed, dose, gap, nfrac, K, cap, half_hour=False):
+    """Whole batch: live[p, r] after `horizon` steps and fitness[p] = mean_r live
+    (delays in half-hours with half_hour=True).
 
     Invalid protocols get live = -1 and fitness NaN.  The paper's own score is
     L*L - fitness (the maximal number of occupiable sites minus the mean count).
@@ -237,8 +255,8 @@ def simulate(params: Params, L, horizon, substeps, R, seed, dose, gap, nfrac, K,
     for p in range(P):
         if status[p]:
             continue
-        ev = events(dose[p], gap[p], nfrac[p], horizon, params)
+        ev = events(dose[p], gap[p], nfrac[p], horizon, params, half_hour)
         for r in range(R):
-            live[p, r] = run_instance(params, L, horizon, substeps, ev, p, r, seed)[2][-1]
+            live[p, r] = run_instance(params, L, horizon, substeps, ev, p, r, seed, half_hour=half_hour)[2][-1]
         fitness[p] = live[p].mean()
     return live, fitness

@@ -232,11 +232,16 @@ def params_from_json(path):
     return p
 
 
-def make_cfg(L, horizon, R, seed=0, substeps=10, dose_cap=20.0):
+SIM_HALF_HOUR = 1
+
+
+def make_cfg(L, horizon, R, seed=0, substeps=10, dose_cap=20.0, half_hour=False):
+    """Simulation settings; half_hour=True counts protocol delays in 30-minute
+    units (GGA_SIM_HALF_HOUR)."""
     c = SimCfg()
     c.struct_size = ctypes.sizeof(SimCfg)
     c.L, c.horizon, c.substeps, c.R = int(L), int(horizon), int(substeps), int(R)
-    c.flags, c.seed, c.dose_cap = 0, int(seed), float(dose_cap)
+    c.flags, c.seed, c.dose_cap = SIM_HALF_HOUR if half_hour else 0, int(seed), float(dose_cap)
     return c
 
 

@@ -49,7 +49,7 @@ int check_params(const gga_params* p) {
 int check_cfg(const gga_sim_cfg* c) {
     if (!c) return GGA_E_ARG;
     if (c->struct_size != sizeof(gga_sim_cfg)) return GGA_E_ABI;
-    if (c->flags != 0 || c->R < 1 || c->horizon < 0) return GGA_E_ARG;
+    if ((c->flags & ~GGA_SIM_HALF_HOUR) != 0 || c->R < 1 || c->horizon < 0 || c->horizon > (1 << 30)) return GGA_E_ARG;
     if (!std::isfinite(c->dose_cap)) return GGA_E_ARG;
     if (!gga::sim_supported(c->L) || c->substeps < 1 || c->substeps > 64) return GGA_E_UNSUPPORTED;
     return GGA_OK;
@@ -75,6 +75,7 @@ gga::SimArgs make_args(const gga_params* prm, const gga_sim_cfg* cfg, const floa
     a.seed_lo = static_cast<uint32_t>(cfg->seed);
     a.seed_hi = static_cast<uint32_t>(cfg->seed >> 32);
     a.dose_cap = cfg->dose_cap;
+    a.half = (cfg->flags & GGA_SIM_HALF_HOUR) ? 1 : 0;
     return a;
 }
 
@@ -1148,7 +1149,7 @@ int plan_uneven(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, i
     const int sides[3] = {64, 128, 256};
     for (int32_t p = 0; p < P; ++p) {
         if (!side_ok(lattice_h[p])) return GGA_E_UNSUPPORTED;
-        if (horizon_h[p] < 0) return GGA_E_ARG;
+        if (horizon_h[p] < 0 || horizon_h[p] > (1 << 30)) return GGA_E_ARG;
     }
     plan->host.clear();
     plan->groups.clear();
@@ -1255,7 +1256,7 @@ int upload_plan(const UnevenPlan& plan, char* ws, int32_t P, hipStream_t stream)
 int check_uneven_cfg(const gga_sim_cfg* c) {
     if (!c) return GGA_E_ARG;
     if (c->struct_size != sizeof(gga_sim_cfg)) return GGA_E_ABI;
-    if (c->flags != 0 || c->R < 1 || !std::isfinite(c->dose_cap)) return GGA_E_ARG;
+    if ((c->flags & ~GGA_SIM_HALF_HOUR) != 0 || c->R < 1 || !std::isfinite(c->dose_cap)) return GGA_E_ARG;
     if (c->substeps < 1 || c->substeps > 64) return GGA_E_UNSUPPORTED;
     return GGA_OK;
 }
@@ -1327,7 +1328,7 @@ int gga_state_run_variant(const gga_params* params, const gga_sim_cfg* cfg, int3
     if ((rc = check_uneven_cfg(cfg))) return rc;
     if ((rc = check_batch(P, K, cfg->R))) return rc;
     if (variant < 0 || variant >= gga::N_SIM_VARIANTS || gga::SIM_VARIANTS[variant].L != cfg->L) return GGA_E_ARG;
-    if (n0 < 0 || nsteps < 0 || (long long)n0 + nsteps > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
+    if (n0 < 0 || nsteps < 0 || (long long)n0 + nsteps > (1LL << 30)) return GGA_E_ARG;   // half-hour event times fit int32
     if (P == 0) return GGA_OK;
     if (!nfrac_d || !fields_d || !cells_d || (K > 0 && (!dose_d || !gap_h_d))) return GGA_E_ARG;
     gga::SimArgs a = make_args(params, cfg, dose_d, gap_h_d, nfrac_d, K);

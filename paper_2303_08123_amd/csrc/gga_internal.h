@@ -16,6 +16,7 @@ struct SimArgs {
     const int32_t* gap;     // [P][K]
     const int32_t* nfrac;   // [P]
     int32_t K, R, substeps, n0, nsteps, mode;
+    int32_t half;           // delays count half-hours (GGA_SIM_HALF_HOUR)
     uint32_t seed_lo, seed_hi;
     double dose_cap;
     float* fields;          // [P*R][3][L][L] when mode has LOAD or STORE
@@ -41,7 +42,7 @@ struct SimArgs {
     int32_t slab_ys[16], slab_i0[16], slab_i1[16];   // first lattice row; own rows [i0, i1) of the slab
     const int32_t* ev_valid;  // [P]
     const int32_t* ev_count;  // [P]
-    const int32_t* ev_step;   // [P][K] steps of the positive-dose fractions, in order
+    const int32_t* ev_step;   // [P][K] times of the positive-dose fractions in half-hours, in order
     const uint32_t* ev_thr;   // [P][K][4] survival thresholds per sensitivity class
     int32_t count_at;         // slab form without horizon[]: the step whose end is counted
     int32_t lib_n;            // resident form with MODE_LOAD: replica r loads state r mod lib_n (0: its own)

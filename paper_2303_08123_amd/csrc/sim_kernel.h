@@ -27,10 +27,13 @@
 // damage; fitness from the final number of occupied sites, equation
 // final_fit_fun) with the synthetic model's rules:
 //   step n:  (1) fraction at n?  live cell of class c survives iff w1 < T_c
-//            (2) activity a = act[state], frozen for the hour
+//            (2) activity a = act[state], frozen until the next fraction
 //            (3) `substeps` FTCS sub-steps
 //                c' = c + lam (N + S + E + W - 4c) - kappa a  (O, G; then max(., 0))
 //                H' = H + lam (N + S + E + W - 4H) + kappa a
+//                (protocols timed in half-hours, the paper's 30-minute slots:
+//                a fraction at the half hour runs (1) and (2) again after
+//                substeps / 2 of them)
 //            (4) synchronous cell update from the snapshot (lysis, environment,
 //                division proposals into free von Neumann neighbours, conflict
 //                resolution by the smallest key)
@@ -177,10 +180,10 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     __shared__ __attribute__((aligned(16))) uint16_t s_cell[RR * L];
     __shared__ __attribute__((aligned(16))) uint32_t s_pool[G::POOL];   // halo buffer(s), then claim slots
     __shared__ uint32_t s_claim[RR * L / 32];  // one "has a daughter" bit per site
-    __shared__ int s_ev_step[GGA_KMAX];
+    __shared__ uint32_t s_ev_step[GGA_KMAX];   // half-hours since step n0 (2 (n - n0), + 1 at the half hour)
     __shared__ float s_ev_dose[GGA_KMAX];
     __shared__ uint32_t s_ev_thr[GGA_KMAX][4];
-    __shared__ int s_nev, s_valid, s_evj;
+    __shared__ int s_nev, s_valid, s_evj[2];
     __shared__ int s_count[2];
     __shared__ CellConst s_k;                  // cell-update constants, read where used
 
@@ -228,20 +231,25 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 
     // ---- protocol: validity and irradiation events ----
     if constexpr (SLAB) {
-        // event table (one fraction per step at most): lane j of wave 0 checks fraction j
+        // event table (times in half-hours; at most one fraction at the start of
+        // step n0 and one at its middle): lane j of wave 0 checks fraction j
         if (wave == 0) {
             const int k = a.ev_count[p];
-            bool hit = false;
-            for (int j = lane; j < k; j += 64) hit |= (a.ev_step[(size_t)p * a.K + j] == a.n0);
-            int jj = -1;
-            for (int j = lane; j < k; j += 64)
-                if (a.ev_step[(size_t)p * a.K + j] == a.n0) jj = j;
-            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-            if (lane == (m ? __builtin_ctzll(m) : 0)) s_evj = jj;
+            int j0 = -1, j1 = -1;
+            for (int j = lane; j < k; j += 64) {
+                const int tau = a.ev_step[(size_t)p * a.K + j];
+                if (tau == 2 * a.n0) j0 = j;
+                if (tau == 2 * a.n0 + 1) j1 = j;
+            }
+            const uint64_t m0 = __builtin_amdgcn_ballot_w64(j0 >= 0), m1 = __builtin_amdgcn_ballot_w64(j1 >= 0);
+            const int J0 = m0 ? __shfl(j0, __builtin_ctzll(m0)) : -1;
+            const int J1 = m1 ? __shfl(j1, __builtin_ctzll(m1)) : -1;
             if (lane == 0) {
                 s_valid = a.ev_valid[p];
-                s_nev = m ? 1 : 0;
-                s_ev_step[0] = a.n0;
+                int e = 0;
+                if (J0 >= 0) { s_ev_step[e] = 0u; s_evj[e] = J0; ++e; }
+                if (J1 >= 0) { s_ev_step[e] = 1u; s_evj[e] = J1; ++e; }
+                s_nev = e;
             }
         }
     }
@@ -258,8 +266,10 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             if (g < (j == 0 ? 0 : 1)) { valid = 0; break; }
             total += (double)d;
             t += g;
-            if (d > 0.0f && t >= a.n0 && t < (long long)a.n0 + nsteps) {
-                s_ev_step[nev] = (int)t;
+            // event time in half-hours (delays count half-hours with a.half)
+            const long long tau = a.half ? t : 2 * t;
+            if (d > 0.0f && tau >= 2LL * a.n0 && tau < 2LL * ((long long)a.n0 + nsteps)) {
+                s_ev_step[nev] = (uint32_t)(tau - 2LL * a.n0);
                 s_ev_dose[nev] = d;
                 ++nev;
             }
@@ -288,7 +298,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     }
     const int nev = s_nev;
     if constexpr (SLAB) {
-        if (tid < 4 * nev) s_ev_thr[0][tid] = a.ev_thr[((size_t)p * a.K + s_evj) * 4 + tid];
+        if (tid < 4 * nev) s_ev_thr[tid >> 2][tid & 3] = a.ev_thr[((size_t)p * a.K + s_evj[tid >> 2]) * 4 + (tid & 3)];
     } else {
         for (int e = tid; e < 4 * nev; e += G::NT)
             s_ev_thr[e >> 2][e & 3] = lq_threshold((double)s_ev_dose[e >> 2], P.m[e & 3], P.alpha, P.beta);
@@ -364,40 +374,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         int own = y0 * L + x0;
         asm volatile("" : "+v"(own));
         uint16_t* const cellp = s_cell + own;            // row i: cellp + i * L
-        // (1) irradiation: every live cell draws w1 against its class threshold
-        if (ev < nev && s_ev_step[ev] == n) {
-            const uint32_t t0 = s_ev_thr[ev][0], t1 = s_ev_thr[ev][1];
-            const uint32_t t2 = s_ev_thr[ev][2], t3 = s_ev_thr[ev][3];
-            const int ca0 = s_k.ca0, ca1 = s_k.ca1;
-            uint32_t live_mask = 0;
-#pragma unroll
-            for (int i = 0; i < RPT; ++i)
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const int st = cellp[i * L + c] & 3;
-                    if (st == PROLIF || st == QUIESC) live_mask |= 1u << (i * CPL + c);
-                }
-            while (live_mask) {
-                const int idx = __builtin_ctz(live_mask);
-                live_mask &= live_mask - 1;
-                const int site = own + (idx / CPL) * L + idx % CPL;
-                const uint32_t w = s_cell[site];
-                const int st = w & 3, age = w >> 2;
-                const uint32_t thr = (st == QUIESC) ? t3 : (age < ca0 ? t0 : (age < ca1 ? t1 : t2));
-                const Block4 b = philox10(site + gofs, n, r, p, seed_lo, seed_hi);
-                if (b.w1 >= thr) s_cell[site] = DEAD;
-            }
-            ++ev;
-        }
-
-        // (2) reaction term for the hour, one per site for all three fields in
-        // field units: Ro = -kappa_O a.
-        float Ro[RPT][CPL];
-#pragma unroll
-        for (int i = 0; i < RPT; ++i)
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) Ro[i][c] = kapO * actv[cellp[i * L + c] & 3];
-
+        float Ro[RPT][CPL];                              // reaction term, set below
         // (3) diffusion sub-steps, in pairs over the RPT + 1 register slots with
         // no row copied: a forward sub-step (rows top to bottom) writes new row
         // i over old row i - 1, which row i was the last to read, moving every
@@ -526,12 +503,57 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             const int blk = k / G::BLK, off = k - blk * G::BLK;
             reinterpret_cast<float*>(s_pool)[blk * (NWAVE + 1) * G::BLK + off] = 0.0f;   // the boundary, in field units
         }
+        const uint32_t rel = 2u * (uint32_t)(n - a.n0);  // the hour's start, in half-hours since step n0
         int s = 0;
-        for (; s + 2 <= a.substeps; s += 2) {
-            rotating_substep(std::integral_constant<int, 0>{}, s & 1);
-            reverse_substep(std::integral_constant<int, 1>{}, (s + 1) & 1);
+#pragma nounroll
+        for (uint32_t half = 0;; half = 1) {
+            // (1) irradiation: every live cell draws w1 against its class
+            // threshold, at the start of the hour or, for a fraction timed at
+            // the half hour, after half of the hour's sub-steps (its words from
+            // the block of step word n | 2^31)
+            if (ev < nev && s_ev_step[ev] == rel + half) {
+                const uint32_t t0 = s_ev_thr[ev][0], t1 = s_ev_thr[ev][1];
+                const uint32_t t2 = s_ev_thr[ev][2], t3 = s_ev_thr[ev][3];
+                const int ca0 = s_k.ca0, ca1 = s_k.ca1;
+                uint32_t live_mask = 0;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const int st = cellp[i * L + c] & 3;
+                        if (st == PROLIF || st == QUIESC) live_mask |= 1u << (i * CPL + c);
+                    }
+                while (live_mask) {
+                    const int idx = __builtin_ctz(live_mask);
+                    live_mask &= live_mask - 1;
+                    const int site = own + (idx / CPL) * L + idx % CPL;
+                    const uint32_t w = s_cell[site];
+                    const int st = w & 3, age = w >> 2;
+                    const uint32_t thr = (st == QUIESC) ? t3 : (age < ca0 ? t0 : (age < ca1 ? t1 : t2));
+                    const Block4 b = philox10(site + gofs, (uint32_t)n | (half << 31), r, p, seed_lo, seed_hi);
+                    if (b.w1 >= thr) s_cell[site] = DEAD;
+                }
+                ++ev;
+            }
+
+            // (2) reaction term until the next fraction or the end of the hour,
+            // one per site for all three fields in field units: Ro = -kappa_O a.
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) Ro[i][c] = kapO * actv[cellp[i * L + c] & 3];
+            // (3) the sub-steps up to a fraction at the half hour, or to the end of the hour
+            const int stop = (half == 0 && ev < nev && s_ev_step[ev] == rel + 1) ? a.substeps / 2 : a.substeps;
+            for (; s + 2 <= stop; s += 2) {
+                rotating_substep(std::integral_constant<int, 0>{}, s & 1);
+                reverse_substep(std::integral_constant<int, 1>{}, (s + 1) & 1);
+            }
+            if (s < stop) {
+                plain_substep(s & 1);
+                ++s;
+            }
+            if (stop == a.substeps) break;
         }
-        if (s < a.substeps) plain_substep(s & 1);
 
         // (4) cell update, bit-parallel over the thread's RPT x CPL sites
         // (bit idx = i * CPL + c of 32-bit masks).  Proposers claim an EMPTY

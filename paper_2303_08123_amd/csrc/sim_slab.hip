@@ -6,7 +6,8 @@
 namespace gga {
 namespace {
 
-// Per protocol: validity (the resident kernel's rules), and the step and class
+// Per protocol: validity (the resident kernel's rules), and the time in
+// half-hours (2 t for delays in hours; horizons stay below 2^30) and class
 // survival thresholds of every positive-dose fraction, in order.
 __global__ void event_table_kernel(SimArgs a, int P, int32_t* valid_out, int32_t* count_out, int32_t* step_out,
                                    uint32_t* thr_out) {
@@ -25,7 +26,8 @@ __global__ void event_table_kernel(SimArgs a, int P, int32_t* valid_out, int32_t
         total += (double)d;
         t += g;
         if (d > 0.0f) {
-            step_out[(size_t)p * a.K + nev] = t > 0x7FFFFFFFll ? 0x7FFFFFFF : (int)t;
+            const long long tau = a.half ? t : 2 * t;
+            step_out[(size_t)p * a.K + nev] = tau > 0x7FFFFFFFll ? 0x7FFFFFFF : (int)tau;
             for (int c = 0; c < 4; ++c)
                 thr_out[((size_t)p * a.K + nev) * 4 + c] = lq_threshold((double)d, a.prm.m[c], a.prm.alpha, a.prm.beta);
             ++nev;

@@ -68,27 +68,36 @@ def near_threshold(fields, cells, params, window=WINDOW, radius=2, abs_window=0.
     return out
 
 
-def oracle_step_detail(fields, cells, n, thr, p, r, seed, params, substeps, abs_window=0.0):
-    """One oracle step; returns (fields, cells, counted-site map)."""
+def oracle_step_detail(fields, cells, n, thr, p, r, seed, params, substeps, abs_window=0.0, thr_mid=None):
+    """One oracle step (thr_mid: a fraction at the half hour); returns
+    (fields, cells, counted-site map)."""
     draw = lambda s: site_words(s, n, r, p, seed)
     c1 = sim.irradiate(cells, thr, draw, params) if thr is not None else cells
     act = sim.activity(c1, params)
     f = fields
-    for _ in range(substeps):
+    first = substeps // 2 if thr_mid is not None else substeps
+    for _ in range(first):
         f = sim.diffuse_substep(f, act, params)
+    if thr_mid is not None:
+        c1 = sim.irradiate(c1, thr_mid, lambda s: site_words(s, sim.MID_STEP | n, r, p, seed), params)
+        act = sim.activity(c1, params)
+        for _ in range(substeps - first):
+            f = sim.diffuse_substep(f, act, params)
     c2 = sim.cell_update(c1, f, draw, params)
     return f, c2, near_threshold(f, c1, params, abs_window=abs_window)
 
 
-def oracle_certain_prefix(params, L, nsteps, substeps, ev, p, r, seed):
+def oracle_certain_prefix(params, L, nsteps, substeps, ev, p, r, seed, half_hour=False):
     """Oracle trajectory plus the number of leading steps whose outcome no
-    float32 rounding can change (no counted site yet)."""
+    float32 rounding can change (no counted site yet); event times in
+    half-hours with half_hour."""
     fields, cells = sim.init_state(params, L, p, r, seed)
-    evmap = {t: thr for t, thr in ev}
+    evmap = {(t if half_hour else 2 * t): thr for t, thr in ev}
     traj = np.zeros(nsteps, np.int64)
     certain = nsteps
     for n in range(nsteps):
-        fields, cells, near = oracle_step_detail(fields, cells, n, evmap.get(n), p, r, seed, params, substeps)
+        fields, cells, near = oracle_step_detail(fields, cells, n, evmap.get(2 * n), p, r, seed, params, substeps,
+                                                 thr_mid=evmap.get(2 * n + 1))
         traj[n] = sim.live_count(cells)
         if certain == nsteps and near.any():
             certain = n

@@ -76,6 +76,12 @@ typedef struct gga_params {
     double P_div;           /* hourly division probability once age >= T_min             */
     double alpha, beta;     /* linear-quadratic survival exp(-alpha x - beta x^2)        */
     double m[4];            /* x = m[class] * dose; classes young, mid, old, quiescent   */
+    double repair_half_time;/* hours, finite, >= 0.  0: sublethal damage is repaired
+                               between fractions (plain law per fraction).  > 0:
+                               incomplete repair: fraction j survives with
+                               exp(-alpha x - beta x (x + 2 y)), y = m D_j,
+                               D_j = sum over earlier fractions i of
+                               d_i 2^(-(t_j - t_i) / repair_half_time)          */
 } gga_params;
 
 /*
@@ -83,7 +89,8 @@ typedef struct gga_params {
  * arrays of numbers, keys lambda[3], kappa[3], ghost[3], init_fields[3],
  * activity[4], theta_O_quiesce, theta_G_quiesce, theta_O_death,
  * theta_G_death, theta_H_death, T_min, T_lys, A0, seed_radius (integers),
- * class_age[2] (integers), P_div, alpha, beta, m[4] (the package's
+ * class_age[2] (integers), P_div, alpha, beta, m[4], and optionally
+ * repair_half_time (default 0) (the package's
  * data/model_default.json).  Other keys are ignored.  out->struct_size must
  * be sizeof(gga_params) (GGA_E_ABI otherwise); *out is written only on
  * success.  Host only, no device work.  Errors: GGA_E_ARG (null pointer,

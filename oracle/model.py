@@ -43,6 +43,7 @@ class Params:
     beta: float       # LQ beta (1/Gy^2)
     class_age: tuple  # proliferating sensitivity classes: age < a0, < a1, >= a1
     m: tuple          # dose multipliers for the classes young, mid, old, quiescent
+    repair_half_time: float = 0.0   # hours; 0: sublethal damage repaired between fractions
 
     @classmethod
     def from_dict(cls, d):
@@ -58,6 +59,7 @@ class Params:
             alpha=float(d["alpha"]), beta=float(d["beta"]),
             class_age=tuple(int(v) for v in d["class_age"]),
             m=tuple(float(v) for v in d["m"]),
+            repair_half_time=float(d.get("repair_half_time", 0.0)),
         )
 
     @property

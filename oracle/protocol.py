@@ -59,14 +59,40 @@ def lq_survival(d, m, alpha, beta):
     return math.exp(-alpha * x - beta * x * x)
 
 
-def lq_threshold(d, m, alpha, beta):
+def lq_threshold(d, m, alpha, beta, prior=0.0):
     """32-bit survival threshold: a cell survives iff its word w1 < threshold.
 
     threshold = min(floor(S * 2**32), 2**32 - 1), S the LQ surviving fraction,
-    evaluated in float64 (the multiplication by 2**32 is exact).
+    evaluated in float64 (the multiplication by 2**32 is exact).  With
+    unrepaired damage from earlier fractions (`prior`, in Gy, see
+    prior_damage), S = exp(-alpha x - beta x (x + 2 y)), x = m d, y = m prior:
+    the incomplete-repair form of the linear-quadratic law, in which the
+    quadratic term couples each fraction with the unrepaired part of every
+    earlier one; prior = 0 is the plain law.
     """
-    s = lq_survival(d, m, alpha, beta)
+    x = float(m) * float(d)
+    y = float(m) * float(prior)
+    s = math.exp(-alpha * x - beta * x * (x + 2.0 * y))
     return min(int(math.floor(s * 4294967296.0)), 0xFFFFFFFF)
+
+
+def prior_damage(dose_row, gap_row, j, half_time, unit=1.0):
+    """Unrepaired dose before fraction j: sum over earlier fractions i of
+    d_i 2^(-(t_j - t_i) / half_time) (mono-exponential repair with the given
+    half-time in hours; times in units of `unit` hours), summed in index
+    order; 0 when half_time is 0 (complete repair between fractions)."""
+    if half_time <= 0.0:
+        return 0.0
+    t = [0]
+    for i in range(j + 1):
+        t.append(t[-1] + int(gap_row[i]))
+    tj = t[j + 1]
+    acc = 0.0
+    for i in range(j):
+        di = float(np.float32(dose_row[i]))
+        if di > 0.0:
+            acc += di * 2.0 ** (-(float(tj - t[i + 1]) * unit / half_time))
+    return acc
 
 
 def events(dose_row, gap_row, nfrac, horizon, params, half_hour=False):
@@ -87,7 +113,8 @@ def events(dose_row, gap_row, nfrac, horizon, params, half_hour=False):
         d = float(np.float32(dose_row[j]))
         if d <= 0.0 or t >= end:
             continue
-        thr = [lq_threshold(d, params.m[c], params.alpha, params.beta) for c in range(4)]
+        prior = prior_damage(dose_row, gap_row, j, params.repair_half_time, 0.5 if half_hour else 1.0)
+        thr = [lq_threshold(d, params.m[c], params.alpha, params.beta, prior) for c in range(4)]
         out.append((t, thr))
     return out
 

@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
         ("T_min", ctypes.c_int32), ("T_lys", ctypes.c_int32), ("A0", ctypes.c_int32),
         ("seed_radius", ctypes.c_int32), ("class_age", ctypes.c_int32 * 2),
         ("P_div", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-        ("m", ctypes.c_double * 4),
+        ("m", ctypes.c_double * 4), ("repair_half_time", ctypes.c_double),
     ]
 
 
@@ -221,6 +221,7 @@ def make_params(d):
     p.class_age[:] = [int(v) for v in d["class_age"]]
     p.P_div, p.alpha, p.beta = float(d["P_div"]), float(d["alpha"]), float(d["beta"])
     p.m[:] = [float(v) for v in d["m"]]
+    p.repair_half_time = float(d.get("repair_half_time", 0.0))
     return p
 
 

@@ -43,6 +43,7 @@ int check_params(const gga_params* p) {
     if (!std::isfinite(p->alpha) || !std::isfinite(p->beta)) return GGA_E_PARAM;
     for (int c = 0; c < 4; ++c)
         if (!std::isfinite(p->m[c])) return GGA_E_PARAM;
+    if (!(std::isfinite(p->repair_half_time) && p->repair_half_time >= 0.0)) return GGA_E_PARAM;
     return GGA_OK;
 }
 

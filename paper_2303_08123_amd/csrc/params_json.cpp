@@ -1,7 +1,7 @@
 // gga_params_from_json: the model constants from a flat JSON object whose
 // values are numbers or arrays of numbers (the format of the package's
-// data/model_default.json).  Every field of gga_params must be present; keys
-// the struct does not have are ignored.
+// data/model_default.json).  Every field of gga_params must be present except
+// repair_half_time (default 0); keys the struct does not have are ignored.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -156,6 +156,7 @@ extern "C" int gga_params_from_json(const char* path, gga_params* out) {
     doubles("alpha", &p.alpha, 1);
     doubles("beta", &p.beta, 1);
     doubles("m", p.m, 4);
+    if (kv.count("repair_half_time")) doubles("repair_half_time", &p.repair_half_time, 1);   // optional, default 0
     if (!ok) return GGA_E_PARAM;
     const int rc = gga::check_params_host(&p);
     if (rc != GGA_OK) return rc;

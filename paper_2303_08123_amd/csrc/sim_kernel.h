@@ -57,14 +57,32 @@ constexpr uint32_t INIT_STEP = 0xFFFFFFFFu;
 constexpr int EMPTY = 0, PROLIF = 1, QUIESC = 2, DEAD = 3;
 
 // 32-bit linear-quadratic survival threshold, evaluated in float64 exactly as
-// written: x = m d, S = exp(-alpha x - beta x x), T = min(floor(S 2^32), 2^32-1).
+// written: x = m d, y = m D, S = exp(-alpha x - beta x (x + 2 y)),
+// T = min(floor(S 2^32), 2^32-1).  D is the unrepaired dose of earlier
+// fractions (incomplete repair, see prior_damage); D = 0 is the plain law.
 #pragma clang fp contract(off)
-__device__ uint32_t lq_threshold(double d, double m, double alpha, double beta) {
-    const double x = m * d;
-    const double e = -(alpha * x) - (beta * x) * x;
+__device__ uint32_t lq_threshold(double d, double m, double alpha, double beta, double D) {
+    const double x = m * d, y = m * D;
+    const double e = -(alpha * x) - (beta * x) * (x + 2.0 * y);
     const double s = exp(e) * 4294967296.0;
     const double f = floor(s);
     return f >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)f;
+}
+
+// Unrepaired dose before fraction j of protocol p: the sum over earlier
+// fractions i of d_i 2^(-(t_j - t_i) / half_time), in index order (times in
+// hours, or half-hours scaled by 0.5); 0 when half_time is 0.
+__device__ double prior_damage(const float* dose, const int32_t* gap, int j, long long tj, double half_time,
+                               double unit) {
+    if (!(half_time > 0.0)) return 0.0;
+    double acc = 0.0;
+    long long ti = 0;
+    for (int i = 0; i < j; ++i) {
+        ti += gap[i];
+        const float di = dose[i];
+        if (di > 0.0f) acc += (double)di * exp2(-(((double)(tj - ti) * unit) / half_time));
+    }
+    return acc;
 }
 #pragma clang fp contract(on)
 
@@ -182,6 +200,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     __shared__ uint32_t s_claim[RR * L / 32];  // one "has a daughter" bit per site
     __shared__ uint32_t s_ev_step[GGA_KMAX];   // half-hours since step n0 (2 (n - n0), + 1 at the half hour)
     __shared__ float s_ev_dose[GGA_KMAX];
+    __shared__ double s_ev_prior[GGA_KMAX];    // unrepaired dose of the earlier fractions (incomplete repair)
     __shared__ uint32_t s_ev_thr[GGA_KMAX][4];
     __shared__ int s_nev, s_valid, s_evj[2];
     __shared__ int s_count[2];
@@ -271,6 +290,8 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             if (d > 0.0f && tau >= 2LL * a.n0 && tau < 2LL * ((long long)a.n0 + nsteps)) {
                 s_ev_step[nev] = (uint32_t)(tau - 2LL * a.n0);
                 s_ev_dose[nev] = d;
+                s_ev_prior[nev] = prior_damage(a.dose + (size_t)p * a.K, a.gap + (size_t)p * a.K, j, t,
+                                               a.prm.repair_half_time, a.half ? 0.5 : 1.0);
                 ++nev;
             }
         }
@@ -301,7 +322,8 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         if (tid < 4 * nev) s_ev_thr[tid >> 2][tid & 3] = a.ev_thr[((size_t)p * a.K + s_evj[tid >> 2]) * 4 + (tid & 3)];
     } else {
         for (int e = tid; e < 4 * nev; e += G::NT)
-            s_ev_thr[e >> 2][e & 3] = lq_threshold((double)s_ev_dose[e >> 2], P.m[e & 3], P.alpha, P.beta);
+            s_ev_thr[e >> 2][e & 3] = lq_threshold((double)s_ev_dose[e >> 2], P.m[e & 3], P.alpha, P.beta,
+                                                   s_ev_prior[e >> 2]);
     }
 
     // ---- state: fields in registers, cells in LDS ----

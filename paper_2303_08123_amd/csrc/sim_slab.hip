@@ -8,7 +8,8 @@ namespace {
 
 // Per protocol: validity (the resident kernel's rules), and the time in
 // half-hours (2 t for delays in hours; horizons stay below 2^30) and class
-// survival thresholds of every positive-dose fraction, in order.
+// survival thresholds (with the unrepaired dose of the earlier fractions) of
+// every positive-dose fraction, in order.
 __global__ void event_table_kernel(SimArgs a, int P, int32_t* valid_out, int32_t* count_out, int32_t* step_out,
                                    uint32_t* thr_out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -27,9 +28,11 @@ __global__ void event_table_kernel(SimArgs a, int P, int32_t* valid_out, int32_t
         t += g;
         if (d > 0.0f) {
             const long long tau = a.half ? t : 2 * t;
+            const double D = prior_damage(a.dose + (size_t)p * a.K, a.gap + (size_t)p * a.K, j, t,
+                                          a.prm.repair_half_time, a.half ? 0.5 : 1.0);
             step_out[(size_t)p * a.K + nev] = tau > 0x7FFFFFFFll ? 0x7FFFFFFF : (int)tau;
             for (int c = 0; c < 4; ++c)
-                thr_out[((size_t)p * a.K + nev) * 4 + c] = lq_threshold((double)d, a.prm.m[c], a.prm.alpha, a.prm.beta);
+                thr_out[((size_t)p * a.K + nev) * 4 + c] = lq_threshold((double)d, a.prm.m[c], a.prm.alpha, a.prm.beta, D);
             ++nev;
         }
     }

@@ -295,7 +295,9 @@ def test_params_from_json_reads_the_model_file(gga, tmp_path):
     cases = [("{ not json", -1), (json.dumps({k: v for k, v in model.items() if k != "kappa"}), -5),
              (json.dumps(dict(model, T_min=12.5)), -5), (json.dumps(dict(model, lambda_=1)), 0),
              (json.dumps(dict(model, **{"lambda": [0.3, 0.1, 0.1]})), -5), (json.dumps(dict(model, m=[1, 2])), -5),
-             (json.dumps(model) + " trailing", -1)]
+             (json.dumps(model) + " trailing", -1),
+             (json.dumps(dict(model, repair_half_time=-1.0)), -5),
+             (json.dumps(dict(model, repair_half_time=float("inf"))), -1)]
     for text, rc in cases:
         bad.write_text(text)
         assert gga.LIB.gga_params_from_json(str(bad).encode(), ctypes.byref(p)) == rc, text[:40]
@@ -303,6 +305,12 @@ def test_params_from_json_reads_the_model_file(gga, tmp_path):
             assert bytes(p) == before
         p = gga.Params()
         p.struct_size = ctypes.sizeof(gga.Params)
+    # the repair half-time is optional (0 when absent) and read when present
+    bad.write_text(json.dumps({k: v for k, v in model.items() if k != "repair_half_time"}))
+    assert gga.LIB.gga_params_from_json(str(bad).encode(), ctypes.byref(p)) == 0 and p.repair_half_time == 0.0
+    bad.write_text(json.dumps(dict(model, repair_half_time=2.5)))
+    assert gga.LIB.gga_params_from_json(str(bad).encode(), ctypes.byref(p)) == 0 and p.repair_half_time == 2.5
+    assert bytes(p) == bytes(gga.make_params(dict(model, repair_half_time=2.5)))
     assert gga.LIB.gga_params_from_json(b"/nonexistent/model.json", ctypes.byref(p)) == -1
     p.struct_size = 4
     assert gga.LIB.gga_params_from_json(path.encode(), ctypes.byref(p)) == -2

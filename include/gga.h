@@ -82,7 +82,15 @@ typedef struct gga_params {
                                exp(-alpha x - beta x (x + 2 y)), y = m D_j,
                                D_j = sum over earlier fractions i of
                                d_i 2^(-(t_j - t_i) / repair_half_time)          */
+    double oer_max;         /* oxygen effect: finite, >= 1; 1 turns it off.  > 1: a cell's
+                               dose d and unrepaired dose D are scaled by
+                               OMF = (oer_max o + oer_k) / (oer_max (o + oer_k)), o the
+                               midpoint of the oxygen bin of the site's current O
+                               (GGA_OER_BINS bins of O / ghost[0] over [0, 1], the
+                               last also above 1; ghost[0] > 0 required)               */
+    double oer_k;           /* oxygen level of half the effect, same units as O; > 0  */
 } gga_params;
+#define GGA_OER_BINS 16
 
 /*
  * Fill *out from a model file: a flat JSON object whose values are numbers or
@@ -90,7 +98,8 @@ typedef struct gga_params {
  * activity[4], theta_O_quiesce, theta_G_quiesce, theta_O_death,
  * theta_G_death, theta_H_death, T_min, T_lys, A0, seed_radius (integers),
  * class_age[2] (integers), P_div, alpha, beta, m[4], and optionally
- * repair_half_time (default 0) (the package's
+ * repair_half_time (default 0), oer_max (default 1) and oer_k (default
+ * 0.05) (the package's
  * data/model_default.json).  Other keys are ignored.  out->struct_size must
  * be sizeof(gga_params) (GGA_E_ABI otherwise); *out is written only on
  * success.  Host only, no device work.  Errors: GGA_E_ARG (null pointer,

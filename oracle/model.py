@@ -16,6 +16,7 @@ import numpy as np
 
 EMPTY, PROLIF, QUIESC, DEAD = 0, 1, 2, 3
 AGE_MAX = 255
+OER_BINS = 16      # oxygen levels of the oxygen effect: bins of O / O_boundary over [0, 1]
 
 
 def _f32(x):
@@ -44,6 +45,8 @@ class Params:
     class_age: tuple  # proliferating sensitivity classes: age < a0, < a1, >= a1
     m: tuple          # dose multipliers for the classes young, mid, old, quiescent
     repair_half_time: float = 0.0   # hours; 0: sublethal damage repaired between fractions
+    oer_max: float = 1.0            # oxygen enhancement ratio at full oxygenation; 1: no oxygen effect
+    oer_k: float = 0.05             # oxygen level of half the effect, in the oxygen field's units
 
     @classmethod
     def from_dict(cls, d):
@@ -60,7 +63,12 @@ class Params:
             class_age=tuple(int(v) for v in d["class_age"]),
             m=tuple(float(v) for v in d["m"]),
             repair_half_time=float(d.get("repair_half_time", 0.0)),
+            oer_max=float(d.get("oer_max", 1.0)), oer_k=float(d.get("oer_k", 0.05)),
         )
+
+    @property
+    def oxygen_effect(self):
+        return self.oer_max > 1.0
 
     @property
     def T_div(self):

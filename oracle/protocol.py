@@ -114,9 +114,44 @@ def events(dose_row, gap_row, nfrac, horizon, params, half_hour=False):
         if d <= 0.0 or t >= end:
             continue
         prior = prior_damage(dose_row, gap_row, j, params.repair_half_time, 0.5 if half_hour else 1.0)
-        thr = [lq_threshold(d, params.m[c], params.alpha, params.beta, prior) for c in range(4)]
+        if params.oxygen_effect:
+            thr = oxygen_thresholds(d, prior, params)
+        else:
+            thr = [lq_threshold(d, params.m[c], params.alpha, params.beta, prior) for c in range(4)]
         out.append((t, thr))
     return out
+
+
+def oxygen_modification(b, params):
+    """Dose-modifying factor of oxygen bin b: the oxygen enhancement ratio law
+    OMF(O) = (oer_max O + K) / (oer_max (O + K)) (1 when well oxygenated,
+    1 / oer_max without oxygen) at the bin's midpoint O = (b + 1/2) O_ref / B,
+    O_ref the boundary oxygen value, B = OER_BINS."""
+    from .model import OER_BINS
+    o = (b + 0.5) * float(params.ghost[0]) / OER_BINS
+    return (params.oer_max * o + params.oer_k) / (params.oer_max * (o + params.oer_k))
+
+
+def oxygen_thresholds(d, prior, params):
+    """Thresholds [class][oxygen bin] of a fraction of d Gy (unrepaired dose
+    `prior`): the dose and the unrepaired dose are both scaled by the bin's
+    oxygen modification factor."""
+    from .model import OER_BINS
+    out = []
+    for c in range(4):
+        row = []
+        for b in range(OER_BINS):
+            f = oxygen_modification(b, params)
+            row.append(lq_threshold(f * d, params.m[c], params.alpha, params.beta, f * prior))
+        out.append(row)
+    return out
+
+
+def oxygen_bin(o, params):
+    """Bin of oxygen level o: floor(B o / O_ref) clamped to 0 .. B - 1."""
+    from .model import OER_BINS
+    q = float(o) / float(params.ghost[0])
+    return min(OER_BINS - 1, max(0, int(math.floor(q * OER_BINS))))
 
 
 def count_sequences(values, length, budget, exact=False):

@@ -14,7 +14,8 @@ are not printed in the paper; the synthetic model below fixes them:
 Per instance (protocol p, replica r) and step n = 0 .. N-1 (one model hour):
   1. irradiation, if a fraction falls on step n: each live cell of sensitivity
      class c survives iff w1 < T_c (linear-quadratic threshold), else it is
-     DEAD with age 0;
+     DEAD with age 0; with the oxygen effect the threshold also depends on
+     the oxygen bin of the site's current O (protocol.oxygen_thresholds);
   2. the activity map a = act[state] is frozen until the next fraction or the
      end of the hour;
   3. `substeps` explicit FTCS updates of the three fields,
@@ -35,7 +36,7 @@ import numpy as np
 
 from .model import AGE_MAX, DEAD, EMPTY, PROLIF, QUIESC, Params
 from .philox import INIT_STEP, site_words
-from .protocol import events, validate
+from .protocol import events, oxygen_bin, validate
 
 # Von Neumann neighbours in the fixed order N, E, S, W (row y grows southwards).
 DY = (-1, 0, 1, 0)
@@ -84,8 +85,9 @@ def sensitivity_class(state, age, params: Params):
     return np.where(state == QUIESC, 3, cls)
 
 
-def irradiate(cells, thresholds, draw, params: Params):
-    """Apply one fraction: a live cell survives iff its word w1 < T[class]."""
+def irradiate(cells, thresholds, draw, params: Params, fields=None):
+    """Apply one fraction: a live cell survives iff its word w1 < T[class]
+    (with the oxygen effect, T[class][oxygen bin of the site's O])."""
     H, W = cells.shape
     state, age = unpack(cells)
     live = (state == PROLIF) | (state == QUIESC)
@@ -93,7 +95,12 @@ def irradiate(cells, thresholds, draw, params: Params):
     if len(ys) == 0:
         return cells.copy()
     w1 = draw(ys * W + xs)[1].astype(np.int64)
-    thr = np.asarray(thresholds, dtype=np.int64)[sensitivity_class(state[ys, xs], age[ys, xs], params)]
+    cls = sensitivity_class(state[ys, xs], age[ys, xs], params)
+    if params.oxygen_effect:
+        bins = np.array([oxygen_bin(fields[0, y, x], params) for y, x in zip(ys, xs)], dtype=np.int64)
+        thr = np.asarray(thresholds, dtype=np.int64)[cls, bins]
+    else:
+        thr = np.asarray(thresholds, dtype=np.int64)[cls]
     killed = w1 >= thr
     out = cells.copy()
     out[ys[killed], xs[killed]] = pack(DEAD, 0)
@@ -206,13 +213,14 @@ def step(fields, cells, n, thresholds, p, r, seed, params: Params, substeps, thr
     `thresholds_mid` (its middle) are None without a fraction."""
     draw = lambda sites: site_words(sites, n, r, p, seed)
     if thresholds is not None:
-        cells = irradiate(cells, thresholds, draw, params)
+        cells = irradiate(cells, thresholds, draw, params, fields)
     act = activity(cells, params)
     first = substeps // 2 if thresholds_mid is not None else substeps
     for _ in range(first):
         fields = diffuse_substep(fields, act, params)
     if thresholds_mid is not None:
-        cells = irradiate(cells, thresholds_mid, lambda sites: site_words(sites, MID_STEP | n, r, p, seed), params)
+        cells = irradiate(cells, thresholds_mid, lambda sites: site_words(sites, MID_STEP | n, r, p, seed), params,
+                          fields)
         act = activity(cells, params)
         for _ in range(substeps - first):
             fields = diffuse_substep(fields, act, params)

@@ -37,6 +37,7 @@ class Params(ctypes.Structure):
         ("seed_radius", ctypes.c_int32), ("class_age", ctypes.c_int32 * 2),
         ("P_div", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
         ("m", ctypes.c_double * 4), ("repair_half_time", ctypes.c_double),
+        ("oer_max", ctypes.c_double), ("oer_k", ctypes.c_double),
     ]
 
 
@@ -222,6 +223,7 @@ def make_params(d):
     p.P_div, p.alpha, p.beta = float(d["P_div"]), float(d["alpha"]), float(d["beta"])
     p.m[:] = [float(v) for v in d["m"]]
     p.repair_half_time = float(d.get("repair_half_time", 0.0))
+    p.oer_max, p.oer_k = float(d.get("oer_max", 1.0)), float(d.get("oer_k", 0.05))
     return p
 
 

@@ -44,6 +44,9 @@ int check_params(const gga_params* p) {
     for (int c = 0; c < 4; ++c)
         if (!std::isfinite(p->m[c])) return GGA_E_PARAM;
     if (!(std::isfinite(p->repair_half_time) && p->repair_half_time >= 0.0)) return GGA_E_PARAM;
+    if (!(std::isfinite(p->oer_max) && p->oer_max >= 1.0 && std::isfinite(p->oer_k) && p->oer_k > 0.0))
+        return GGA_E_PARAM;
+    if (p->oer_max > 1.0 && !(p->ghost[0] > 0.0f)) return GGA_E_PARAM;   // oxygen bins are fractions of ghost[0]
     return GGA_OK;
 }
 
@@ -1140,7 +1143,7 @@ struct Group {
 struct UnevenPlan {
     std::vector<int32_t> host;             // instance lists then horizons, uploaded together
     std::vector<Group> groups;
-    size_t off_lists, off_horizon, off_valid, off_count, off_step, off_thr, total;
+    size_t off_lists, off_horizon, off_valid, off_count, off_step, off_frac, total;
 };
 
 // Group the P*R instances by lattice side, each group sorted by horizon
@@ -1178,7 +1181,7 @@ int plan_uneven(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, i
     plan->off_valid = take(sizeof(int32_t) * (size_t)P);
     plan->off_count = take(sizeof(int32_t) * (size_t)P);
     plan->off_step = take(sizeof(int32_t) * (size_t)P * K);
-    plan->off_thr = take(sizeof(uint32_t) * 4 * (size_t)P * K);
+    plan->off_frac = take(sizeof(gga::EventFraction) * (size_t)P * K);
     for (auto& g : plan->groups)
         if (gga::variant_is_slab(g.variant)) g.state_off = take(2 * state_bytes(g.L) * (size_t)g.count);
     plan->total = off;
@@ -1194,11 +1197,11 @@ hipError_t enqueue_uneven(const gga::SimArgs& base, const UnevenPlan& plan, char
     a.ev_valid = reinterpret_cast<const int32_t*>(ws + plan.off_valid);
     a.ev_count = reinterpret_cast<const int32_t*>(ws + plan.off_count);
     a.ev_step = reinterpret_cast<const int32_t*>(ws + plan.off_step);
-    a.ev_thr = reinterpret_cast<const uint32_t*>(ws + plan.off_thr);
+    a.ev_frac = reinterpret_cast<const gga::EventFraction*>(ws + plan.off_frac);
     hipError_t e = gga::launch_event_table(a, P, reinterpret_cast<int32_t*>(ws + plan.off_valid),
                                            reinterpret_cast<int32_t*>(ws + plan.off_count),
                                            reinterpret_cast<int32_t*>(ws + plan.off_step),
-                                           reinterpret_cast<uint32_t*>(ws + plan.off_thr), stream);
+                                           reinterpret_cast<gga::EventFraction*>(ws + plan.off_frac), stream);
     const int32_t* lists = reinterpret_cast<const int32_t*>(ws + plan.off_lists);
     for (const Group& g : plan.groups) {
         if (e != hipSuccess) break;
@@ -1302,7 +1305,8 @@ int gga_simulate_uneven(const gga_params* params, const gga_sim_cfg* cfg, const 
     if ((rc = check_uneven_cfg(cfg))) return rc;
     if ((rc = check_batch(P, K, cfg->R))) return rc;
     if (P == 0) return GGA_OK;
-    if (!lattice_h || !horizon_h || !nfrac_d || !live_d || !fitness_d || !ws_d || (K > 0 && (!dose_d || !gap_h_d)))
+    if (!lattice_h || !horizon_h || !nfrac_d || !live_d || !fitness_d || !ws_d || misaligned16(ws_d) ||
+        (K > 0 && (!dose_d || !gap_h_d)))
         return GGA_E_ARG;
     UnevenPlan plan;
     if ((rc = plan_uneven(lattice_h, horizon_h, P, K, cfg->R, nullptr, &plan))) return rc;
@@ -1316,7 +1320,8 @@ int gga_simulate_uneven(const gga_params* params, const gga_sim_cfg* cfg, const 
 
 size_t gga_event_table_bytes(int32_t P, int32_t K) {
     if (P < 0 || K < 0 || K > GGA_KMAX) return 0;
-    return align256(sizeof(int32_t) * 2 * (size_t)P) + align256(sizeof(int32_t) * 5 * (size_t)P * K);
+    return align256(sizeof(int32_t) * 2 * (size_t)P) + align256(sizeof(int32_t) * (size_t)P * K) +
+           align256(sizeof(gga::EventFraction) * (size_t)P * K);
 }
 
 int gga_state_run_variant(const gga_params* params, const gga_sim_cfg* cfg, int32_t variant,
@@ -1344,20 +1349,22 @@ int gga_state_run_variant(const gga_params* params, const gga_sim_cfg* cfg, int3
         e = gga::launch_variant(variant, a, P * cfg->R, stream);
         return e == hipSuccess ? GGA_OK : hip_fail(e);
     }
-    if (nsteps < 1 || !fields2_d || !cells2_d || !ws_d || ws_bytes < gga_event_table_bytes(P, K)) return GGA_E_ARG;
+    if (nsteps < 1 || !fields2_d || !cells2_d || !ws_d || misaligned16(ws_d) || ws_bytes < gga_event_table_bytes(P, K))
+        return GGA_E_ARG;
     const gga::SimVariant& v = gga::SIM_VARIANTS[variant];
     if (slab_plan(cfg->L, v.rpt * v.nw, cfg->substeps + 2, &a) <= 0) return GGA_E_UNSUPPORTED;
     char* ws = static_cast<char*>(ws_d);
     int32_t* valid = reinterpret_cast<int32_t*>(ws);
     int32_t* count = valid + P;
     int32_t* step = reinterpret_cast<int32_t*>(ws + align256(sizeof(int32_t) * 2 * (size_t)P));
-    uint32_t* thr = reinterpret_cast<uint32_t*>(step + (size_t)P * K);
+    gga::EventFraction* frac = reinterpret_cast<gga::EventFraction*>(
+        ws + align256(sizeof(int32_t) * 2 * (size_t)P) + align256(sizeof(int32_t) * (size_t)P * K));
     a.ev_valid = valid;
     a.ev_count = count;
     a.ev_step = step;
-    a.ev_thr = thr;
+    a.ev_frac = frac;
     a.count_at = n0 + nsteps;
-    e = gga::launch_event_table(a, P, valid, count, step, thr, stream);
+    e = gga::launch_event_table(a, P, valid, count, step, frac, stream);
     if (e == hipSuccess) e = gga::launch_slab_live(a, P * cfg->R, stream);
     for (int32_t n = n0; n < n0 + nsteps && e == hipSuccess; ++n) {
         const bool odd = ((n - n0) & 1) != 0;

@@ -9,6 +9,13 @@ namespace gga {
 
 enum : int { MODE_LOAD = 1, MODE_STORE = 2 };
 
+// One positive-dose fraction of the slab form's event table (16 bytes).
+struct EventFraction {
+    float dose;
+    int32_t pad;
+    double prior;           // unrepaired dose of the earlier fractions (incomplete repair)
+};
+
 // Arguments of one simulation launch (passed by value as the kernel argument).
 struct SimArgs {
     gga_params prm;
@@ -43,7 +50,7 @@ struct SimArgs {
     const int32_t* ev_valid;  // [P]
     const int32_t* ev_count;  // [P]
     const int32_t* ev_step;   // [P][K] times of the positive-dose fractions in half-hours, in order
-    const uint32_t* ev_thr;   // [P][K][4] survival thresholds per sensitivity class
+    const EventFraction* ev_frac;   // [P][K] dose and unrepaired dose of each of those fractions
     int32_t count_at;         // slab form without horizon[]: the step whose end is counted
     int32_t lib_n;            // resident form with MODE_LOAD: replica r loads state r mod lib_n (0: its own)
 };
@@ -81,7 +88,7 @@ int variant_choice(int L, bool resident_only);
 int set_variant_choice(int L, int v);
 // event table of P protocols for the slab form (validity as the resident kernel decides it)
 hipError_t launch_event_table(const SimArgs& a, int P, int32_t* valid, int32_t* count, int32_t* step,
-                              uint32_t* thr, hipStream_t stream);
+                              EventFraction* frac, hipStream_t stream);
 // live[inst] = 0 (-1 for invalid protocols) for instances inst_list[0 .. n-1] (or 0 .. n-1)
 hipError_t launch_slab_live(const SimArgs& a, int n, hipStream_t stream);
 // initial state of the slab-form instances inst_list[0 .. n-1] into state rows 0 .. n-1, live

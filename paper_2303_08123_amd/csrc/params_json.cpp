@@ -1,7 +1,8 @@
 // gga_params_from_json: the model constants from a flat JSON object whose
 // values are numbers or arrays of numbers (the format of the package's
 // data/model_default.json).  Every field of gga_params must be present except
-// repair_half_time (default 0); keys the struct does not have are ignored.
+// repair_half_time (default 0), oer_max (default 1, no oxygen effect) and
+// oer_k (default 0.05); keys the struct does not have are ignored.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -157,6 +158,10 @@ extern "C" int gga_params_from_json(const char* path, gga_params* out) {
     doubles("beta", &p.beta, 1);
     doubles("m", p.m, 4);
     if (kv.count("repair_half_time")) doubles("repair_half_time", &p.repair_half_time, 1);   // optional, default 0
+    p.oer_max = 1.0;                                  // optional: no oxygen effect
+    p.oer_k = 0.05;
+    if (kv.count("oer_max")) doubles("oer_max", &p.oer_max, 1);
+    if (kv.count("oer_k")) doubles("oer_k", &p.oer_k, 1);
     if (!ok) return GGA_E_PARAM;
     const int rc = gga::check_params_host(&p);
     if (rc != GGA_OK) return rc;

@@ -35,7 +35,10 @@ template <int CPL, int RPT, int NW>
 hipError_t launch_sim(const SimArgs& a, int n_blocks, hipStream_t stream) {
     using G = Geo<CPL, RPT, NW>;
     static_assert(!G::SLAB, "slab variants are built in sim_slab.hip");
-    hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
+    if (a.prm.oer_max > 1.0)
+        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, true>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
+    else
+        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, false>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
     return hipGetLastError();
 }
 

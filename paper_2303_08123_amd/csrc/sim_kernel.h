@@ -84,6 +84,22 @@ __device__ double prior_damage(const float* dose, const int32_t* gap, int j, lon
     }
     return acc;
 }
+
+// Oxygen modification factor of oxygen bin b (the oxygen effect, oer_max > 1):
+// (oer_max o + K) / (oer_max (o + K)) at the bin's midpoint
+// o = (b + 1/2) ghost_O / GGA_OER_BINS.
+__device__ double oxygen_modification(const gga_params& P, int b) {
+    const double o = (((double)b + 0.5) * (double)P.ghost[0]) / GGA_OER_BINS;
+    return (P.oer_max * o + P.oer_k) / (P.oer_max * (o + P.oer_k));
+}
+
+// Oxygen bin of a site from its O in field units (O = o^ + ghost_O, rho_O = 1):
+// floor(GGA_OER_BINS O / ghost_O) clamped to 0 .. GGA_OER_BINS - 1, in float64.
+__device__ __forceinline__ int oxygen_bin(float o_hat, const gga_params& P) {
+    const double q = ((double)o_hat + (double)P.ghost[0]) / (double)P.ghost[0];
+    const double b = floor(q * GGA_OER_BINS);
+    return b < 0.0 ? 0 : (b > GGA_OER_BINS - 1 ? GGA_OER_BINS - 1 : (int)b);
+}
 #pragma clang fp contract(on)
 
 // CPL consecutive uint16 cell words of one row, read or written with one
@@ -186,7 +202,9 @@ struct Geo {
     static constexpr uint32_t COL_LAST = col_bits(CPL - 1);
 };
 
-template <int CPL, int RPT, int NW>
+// OER: the oxygen effect on radiosensitivity (gga_params.oer_max > 1), a
+// separate instantiation so that runs without it keep their register budget.
+template <int CPL, int RPT, int NW, bool OER>
 __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     using G = Geo<CPL, RPT, NW>;
     constexpr int L = G::L;
@@ -202,6 +220,8 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     __shared__ float s_ev_dose[GGA_KMAX];
     __shared__ double s_ev_prior[GGA_KMAX];    // unrepaired dose of the earlier fractions (incomplete repair)
     __shared__ uint32_t s_ev_thr[GGA_KMAX][4];
+    // the current fraction's thresholds per class and oxygen bin (oxygen effect only)
+    __shared__ uint32_t s_oer_thr[OER ? 4 : 1][OER ? GGA_OER_BINS : 1];
     __shared__ int s_nev, s_valid, s_evj[2];
     __shared__ int s_count[2];
     __shared__ CellConst s_k;                  // cell-update constants, read where used
@@ -319,12 +339,16 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     }
     const int nev = s_nev;
     if constexpr (SLAB) {
-        if (tid < 4 * nev) s_ev_thr[tid >> 2][tid & 3] = a.ev_thr[((size_t)p * a.K + s_evj[tid >> 2]) * 4 + (tid & 3)];
-    } else {
-        for (int e = tid; e < 4 * nev; e += G::NT)
-            s_ev_thr[e >> 2][e & 3] = lq_threshold((double)s_ev_dose[e >> 2], P.m[e & 3], P.alpha, P.beta,
-                                                   s_ev_prior[e >> 2]);
+        if (tid < nev) {
+            const EventFraction ef = a.ev_frac[(size_t)p * a.K + s_evj[tid]];
+            s_ev_dose[tid] = ef.dose;
+            s_ev_prior[tid] = ef.prior;
+        }
+        __syncthreads();
     }
+    for (int e = tid; e < 4 * nev; e += G::NT)
+        s_ev_thr[e >> 2][e & 3] = lq_threshold((double)s_ev_dose[e >> 2], P.m[e & 3], P.alpha, P.beta,
+                                               s_ev_prior[e >> 2]);
 
     // ---- state: fields in registers, cells in LDS ----
     float F[3][RPT + 1][CPL];                  // slot RPT: spare row for the rotating sub-steps
@@ -534,6 +558,18 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             // the half hour, after half of the hour's sub-steps (its words from
             // the block of step word n | 2^31)
             if (ev < nev && s_ev_step[ev] == rel + half) {
+                // with the oxygen effect: this fraction's thresholds per class
+                // and oxygen bin, and each site's bin from its current O
+                if constexpr (OER) {
+                    __syncthreads();                      // the previous fraction's table is read
+                    if (tid < 4 * GGA_OER_BINS) {
+                        const double f = oxygen_modification(P, tid % GGA_OER_BINS);
+                        s_oer_thr[tid / GGA_OER_BINS][tid % GGA_OER_BINS] =
+                            lq_threshold(f * (double)s_ev_dose[ev], P.m[tid / GGA_OER_BINS], P.alpha, P.beta,
+                                         f * s_ev_prior[ev]);
+                    }
+                    __syncthreads();
+                }
                 const uint32_t t0 = s_ev_thr[ev][0], t1 = s_ev_thr[ev][1];
                 const uint32_t t2 = s_ev_thr[ev][2], t3 = s_ev_thr[ev][3];
                 const int ca0 = s_k.ca0, ca1 = s_k.ca1;
@@ -542,18 +578,34 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                 for (int i = 0; i < RPT; ++i)
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) {
-                        const int st = cellp[i * L + c] & 3;
-                        if (st == PROLIF || st == QUIESC) live_mask |= 1u << (i * CPL + c);
+                        const uint32_t w = cellp[i * L + c];
+                        const int st = w & 3;
+                        if (st == PROLIF || st == QUIESC) {
+                            live_mask |= 1u << (i * CPL + c);
+                            // the site's oxygen bin rides in the word's free bits 10-13
+                            // until this fraction is done
+                            if constexpr (OER) cellp[i * L + c] = (uint16_t)(w | ((uint32_t)oxygen_bin(F[0][i][c], P) << 10));
+                        }
                     }
                 while (live_mask) {
                     const int idx = __builtin_ctz(live_mask);
                     live_mask &= live_mask - 1;
                     const int site = own + (idx / CPL) * L + idx % CPL;
                     const uint32_t w = s_cell[site];
-                    const int st = w & 3, age = w >> 2;
-                    const uint32_t thr = (st == QUIESC) ? t3 : (age < ca0 ? t0 : (age < ca1 ? t1 : t2));
+                    const int st = w & 3, age = OER ? (w >> 2) & 255 : w >> 2;
+                    uint32_t thr = (st == QUIESC) ? t3 : (age < ca0 ? t0 : (age < ca1 ? t1 : t2));
+                    if constexpr (OER) {
+                        const int cls = (st == QUIESC) ? 3 : (age < ca0 ? 0 : (age < ca1 ? 1 : 2));
+                        thr = s_oer_thr[cls][(w >> 10) & 15u];
+                    }
                     const Block4 b = philox10(site + gofs, (uint32_t)n | (half << 31), r, p, seed_lo, seed_hi);
                     if (b.w1 >= thr) s_cell[site] = DEAD;
+                }
+                if constexpr (OER) {
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c) cellp[i * L + c] = (uint16_t)(cellp[i * L + c] & 0x3FFu);
                 }
                 ++ev;
             }

@@ -7,11 +7,11 @@ namespace gga {
 namespace {
 
 // Per protocol: validity (the resident kernel's rules), and the time in
-// half-hours (2 t for delays in hours; horizons stay below 2^30) and class
-// survival thresholds (with the unrepaired dose of the earlier fractions) of
-// every positive-dose fraction, in order.
+// half-hours (2 t for delays in hours; horizons stay below 2^30), dose and
+// unrepaired dose of the earlier fractions of every positive-dose fraction,
+// in order (the slab kernels derive the survival thresholds from them).
 __global__ void event_table_kernel(SimArgs a, int P, int32_t* valid_out, int32_t* count_out, int32_t* step_out,
-                                   uint32_t* thr_out) {
+                                   EventFraction* frac_out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     const int k = a.nfrac[p];
@@ -31,8 +31,7 @@ __global__ void event_table_kernel(SimArgs a, int P, int32_t* valid_out, int32_t
             const double D = prior_damage(a.dose + (size_t)p * a.K, a.gap + (size_t)p * a.K, j, t,
                                           a.prm.repair_half_time, a.half ? 0.5 : 1.0);
             step_out[(size_t)p * a.K + nev] = tau > 0x7FFFFFFFll ? 0x7FFFFFFF : (int)tau;
-            for (int c = 0; c < 4; ++c)
-                thr_out[((size_t)p * a.K + nev) * 4 + c] = lq_threshold((double)d, a.prm.m[c], a.prm.alpha, a.prm.beta, D);
+            frac_out[(size_t)p * a.K + nev] = EventFraction{d, 0, D};
             ++nev;
         }
     }
@@ -80,7 +79,10 @@ template <int CPL, int RPT, int NW>
 hipError_t launch_slab(const SimArgs& a, int n_blocks, hipStream_t stream) {
     using G = Geo<CPL, RPT, NW>;
     static_assert(G::SLAB, "resident variants are built in sim.hip");
-    hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
+    if (a.prm.oer_max > 1.0)
+        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, true>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
+    else
+        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, false>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -98,9 +100,9 @@ hipError_t launch_slab_variant(int v, const SimArgs& a, int n_blocks, hipStream_
 }
 
 hipError_t launch_event_table(const SimArgs& a, int P, int32_t* valid, int32_t* count, int32_t* step,
-                              uint32_t* thr, hipStream_t stream) {
+                              EventFraction* frac, hipStream_t stream) {
     if (P <= 0) return hipSuccess;
-    hipLaunchKernelGGL(event_table_kernel, dim3((P + 127) / 128), dim3(128), 0, stream, a, P, valid, count, step, thr);
+    hipLaunchKernelGGL(event_table_kernel, dim3((P + 127) / 128), dim3(128), 0, stream, a, P, valid, count, step, frac);
     return hipGetLastError();
 }
 

@@ -57,9 +57,14 @@ def near_threshold(fields, cells, params, window=WINDOW, radius=2, abs_window=0.
     for f, th in ((O, params.th_Od), (O, params.th_Oq), (G, params.th_Gd), (G, params.th_Gq),
                   (H, params.th_Hd)):
         near |= live & (np.abs(f - th) <= max(window * max(abs(th), 1e-3), abs_window))
-    out = near.copy()
-    ys, xs = np.nonzero(near)
-    Hh, W = cells.shape
+    return dilate(near, radius)
+
+
+def dilate(mask, radius):
+    """Sites within Manhattan distance `radius` of a marked site."""
+    out = mask.copy()
+    ys, xs = np.nonzero(mask)
+    Hh, W = mask.shape
     for dy in range(-radius, radius + 1):
         for dx in range(-(radius - abs(dy)), radius - abs(dy) + 1):
             yy, xx = ys + dy, xs + dx
@@ -72,19 +77,34 @@ def oracle_step_detail(fields, cells, n, thr, p, r, seed, params, substeps, abs_
     """One oracle step (thr_mid: a fraction at the half hour); returns
     (fields, cells, counted-site map)."""
     draw = lambda s: site_words(s, n, r, p, seed)
-    c1 = sim.irradiate(cells, thr, draw, params) if thr is not None else cells
+    c1 = sim.irradiate(cells, thr, draw, params, fields) if thr is not None else cells
     act = sim.activity(c1, params)
     f = fields
     first = substeps // 2 if thr_mid is not None else substeps
+    edge = np.zeros(cells.shape, bool)
+    if params.oxygen_effect and thr is not None:
+        edge |= near_oxygen_edge(fields, cells, params)
     for _ in range(first):
         f = sim.diffuse_substep(f, act, params)
     if thr_mid is not None:
-        c1 = sim.irradiate(c1, thr_mid, lambda s: site_words(s, sim.MID_STEP | n, r, p, seed), params)
+        if params.oxygen_effect:
+            edge |= near_oxygen_edge(f, c1, params)
+        c1 = sim.irradiate(c1, thr_mid, lambda s: site_words(s, sim.MID_STEP | n, r, p, seed), params, f)
         act = sim.activity(c1, params)
         for _ in range(substeps - first):
             f = sim.diffuse_substep(f, act, params)
     c2 = sim.cell_update(c1, f, draw, params)
-    return f, c2, near_threshold(f, c1, params, abs_window=abs_window)
+    return f, c2, near_threshold(f, c1, params, abs_window=abs_window) | dilate(edge, 2)
+
+
+def near_oxygen_edge(fields, cells, params, window=WINDOW):
+    """Live sites whose oxygen level lies within `window` (relative) of an
+    oxygen-bin edge: float32 rounding may put them in the other bin."""
+    from oracle.model import OER_BINS
+    state = cells & 3
+    live = (state == 1) | (state == 2)
+    q = fields[0] / float(params.ghost[0]) * OER_BINS
+    return live & (np.abs(q - np.round(q)) < window * np.maximum(np.abs(q), 1.0)) & (q > 0.5) & (q < OER_BINS - 0.5)
 
 
 def oracle_certain_prefix(params, L, nsteps, substeps, ev, p, r, seed, half_hour=False):

@@ -297,6 +297,9 @@ def test_params_from_json_reads_the_model_file(gga, tmp_path):
              (json.dumps(dict(model, **{"lambda": [0.3, 0.1, 0.1]})), -5), (json.dumps(dict(model, m=[1, 2])), -5),
              (json.dumps(model) + " trailing", -1),
              (json.dumps(dict(model, repair_half_time=-1.0)), -5),
+             (json.dumps(dict(model, oer_max=0.5)), -5), (json.dumps(dict(model, oer_k=0.0)), -5),
+             (json.dumps(dict(model, oer_max=3.0, ghost=[0.0, 1.0, 0.0])), -5),
+             (json.dumps(dict(model, oer_max=3.0, oer_k=0.1)), 0),
              (json.dumps(dict(model, repair_half_time=float("inf"))), -1)]
     for text, rc in cases:
         bad.write_text(text)
@@ -311,6 +314,13 @@ def test_params_from_json_reads_the_model_file(gga, tmp_path):
     bad.write_text(json.dumps(dict(model, repair_half_time=2.5)))
     assert gga.LIB.gga_params_from_json(str(bad).encode(), ctypes.byref(p)) == 0 and p.repair_half_time == 2.5
     assert bytes(p) == bytes(gga.make_params(dict(model, repair_half_time=2.5)))
+    # the oxygen effect: off (1, 0.05) when absent, read when present
+    bad.write_text(json.dumps({k: v for k, v in model.items() if k not in ("oer_max", "oer_k")}))
+    assert gga.LIB.gga_params_from_json(str(bad).encode(), ctypes.byref(p)) == 0
+    assert (p.oer_max, p.oer_k) == (1.0, 0.05)
+    bad.write_text(json.dumps(dict(model, oer_max=2.5, oer_k=0.02)))
+    assert gga.LIB.gga_params_from_json(str(bad).encode(), ctypes.byref(p)) == 0
+    assert bytes(p) == bytes(gga.make_params(dict(model, oer_max=2.5, oer_k=0.02)))
     assert gga.LIB.gga_params_from_json(b"/nonexistent/model.json", ctypes.byref(p)) == -1
     p.struct_size = 4
     assert gga.LIB.gga_params_from_json(path.encode(), ctypes.byref(p)) == -2

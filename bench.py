@@ -210,7 +210,8 @@ def ga_bench(gga, workloads, md, args):
 def slots_bench(gga, workloads, md, args):
     """The paper's GA on its own genome: a generation of 40 protocols, each
     simulated 80 times (128 x 128, 5-day treatment window of 120 hourly
-    slots plus 5 days of regrowth = 240 h), minimal interval 6 h, single doses
+    slots, or the paper's 240 slots of 30 minutes with --slot-half-hour, plus
+    5 days of regrowth = 240 h), minimal interval 6 h, single doses
     up to 4.5 Gy and a 10 Gy total in 0.25 Gy quanta, tournament k = 4,
     two-point crossover 0.8, swap, split and dose-time mutations 0.1 each, 4
     elites, 50 generations.  Each generation decodes the genomes, simulates
@@ -218,13 +219,15 @@ def slots_bench(gga, workloads, md, args):
     replayed hipGraphs (and, for comparison, as a host-driven loop)."""
     import torch
     N, R, G, K = args.slot_population, args.slot_replicas, args.slot_generations, 20
-    L, H, S = 128, 240, 120
-    cfg = gga.make_cfg(L, H, R, seed=3, substeps=10, dose_cap=10.0)
-    sc = gga.make_slots(S=S, g_min=6, dmax_q=18, cap_q=40, quantum=0.25)
+    half = args.slot_half_hour                     # the paper's 30-minute slots: 240 over the window
+    L, H, S, g_min = 128, 240, (240 if half else 120), (12 if half else 6)
+    cfg = gga.make_cfg(L, H, R, seed=3, substeps=10, dose_cap=10.0, half_hour=half)
+    sc = gga.make_slots(S=S, g_min=g_min, dmax_q=18, cap_q=40, quantum=0.25)
     ga_cfg = gga.make_ga(n_elite=max(1, N // 10), tournament_k=4, p_cross=0.8, p_mut=0.1, seed=2,
                          crossover="two_point", mutation=())
     params = gga.make_params(md)
-    alpha = gga.make_alphabet(0.25, list(range(1, 19)), [6, 12, 18, 24, 36, 48], 2, 10, 10.0)
+    alpha = gga.make_alphabet(0.25, list(range(1, 19)), [x * (2 if half else 1) for x in (6, 12, 18, 24, 36, 48)],
+                              2, 10, 10.0)
     d0, g0, n0 = gga.population_random(alpha, N, K, seed=4)
     pop0 = gga.slots_encode(sc, d0, g0, n0)
     torch.cuda.synchronize()
@@ -243,15 +246,16 @@ def slots_bench(gga, workloads, md, args):
                      "generation_of_best": hit, "final_best_fitness": final,
                      "best_first_generation": float(h[0, 0]), "mean_last_generation": float(h[-1, 1]),
                      "best_protocol": {"dose_gy": [float(x) for x in bd[best_g].cpu().numpy()[:nb]],
-                                       "delay_h": [int(x) for x in bg[best_g].cpu().numpy()[:nb]]}}
+                                       "delay_h": [int(x) / (2 if half else 1) for x in bg[best_g].cpu().numpy()[:nb]]}}
     inst = N * R
     b = out["batched"]
     return {
         "metric": "slot-genome GA seconds per generation (40 protocols x 80 simulations, hipGraph replay)",
         "value": b["s_per_generation"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"slots-{N}x{R}-{L}x{L}-{H // 24}d", "population": N, "replicas": R,
-                   "generations": G, "slots": S, "min_interval_h": 6, "dmax_gy": 4.5, "cap_gy": 10.0,
+        "config": {"workload": f"slots-{N}x{R}-{L}x{L}-{H // 24}d" + ("-30min" if half else ""), "population": N,
+                   "replicas": R, "generations": G, "slots": S, "slot_minutes": 30 if half else 60,
+                   "min_interval_h": 6, "dmax_gy": 4.5, "cap_gy": 10.0,
                    "quantum_gy": 0.25, "selection": "tournament", "tournament_k": 4, "crossover": "two_point",
                    "p_cross": 0.8, "mutations": ["swap", "split", "time"], "p_mut": 0.1,
                    "elites": max(1, N // 10)},
@@ -535,6 +539,8 @@ def main():
     ap.add_argument("--slot-population", type=int, default=40, help="slots workload: protocols per generation")
     ap.add_argument("--slot-replicas", type=int, default=80, help="slots workload: simulations per protocol")
     ap.add_argument("--slot-generations", type=int, default=50, help="slots workload: generations")
+    ap.add_argument("--slot-half-hour", action="store_true",
+                    help="slots workload: the paper's 30-minute slots (240 over the 5-day window)")
     ap.add_argument("--candidates", type=int, default=5000, help="surrogate workload: candidates per generation")
     ap.add_argument("--train-pairs", type=int, default=200000, help="surrogate workload: training pairs")
     ap.add_argument("--epochs", type=int, default=10, help="surrogate workload: training epochs")

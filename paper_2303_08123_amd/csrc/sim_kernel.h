@@ -224,6 +224,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     __shared__ uint32_t s_oer_thr[OER ? 4 : 1][OER ? GGA_OER_BINS : 1];
     __shared__ int s_nev, s_valid, s_evj[2];
     __shared__ int s_count[2];
+    __shared__ float s_react[4];               // reaction term per cell state
     __shared__ CellConst s_k;                  // cell-update constants, read where used
 
     const int tid = threadIdx.x;
@@ -395,9 +396,9 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             }
     }
 
-    // Per-field constants (field units, see to_field_units): the update, the
+    // Per-field constants (field units, see to_field_units): the update and the
     // lower clamp of O and G (c >= 0 reads c^ >= -g / rho, rho_O = 1 and
-    // rho_G > 0), and the one reaction rate kappa'_O.
+    // rho_G > 0); the one reaction rate kappa'_O enters through s_react.
     float lam[3], cen[3], lo[2];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
@@ -406,8 +407,9 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     }
 #pragma unroll
     for (int f = 0; f < 2; ++f) lo[f] = to_field_units(P, f, 0.0);
-    const float kapO = -P.kappa[0];
-    const float actv[4] = {P.activity[0], P.activity[1], P.activity[2], P.activity[3]};
+    // reaction term per cell state, -kappa'_O a[state], looked up in LDS by
+    // each site's state (one LDS read instead of a chain of selects)
+    if (tid < 4) s_react[tid] = -P.kappa[0] * P.activity[tid];
 
     int ev = 0;
     int count = 0;
@@ -615,7 +617,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) Ro[i][c] = kapO * actv[cellp[i * L + c] & 3];
+                for (int c = 0; c < CPL; ++c) Ro[i][c] = s_react[cellp[i * L + c] & 3];
             // (3) the sub-steps up to a fraction at the half hour, or to the end of the hour
             const int stop = (half == 0 && ev < nev && s_ev_step[ev] == rel + 1) ? a.substeps / 2 : a.substeps;
             for (; s + 2 <= stop; s += 2) {

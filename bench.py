@@ -101,13 +101,13 @@ def _oracle_instance(args):
     return int(traj[-1]), time.perf_counter() - t0
 
 
-def cpu_baseline(md, wl, dose, gap, nfrac, n_protocols=2):
+def cpu_baseline(md, wl, dose, gap, nfrac, n_protocols=4):
     """The oracle on the first n_protocols protocols x R replicas, one instance
-    per worker process."""
+    per worker process (at most 16 workers: one GPU's share of the host)."""
     R = wl["R"]
     jobs = [(md, wl["L"], wl["horizon"], wl["substeps"], dose[p], gap[p], int(nfrac[p]), p, r, wl["seed"])
             for p in range(n_protocols) for r in range(R)]
-    workers = min(len(jobs), os.cpu_count() or 1)
+    workers = min(len(jobs), os.cpu_count() or 1, 16)
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(workers) as pool:
         res = pool.map(_oracle_instance, jobs)
@@ -662,7 +662,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline(md, wl, dose, gap, nfrac, n_protocols=min(2, P))
+        result["cpu_baseline"] = cpu_baseline(md, wl, dose, gap, nfrac, n_protocols=min(4, P))
     print(json.dumps(result), flush=True)
 
 

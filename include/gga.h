@@ -414,9 +414,11 @@ size_t gga_slots_workspace_bytes(int32_t N, int32_t R, int32_t K);
  * NULL or both [g0 + n_gen][K] device arrays), and breeds the next population
  * as gga_slots_breed.  use_graph as gga_ga_run; gen_ms_h as gga_ga_run.
  *   pop_a_d[N][S], pop_b_d[N][S] (device), hist_d[g0 + n_gen][2] (device)
- * Requires K >= ceil(S / g_min) (every guarded dose is simulated).
+ * Requires K >= ceil(S / g_min) (every guarded dose is simulated) and
+ * cap_q x quantum <= cfg->dose_cap + 1e-6 Gy (guarded genomes are valid
+ * protocols).  With cfg->flags = GGA_SIM_HALF_HOUR the slots are 30 minutes.
  * Synchronous.  Errors: as gga_simulate and gga_slots_breed; GGA_E_ARG for a
- * small workspace.
+ * small workspace or the requirements above.
  */
 int gga_slots_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_cfg* ga,
                   const gga_slot_cfg* sc, uint8_t* pop_a_d, uint8_t* pop_b_d, int32_t N, int32_t K,

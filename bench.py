@@ -387,7 +387,7 @@ def surrogate_bench(gga, workloads, md, args):
         t_off += wall
         log(f"sga: generations {g0}..{g0 + n - 1} in {wall:.1f} s")
     sga_t, sga_total = np.array(times), t_off
-    # 4. judge both with fresh replicas
+    # 4. evaluate both with fresh replicas
     RE = 64
     ga_re = _reevaluate(gga, params, wl, ga_arc[0], ga_arc[1], RE, seed=777)
     sga_re = _reevaluate(gga, params, wl, run.archive[0], run.archive[1], RE, seed=778)

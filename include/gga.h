@@ -528,7 +528,7 @@ int gga_sga_init(const gga_params* params, const gga_sim_cfg* cfg, const gga_sga
  * initial population being population 0), and keep the best N of the N + S
  * evaluated protocols, sorted, in rows 0 .. N-1.  With refine_steps > 0 the
  * surrogate first takes that many Adam steps (on the net's own step count) on
- * the N + S simulated pairs: the simulation judges the surrogate's error and
+ * the N + S simulated pairs: the simulation checks the surrogate's error and
  * corrects it where the search is.  hist_d[g] = (best, mean) fitness of the
  * kept population.  With screen = 0 the S candidates are
  * picked at random instead (the same loop without the surrogate).

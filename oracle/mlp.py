@@ -3,7 +3,7 @@
 Test infrastructure: part of the CPU oracle (see oracle/__init__.py).
 
 The surrogate maps an encoded protocol to its predicted (normalised) fitness;
-it only pre-screens GA offspring, the full simulation stays the judge.  It is
+it only pre-screens GA offspring, the full simulation keeps the final word.  It is
 not in the paper; its shape is fixed here: input 128 features (40 fractions x
 (dose / 5 Gy, delay / 60 h, present), zero-padded from 120), three hidden
 layers of 512 with GELU(x) = x * Phi(x) (Phi the standard normal CDF), one

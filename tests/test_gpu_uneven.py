@@ -180,6 +180,41 @@ def test_uneven_batch_equals_uniform_runs(gga, model_dict):
     assert live[3, 0] == 113 and live[9, 1] == 113        # horizon 0: the seed disc
 
 
+def test_uneven_batch_with_every_option_equals_uniform_runs(gga, model_dict):
+    """With delays in half-hours, incomplete repair and the oxygen effect all
+    on, a mixed batch (resident and slab forms) still equals the same
+    protocols run per (side, horizon)."""
+    md = high_uptake(model_dict)
+    md["repair_half_time"], md["oer_max"], md["oer_k"] = 2.0, 3.0, 0.1
+    prm = Params.from_dict(md)
+    P, K, R, seed = 8, 6, 2, 23
+    dose, gap, nfrac = workloads.random_protocols(P, K, seed=5, kmin=2)
+    gap[:, 1:] = np.maximum(gap[:, 1:] // 3, 1)            # half-hour delays, fractions close together
+    gap[:, 0] = 2 * (gap[:, 0] % 10) + 1                   # the first fraction at an odd half-hour before 10 h
+    lattice = np.array([64, 128, 256, 64, 256, 128, 256, 64], np.int32)
+    horizon = np.array([30, 25, 20, 30, 20, 25, 12, 0], np.int32)
+    cfg = gga.make_cfg(64, 0, R, seed=seed, dose_cap=100.0, half_hour=True)
+    dd = _dev(dose, gap, nfrac)
+    live = gga.simulate_uneven(md, cfg, *dd, lattice, horizon)[0].cpu().numpy()
+    ref = np.zeros((P, R), np.int64)
+    for L, H in sorted(set(zip(lattice.tolist(), horizon.tolist()))):
+        rows = np.nonzero((lattice == L) & (horizon == H))[0]
+        c = gga.make_cfg(L, H, R, seed=seed, dose_cap=100.0, half_hour=True)
+        if L < 256:
+            ref[rows] = gga.simulate(md, c, *dd)[0].cpu().numpy()[rows]
+        elif H > 0:
+            f0, c0 = _oracle_init(prm, L, P, R, seed)
+            f_d, c_d = _dev(f0, c0.view(np.int16))
+            ref[rows] = gga.state_run_variant(md, c, 6, *dd, 0, H, f_d, c_d).cpu().numpy()[rows]
+        else:
+            ref[rows] = sim.live_count(sim.init_state(prm, L, 0, 0, seed)[1])
+    assert np.array_equal(live, ref)
+    # the options change the outcome of the irradiated protocols
+    plain = gga.simulate_uneven(high_uptake(model_dict), gga.make_cfg(64, 0, R, seed=seed, dose_cap=100.0,
+                                                                      half_hour=True), *dd, lattice, horizon)[0]
+    assert not np.array_equal(plain.cpu().numpy(), live)
+
+
 def test_slab_variants_and_choice_do_not_change_results(gga, model_dict):
     P, K, R = 6, 5, 2
     dose, gap, nfrac = workloads.random_protocols(P, K, seed=9, kmin=1)

@@ -21,7 +21,8 @@
  *   - identical inputs give bit-identical outputs on every run.
  *
  * Cell words (uint16): bits 0-1 state (0 EMPTY, 1 PROLIF, 2 QUIESC, 3 DEAD),
- * bits 2-9 age in hours (saturating at 255); EMPTY sites hold 0.
+ * bits 2-9 age in hours (saturating at 255), bit 14 the mark of a lethally hit
+ * cell awaiting mitotic death (gga_params.mitotic_death); EMPTY sites hold 0.
  * Field state (float32): [instance][3][L][L], planes oxygen, glucose, acidity,
  * in normalised units.  Instance i = p * R + r (protocol p, replica r).
  */
@@ -89,6 +90,11 @@ typedef struct gga_params {
                                (GGA_OER_BINS bins of O / ghost[0] over [0, 1], the
                                last also above 1; ghost[0] > 0 required)               */
     double oer_k;           /* oxygen level of half the effect, same units as O; > 0  */
+    int32_t mitotic_death;  /* 0: a lethally hit cell dies at once.  1: it is marked (bit
+                               14 of its cell word) and dies when it next becomes ready
+                               to divide (age >= T_min and its draw below P_div), free
+                               neighbours or not; marked cells never divide          */
+    int32_t reserved;       /* 0                                                      */
 } gga_params;
 #define GGA_OER_BINS 16
 
@@ -98,8 +104,8 @@ typedef struct gga_params {
  * activity[4], theta_O_quiesce, theta_G_quiesce, theta_O_death,
  * theta_G_death, theta_H_death, T_min, T_lys, A0, seed_radius (integers),
  * class_age[2] (integers), P_div, alpha, beta, m[4], and optionally
- * repair_half_time (default 0), oer_max (default 1) and oer_k (default
- * 0.05) (the package's
+ * repair_half_time (default 0), oer_max (default 1), oer_k (default
+ * 0.05) and mitotic_death (default 0) (the package's
  * data/model_default.json).  Other keys are ignored.  out->struct_size must
  * be sizeof(gga_params) (GGA_E_ABI otherwise); *out is written only on
  * success.  Host only, no device work.  Errors: GGA_E_ARG (null pointer,

@@ -17,6 +17,7 @@ import numpy as np
 EMPTY, PROLIF, QUIESC, DEAD = 0, 1, 2, 3
 AGE_MAX = 255
 OER_BINS = 16      # oxygen levels of the oxygen effect: bins of O / O_boundary over [0, 1]
+DOOM = 1 << 14     # cell-word bit of a lethally hit cell awaiting mitotic death
 
 
 def _f32(x):
@@ -47,6 +48,7 @@ class Params:
     repair_half_time: float = 0.0   # hours; 0: sublethal damage repaired between fractions
     oer_max: float = 1.0            # oxygen enhancement ratio at full oxygenation; 1: no oxygen effect
     oer_k: float = 0.05             # oxygen level of half the effect, in the oxygen field's units
+    mitotic_death: int = 0          # 1: a lethally hit cell dies at its next division instead of at once
 
     @classmethod
     def from_dict(cls, d):
@@ -64,6 +66,7 @@ class Params:
             m=tuple(float(v) for v in d["m"]),
             repair_half_time=float(d.get("repair_half_time", 0.0)),
             oer_max=float(d.get("oer_max", 1.0)), oer_k=float(d.get("oer_k", 0.05)),
+            mitotic_death=int(d.get("mitotic_death", 0)),
         )
 
     @property

@@ -30,11 +30,12 @@ Per instance (protocol p, replica r) and step n = 0 .. N-1 (one model hour):
   5. the live count (PROLIF + QUIESC) is recorded.
 
 Cell words: bits 0-1 state (EMPTY, PROLIF, QUIESC, DEAD), bits 2-9 age in
-hours (saturating at 255).
+hours (saturating at 255), bit 14 the mark of a lethally hit cell awaiting
+mitotic death (params.mitotic_death).
 """
 import numpy as np
 
-from .model import AGE_MAX, DEAD, EMPTY, PROLIF, QUIESC, Params
+from .model import AGE_MAX, DEAD, DOOM, EMPTY, PROLIF, QUIESC, Params
 from .philox import INIT_STEP, site_words
 from .protocol import events, oxygen_bin, validate
 
@@ -44,8 +45,13 @@ DX = (0, 1, 0, -1)
 NONE_KEY = 0xFFFFFFFF
 
 
-def pack(state, age):
-    return (np.asarray(state, np.int64) & 3) | (np.asarray(age, np.int64) << 2)
+def pack(state, age, doom=0):
+    return (np.asarray(state, np.int64) & 3) | (np.asarray(age, np.int64) << 2) | (np.asarray(doom, np.int64) * DOOM)
+
+
+def doomed(cells):
+    """1 where a lethally hit cell awaits mitotic death (bit 14 of the word)."""
+    return (np.asarray(cells, np.int64) >> 14) & 1
 
 
 def unpack(cells):
@@ -103,7 +109,10 @@ def irradiate(cells, thresholds, draw, params: Params, fields=None):
         thr = np.asarray(thresholds, dtype=np.int64)[cls]
     killed = w1 >= thr
     out = cells.copy()
-    out[ys[killed], xs[killed]] = pack(DEAD, 0)
+    if params.mitotic_death:        # the cell lives on, marked, until it next divides
+        out[ys[killed], xs[killed]] |= DOOM
+    else:
+        out[ys[killed], xs[killed]] = pack(DEAD, 0)
     return out
 
 
@@ -153,9 +162,14 @@ def cell_update(cells, fields, draw, params: Params):
         ((w2 >> 3) << 2) | d, d its own direction as seen from the target.
       Every EMPTY site with proposers takes the smallest key: the daughter there
         and the winning parent both get age 0.  Every other PROLIF cell ages by 1.
+      With mitotic death, a marked (lethally hit) PROLIF cell with age >= T_min
+        draws its block whatever its neighbours; when ready (w3 < T_div) it
+        dies (DEAD, age 0) instead of dividing.  Live cells keep the mark;
+        dead ones drop it.
     """
     H, W = cells.shape
     state, age = unpack(cells)
+    doom = doomed(cells)
     O, G, Hf = fields
     new_state, new_age = state.copy(), age.copy()
     new_age[state == EMPTY] = 0        # an EMPTY site's word is always 0
@@ -177,8 +191,18 @@ def cell_update(cells, fields, draw, params: Params):
     new_state[cycling] = PROLIF
     new_age[cycling] = older[cycling]
 
+    new_doom = np.where(live & ~necrotic, doom, 0)
     free = free_neighbours(state == EMPTY)
     m = free.sum(axis=0)
+    if params.mitotic_death:
+        marked = cycling & (doom == 1) & (age >= params.T_min)
+        my, mx = np.nonzero(marked)
+        if len(my):
+            dies = draw(my * W + mx)[3].astype(np.uint64) < np.uint64(params.T_div)
+            new_state[my[dies], mx[dies]] = DEAD
+            new_age[my[dies], mx[dies]] = 0
+            new_doom[my[dies], mx[dies]] = 0
+        cycling = cycling & (doom == 0)
     cand = cycling & (age >= params.T_min) & (m >= 1)
     ys, xs = np.nonzero(cand)
     if len(ys):
@@ -202,7 +226,7 @@ def cell_update(cells, fields, draw, params: Params):
         new_state[born] = PROLIF
         new_age[born] = 0
         new_age[ys[won], xs[won]] = 0
-    return pack(new_state, new_age)
+    return pack(new_state, new_age, new_doom)
 
 
 MID_STEP = 0x80000000   # step word bit of the draws of a fraction at the half hour

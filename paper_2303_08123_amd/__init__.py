@@ -38,6 +38,7 @@ class Params(ctypes.Structure):
         ("P_div", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
         ("m", ctypes.c_double * 4), ("repair_half_time", ctypes.c_double),
         ("oer_max", ctypes.c_double), ("oer_k", ctypes.c_double),
+        ("mitotic_death", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -224,6 +225,7 @@ def make_params(d):
     p.m[:] = [float(v) for v in d["m"]]
     p.repair_half_time = float(d.get("repair_half_time", 0.0))
     p.oer_max, p.oer_k = float(d.get("oer_max", 1.0)), float(d.get("oer_k", 0.05))
+    p.mitotic_death = int(d.get("mitotic_death", 0))
     return p
 
 

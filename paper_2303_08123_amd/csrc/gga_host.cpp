@@ -47,6 +47,7 @@ int check_params(const gga_params* p) {
     if (!(std::isfinite(p->oer_max) && p->oer_max >= 1.0 && std::isfinite(p->oer_k) && p->oer_k > 0.0))
         return GGA_E_PARAM;
     if (p->oer_max > 1.0 && !(p->ghost[0] > 0.0f)) return GGA_E_PARAM;   // oxygen bins are fractions of ghost[0]
+    if ((p->mitotic_death != 0 && p->mitotic_death != 1) || p->reserved != 0) return GGA_E_PARAM;
     return GGA_OK;
 }
 

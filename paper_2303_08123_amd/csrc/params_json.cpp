@@ -1,8 +1,9 @@
 // gga_params_from_json: the model constants from a flat JSON object whose
 // values are numbers or arrays of numbers (the format of the package's
 // data/model_default.json).  Every field of gga_params must be present except
-// repair_half_time (default 0), oer_max (default 1, no oxygen effect) and
-// oer_k (default 0.05); keys the struct does not have are ignored.
+// repair_half_time (default 0), oer_max (default 1, no oxygen effect), oer_k
+// (default 0.05) and mitotic_death (default 0); keys the struct does not have
+// are ignored.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -162,6 +163,7 @@ extern "C" int gga_params_from_json(const char* path, gga_params* out) {
     p.oer_k = 0.05;
     if (kv.count("oer_max")) doubles("oer_max", &p.oer_max, 1);
     if (kv.count("oer_k")) doubles("oer_k", &p.oer_k, 1);
+    if (kv.count("mitotic_death")) ints("mitotic_death", &p.mitotic_death, 1);   // optional, default 0
     if (!ok) return GGA_E_PARAM;
     const int rc = gga::check_params_host(&p);
     if (rc != GGA_OK) return rc;

@@ -35,7 +35,7 @@ template <int CPL, int RPT, int NW>
 hipError_t launch_sim(const SimArgs& a, int n_blocks, hipStream_t stream) {
     using G = Geo<CPL, RPT, NW>;
     static_assert(!G::SLAB, "slab variants are built in sim_slab.hip");
-    if (a.prm.oer_max > 1.0)
+    if (a.prm.oer_max > 1.0 || a.prm.mitotic_death)   // the extended radiobiology instantiation
         hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, true>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
     else
         hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, false>), dim3(n_blocks), dim3(G::NT), 0, stream, a);

@@ -55,6 +55,7 @@ namespace {
 constexpr uint32_t NONE_KEY = 0xFFFFFFFFu;
 constexpr uint32_t INIT_STEP = 0xFFFFFFFFu;
 constexpr int EMPTY = 0, PROLIF = 1, QUIESC = 2, DEAD = 3;
+constexpr uint32_t DOOM_BIT = 1u << 14;    // cell word: lethally hit, awaiting mitotic death
 
 // 32-bit linear-quadratic survival threshold, evaluated in float64 exactly as
 // written: x = m d, y = m D, S = exp(-alpha x - beta x (x + 2 y)),
@@ -202,9 +203,10 @@ struct Geo {
     static constexpr uint32_t COL_LAST = col_bits(CPL - 1);
 };
 
-// OER: the oxygen effect on radiosensitivity (gga_params.oer_max > 1), a
-// separate instantiation so that runs without it keep their register budget.
-template <int CPL, int RPT, int NW, bool OER>
+// EXT: the extended radiobiology (the oxygen effect on radiosensitivity,
+// gga_params.oer_max > 1, and mitotic death, gga_params.mitotic_death), a
+// separate instantiation so that runs without them keep their register budget.
+template <int CPL, int RPT, int NW, bool EXT>
 __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     using G = Geo<CPL, RPT, NW>;
     constexpr int L = G::L;
@@ -221,7 +223,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     __shared__ double s_ev_prior[GGA_KMAX];    // unrepaired dose of the earlier fractions (incomplete repair)
     __shared__ uint32_t s_ev_thr[GGA_KMAX][4];
     // the current fraction's thresholds per class and oxygen bin (oxygen effect only)
-    __shared__ uint32_t s_oer_thr[OER ? 4 : 1][OER ? GGA_OER_BINS : 1];
+    __shared__ uint32_t s_oer_thr[EXT ? 4 : 1][EXT ? GGA_OER_BINS : 1];
     __shared__ int s_nev, s_valid, s_evj[2];
     __shared__ int s_count[2];
     __shared__ float s_react[4];               // reaction term per cell state
@@ -562,7 +564,8 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             if (ev < nev && s_ev_step[ev] == rel + half) {
                 // with the oxygen effect: this fraction's thresholds per class
                 // and oxygen bin, and each site's bin from its current O
-                if constexpr (OER) {
+                const bool oer = EXT && P.oer_max > 1.0, mitotic = EXT && P.mitotic_death != 0;
+                if (oer) {
                     __syncthreads();                      // the previous fraction's table is read
                     if (tid < 4 * GGA_OER_BINS) {
                         const double f = oxygen_modification(P, tid % GGA_OER_BINS);
@@ -586,7 +589,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                             live_mask |= 1u << (i * CPL + c);
                             // the site's oxygen bin rides in the word's free bits 10-13
                             // until this fraction is done
-                            if constexpr (OER) cellp[i * L + c] = (uint16_t)(w | ((uint32_t)oxygen_bin(F[0][i][c], P) << 10));
+                            if (oer) cellp[i * L + c] = (uint16_t)(w | ((uint32_t)oxygen_bin(F[0][i][c], P) << 10));
                         }
                     }
                 while (live_mask) {
@@ -594,20 +597,21 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                     live_mask &= live_mask - 1;
                     const int site = own + (idx / CPL) * L + idx % CPL;
                     const uint32_t w = s_cell[site];
-                    const int st = w & 3, age = OER ? (w >> 2) & 255 : w >> 2;
+                    const int st = w & 3, age = EXT ? (w >> 2) & 255 : w >> 2;
                     uint32_t thr = (st == QUIESC) ? t3 : (age < ca0 ? t0 : (age < ca1 ? t1 : t2));
-                    if constexpr (OER) {
+                    if (oer) {
                         const int cls = (st == QUIESC) ? 3 : (age < ca0 ? 0 : (age < ca1 ? 1 : 2));
                         thr = s_oer_thr[cls][(w >> 10) & 15u];
                     }
                     const Block4 b = philox10(site + gofs, (uint32_t)n | (half << 31), r, p, seed_lo, seed_hi);
-                    if (b.w1 >= thr) s_cell[site] = DEAD;
+                    // mitotic death: the cell lives on, marked, until it next divides
+                    if (b.w1 >= thr) s_cell[site] = mitotic ? (uint16_t)(w | DOOM_BIT) : (uint16_t)DEAD;
                 }
-                if constexpr (OER) {
+                if (oer) {
 #pragma unroll
                     for (int i = 0; i < RPT; ++i)
 #pragma unroll
-                        for (int c = 0; c < CPL; ++c) cellp[i * L + c] = (uint16_t)(cellp[i * L + c] & 0x3FFu);
+                        for (int c = 0; c < CPL; ++c) cellp[i * L + c] = (uint16_t)(cellp[i * L + c] & ~0x3C00u);
                 }
                 ++ev;
             }
@@ -672,7 +676,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         for (int k = tid; k < RR * L / 32; k += G::NT) s_claim[k] = 0u;
         __syncthreads();   // boundary rows read, claims reset: own rows may now be rewritten
         // Per site: lysis and environment transitions, written back row by row.
-        uint32_t empty_m = ALL_SITES, cyc_m = 0, old_m = 0, alive_m = 0;
+        uint32_t empty_m = ALL_SITES, cyc_m = 0, old_m = 0, alive_m = 0, doom_m = 0;
         if (__builtin_amdgcn_ballot_w64(occupied != 0u) != 0) {   // wave-uniform; else all EMPTY
             // Environment flags of the thread's sites, from the fields after the
             // sub-steps (x < th  <=>  sign bit of x - th: the difference of two
@@ -702,12 +706,14 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
                     const int idx = i * CPL + c;
-                    const uint32_t st = w[c] & 3u, age = w[c] >> 2;
+                    const uint32_t st = w[c] & 3u, age = EXT ? (w[c] >> 2) & 255u : w[c] >> 2;
                     const uint32_t older = age < 255u ? age + 1u : 255u;
                     const uint32_t nec = (nec_m >> idx) & 1u, starv = (starv_m >> idx) & 1u;
                     const uint32_t live = (0x6u >> st) & 1u;
                     // branch-free selects: x ^ ((y ^ x) & -flag) picks y when flag is 1
-                    const uint32_t kept = (uint32_t)QUIESC | (w[c] & ~3u), grown = (uint32_t)PROLIF | (older << 2);
+                    // a live cell keeps its mitotic-death mark (EXT); dead words carry none
+                    const uint32_t kept = (uint32_t)QUIESC | (w[c] & ~3u);
+                    const uint32_t grown = (uint32_t)PROLIF | (older << 2) | (EXT ? (w[c] & DOOM_BIT) : 0u);
                     uint32_t nl = grown ^ ((kept ^ grown) & (0u - starv));          // live outcome
                     nl ^= (nl ^ (uint32_t)DEAD) & (0u - nec);
                     const uint32_t decay = (uint32_t)((st == DEAD) & ((int)older < T_lys));
@@ -717,6 +723,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                     cyc_m |= (live & ~(nec | starv) & 1u) << idx;
                     old_m |= (uint32_t)((int)age >= T_min) << idx;
                     alive_m |= (live & ~nec & 1u) << idx;
+                    if constexpr (EXT) doom_m |= ((w[c] >> 14) & 1u) << idx;
                     asm volatile("" : "+v"(empty_m), "+v"(cyc_m), "+v"(old_m), "+v"(alive_m));
                 }
                 store_words<CPL>(cellp + i * L, w);
@@ -728,7 +735,22 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         const uint32_t from_left = lane_from_left_u32(empty_m), from_right = lane_from_right_u32(empty_m);
         const uint32_t fW = (CPL == 1) ? from_left : (((empty_m << 1) & ~C0 & ALL_SITES) | ((from_left >> (CPL - 1)) & C0));
         const uint32_t fE = (CPL == 1) ? from_right : (((empty_m >> 1) & ~CL) | ((from_right << (CPL - 1)) & CL));
-        const uint32_t cand = cyc_m & old_m & (fN | fE | fS | fW);
+        // marked cells never divide: they draw their block whatever their
+        // neighbours and die when ready (mitotic death)
+        const uint32_t cand = cyc_m & old_m & ~doom_m & (fN | fE | fS | fW);
+        if constexpr (EXT) {
+            uint32_t m = cyc_m & old_m & doom_m;
+            while (m) {
+                const int idx = __builtin_ctz(m);
+                m &= m - 1;
+                const int site = own + (idx / CPL) * L + idx % CPL;
+                const Block4 b = philox10(site + gofs, n, r, p, seed_lo, seed_hi);
+                if (b.w3 < s_k.T_div) {
+                    cellp[(idx / CPL) * L + idx % CPL] = (uint16_t)DEAD;
+                    alive_m &= ~(1u << idx);
+                }
+            }
+        }
         uint32_t prop_m = 0;
         uint64_t dirs = 0;
         {

@@ -300,6 +300,7 @@ def test_params_from_json_reads_the_model_file(gga, tmp_path):
              (json.dumps(dict(model, oer_max=0.5)), -5), (json.dumps(dict(model, oer_k=0.0)), -5),
              (json.dumps(dict(model, oer_max=3.0, ghost=[0.0, 1.0, 0.0])), -5),
              (json.dumps(dict(model, oer_max=3.0, oer_k=0.1)), 0),
+             (json.dumps(dict(model, mitotic_death=2)), -5), (json.dumps(dict(model, mitotic_death=1)), 0),
              (json.dumps(dict(model, repair_half_time=float("inf"))), -1)]
     for text, rc in cases:
         bad.write_text(text)

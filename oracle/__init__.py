@@ -10,6 +10,6 @@ Modules: philox (Philox4x32-10), model (constants), protocol (validation,
 events, LQ thresholds, counting and sampling of protocols), sim (the lattice
 automaton), ga (GA operators), ga_slots (the GA over the time-slot genome),
 mlp (float64 surrogate network), sga (one generation of the surrogate-screened
-GA with a random screen).
+GA with a random screen), quasi3d (the variant with several cells per site).
 """
-from . import ga, ga_slots, mlp, model, philox, protocol, sga, sim  # noqa: F401
+from . import ga, ga_slots, mlp, model, philox, protocol, quasi3d, sga, sim  # noqa: F401

@@ -526,12 +526,96 @@ def uneven_bench(gga, workloads, md, args):
     }
 
 
+def q3_bytes_per_site_step(C, S):
+    """Algorithmic HBM bytes of one quasi-3D step per site: each FTCS sub-step
+    reads three fields and the reaction term and writes three fields (28 B);
+    the cell update reads the C words, three fields and the free count and
+    writes C words and C 4-byte proposals (13 + 8 C); the resolution reads the
+    words before and after the update and the proposals and writes the words,
+    the reaction term and the free count (5 + 10 C).  Key traffic (8 B per
+    EMPTY slot and proposal) and the steps with a fraction are not counted."""
+    return 28 * S + (13 + 8 * C) + (5 + 10 * C)
+
+
+def q3_cpu_baseline(md, wl, dose, gap, nfrac, n_replicas=2):
+    """The quasi-3D oracle on protocol 0's first n_replicas instances over the
+    whole horizon (one process), scaled to protocols/s at the workload's
+    replica count."""
+    from oracle import protocol as oprotocol, quasi3d
+    from oracle.model import Params
+    prm = Params.from_dict(md)
+    ev = oprotocol.events(dose[0], gap[0], nfrac[0], wl["horizon"], prm)
+    t0 = time.perf_counter()
+    for r in range(n_replicas):
+        quasi3d.run_instance(prm, wl["L"], wl["C"], wl["horizon"], wl["substeps"], ev, 0, r, wl["seed"])
+    t = time.perf_counter() - t0
+    per_protocol = t / n_replicas * wl["R"]
+    return {"value": 1.0 / per_protocol, "unit": "protocols/s", "cores": 1, "kind": "oracle",
+            "sample": f"protocol 0 x {n_replicas} replicas of the same workload, whole horizon, {t:.1f} s, "
+                      f"scaled to {wl['R']} replicas"}
+
+
+def q3_bench(gga, workloads, md, args):
+    """The quasi-3D variant: 256 protocols x 4 replicas on 128 x 128 sites with 8
+    cell slots, 20 days; whole gga_simulate_q3 calls timed with events on the
+    stream they run on."""
+    import torch
+    wl = dict(workloads.CONFIG_Q3)
+    P, R, L, C, N, S = wl["P"], wl["R"], wl["L"], wl["C"], wl["horizon"], wl["substeps"]
+    dose, gap, nfrac = workloads.config2_protocols(P, wl["K"], seed=0, cap=wl["dose_cap"])
+    cfg = gga.make_cfg(L, N, R, seed=wl["seed"], substeps=S, dose_cap=wl["dose_cap"])
+    params = gga.make_params(md)
+    dev = torch.device("cuda:0")
+    d_d, g_d, n_d = (torch.from_numpy(a).to(dev) for a in (dose, gap, nfrac))
+    ws = gga.q3_workspace(cfg, C, P, wl["K"])
+    out = (torch.empty((P, R), dtype=torch.int32, device=dev), torch.empty((P,), dtype=torch.float32, device=dev),
+           None)
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        gga.simulate_q3(params, cfg, C, d_d, g_d, n_d, ws=ws, out=out, stream=stream)
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        gga.simulate_q3(params, cfg, C, d_d, g_d, n_d, ws=ws, out=out, stream=stream)
+        ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        log(f"step {i + 1}/{args.steps} done at {time.perf_counter() - t0:.1f} s")
+    wall = time.perf_counter() - t0
+    call_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1000.0
+    live, fit = out[0].cpu().numpy(), out[1].cpu().numpy()
+    assert np.all(live >= 0) and np.all(np.isfinite(fit))
+    site_steps = float(P * R * L * L * N)
+    s = wall / args.steps
+    achieved = q3_bytes_per_site_step(C, S) * site_steps / call_s
+    result = {
+        "metric": "protocols/sec (quasi-3D batch: 256 protocols x 4 replicas, 128x128 sites x 8 slots, 20 days)",
+        "value": P / s, "unit": "protocols/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * s, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl["name"], "protocols": P, "replicas": R, "lattice": L, "slots": C,
+                   "horizon_h": N, "substeps_per_h": S, "fractions": wl["K"], "dose_cap_gy": wl["dose_cap"]},
+        "site_steps_per_s": site_steps / s,
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_BYTES, "traffic": None, "kernel": "whole step chain",
+                     "bytes_per_site_step": q3_bytes_per_site_step(C, S), "call_ms": call_s * 1000.0},
+        "mean_live_cells": float(live.mean()),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the quasi-3D oracle on a bounded sample")
+        result["cpu_baseline"] = q3_cpu_baseline(md, wl, dose, gap, nfrac)
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "ga", "surrogate", "uneven", "mlp", "slots"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "ga", "surrogate", "uneven", "mlp", "slots", "q3"])
     ap.add_argument("--generations", type=int, default=200, help="GA workload: generations")
     ap.add_argument("--chunk", type=int, default=20, help="GA workload: generations per progress line")
     ap.add_argument("--plain-generations", type=int, default=1,
@@ -585,6 +669,9 @@ def main():
         return
     if args.workload == "uneven":
         print(json.dumps(uneven_bench(gga, workloads, md, args)), flush=True)
+        return
+    if args.workload == "q3":
+        print(json.dumps(q3_bench(gga, workloads, md, args)), flush=True)
         return
     if args.workload == "surrogate":
         print(json.dumps(surrogate_bench(gga, workloads, md, args)), flush=True)

@@ -670,6 +670,67 @@ int gga_autotune(const gga_params* params, const gga_sim_cfg* cfg, const float* 
                  const int32_t* nfrac_d, int32_t P, int32_t K, void* ws_d, size_t ws_bytes, int32_t* live_d,
                  float* fitness_d, float* ms_h, hipStream_t stream);
 
+/*
+ * Quasi-3D variant (the paper's model is quasi-three-dimensional, a site
+ * holding many cells: Introduction, and Materials and Methods on the cells
+ * per site).  Every site holds C cell slots (1 <= C <= GGA_Q3_MAX_SLOTS,
+ * C L^2 <= 2^23, 8 <= L <= 512); the fields stay two-dimensional.  With C = 1
+ * every rule is gga_simulate's.  Rules the paper does not print, fixed here:
+ *   - slot z of site s = y L + x draws the Philox block of site counter
+ *     z L^2 + s (slot 0 draws what the 2D model draws);
+ *   - initial state: slot 0 is the 2D seed disc, the other slots EMPTY;
+ *   - a fraction treats every live cell as the 2D model does (class by its
+ *     age; oxygen bin of its site);
+ *   - a site's activity is the mean over its C slots of activity[state];
+ *   - cell update: every cell as in the 2D model with its site's fields; the
+ *     free places of a cell are the EMPTY slots of its own site and of its four
+ *     von Neumann neighbours, in the order own, N, E, S, W and by slot within a
+ *     site; m counts them, a ready cell proposes the k-th, k = floor(w0 m /
+ *     2^32), with the 64-bit key ((w2 >> 3) << 8) | (d << 5) | z (d = 4 for its
+ *     own site, else its direction seen from the target, N 0, E 1, S 2, W 3),
+ *     and each EMPTY slot takes the smallest key (daughter and winning parent
+ *     get age 0);
+ *   - live counts count PROLIF and QUIESC cells over all slots.
+ * State: fields_d[P*R][3][L][L] (float32, field units as gga_state_init) and
+ * cells_d[P*R][C][L][L] (uint16 words, slot planes).  cfg->flags may hold
+ * GGA_SIM_HALF_HOUR.  Every parameter option of gga_params applies.
+ * Workspace: gga_q3_workspace_bytes(L, C, P, R, K) bytes of device memory,
+ * 16-byte aligned, caller-owned, contents not preserved between calls; calls
+ * sharing a workspace must not overlap.
+ * Errors: GGA_E_ARG (null or misaligned pointer, small workspace, C out of
+ * range, n0 + nsteps > 2^30, P R ceil(L^2 / 256) >= 2^31), GGA_E_ABI,
+ * GGA_E_PARAM, GGA_E_UNSUPPORTED (L, substeps or C L^2 out of range),
+ * GGA_E_HIP.
+ */
+#define GGA_Q3_MAX_SLOTS 32
+size_t gga_q3_workspace_bytes(int32_t L, int32_t C, int32_t P, int32_t R, int32_t K);
+
+/* Initial state of P * cfg->R quasi-3D instances (no workspace). */
+int gga_q3_init(const gga_params* params, const gga_sim_cfg* cfg, int32_t C, int32_t P, float* fields_d,
+                uint16_t* cells_d, hipStream_t stream);
+
+/*
+ * Advance the given quasi-3D states by nsteps steps from step n0, in place.
+ * live_d[P][R] (or NULL) receives the final live counts and traj_d (or NULL)
+ * [P][R][nsteps] the count after every step (with nsteps = 0, live_d gets the
+ * count of the given state).  Invalid protocols leave their states untouched
+ * and get -1 in live_d and traj_d.
+ */
+int gga_q3_run(const gga_params* params, const gga_sim_cfg* cfg, int32_t C, const float* dose_d,
+               const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P, int32_t K, int32_t n0, int32_t nsteps,
+               float* fields_d, uint16_t* cells_d, void* ws_d, size_t ws_bytes, int32_t* live_d, int32_t* traj_d,
+               hipStream_t stream);
+
+/*
+ * gga_simulate for the quasi-3D variant: the initial state, cfg->horizon
+ * steps, live_d[P][R] (-1 for invalid protocols), fitness_d[P] (the mean over
+ * replicas, NaN for invalid protocols) and traj_d[P][R][horizon] or NULL.
+ * The state is held in the workspace.
+ */
+int gga_simulate_q3(const gga_params* params, const gga_sim_cfg* cfg, int32_t C, const float* dose_d,
+                    const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P, int32_t K, void* ws_d, size_t ws_bytes,
+                    int32_t* live_d, float* fitness_d, int32_t* traj_d, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

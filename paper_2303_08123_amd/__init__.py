@@ -151,6 +151,12 @@ def _load():
         "gga_slots_workspace_bytes": ([i32, i32, i32], ctypes.c_size_t),
         "gga_slots_run": ([vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, ctypes.c_size_t, vp, vp, vp, vp,
                            vp], ctypes.c_int),
+        "gga_q3_workspace_bytes": ([i32, i32, i32, i32, i32], ctypes.c_size_t),
+        "gga_q3_init": ([vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
+        "gga_q3_run": ([vp, vp, i32, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp, vp, vp],
+                       ctypes.c_int),
+        "gga_simulate_q3": ([vp, vp, i32, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, vp, vp, vp],
+                            ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -170,7 +176,8 @@ EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
            "gga_set_variant", "gga_uneven_workspace_bytes", "gga_simulate_uneven", "gga_event_table_bytes",
            "gga_state_run_variant", "gga_autotune_workspace_bytes", "gga_autotune", "gga_simulate_library",
            "gga_measure_peaks", "gga_params_from_json", "gga_slots_breed", "gga_slots_decode",
-           "gga_slots_encode", "gga_slots_workspace_bytes", "gga_slots_run")
+           "gga_slots_encode", "gga_slots_workspace_bytes", "gga_slots_run", "gga_q3_workspace_bytes",
+           "gga_q3_init", "gga_q3_run", "gga_simulate_q3")
 
 
 class GGAError(RuntimeError):
@@ -463,6 +470,60 @@ def autotune(params, cfg, dose, gap, nfrac, stream=None):
                          _stream(stream))
     _check(min(v, 0))
     return v, {i: float(t) for i, t in enumerate(ms) if np.isfinite(t)}
+
+
+# ---------------------------------------------------------------- quasi-3D variant
+
+def q3_workspace(cfg, C, P, K, device="cuda"):
+    """Device workspace of the quasi-3D calls for P protocols x cfg.R replicas."""
+    n = LIB.gga_q3_workspace_bytes(cfg.L, int(C), P, cfg.R, K)
+    if n == 0:
+        raise GGAError(f"no quasi-3D workspace for L={cfg.L}, C={C}, P={P}, R={cfg.R}, K={K}")
+    return torch.empty(int(n), dtype=torch.uint8, device=device)
+
+
+def q3_init(params, cfg, C, P, device="cuda", stream=None):
+    """Initial quasi-3D states: (fields[P*R, 3, L, L] f32, cells[P*R, C, L, L] int16 holding uint16 words)."""
+    n = P * cfg.R
+    fields = torch.empty((n, 3, cfg.L, cfg.L), dtype=torch.float32, device=device)
+    cells = torch.empty((n, int(C), cfg.L, cfg.L), dtype=torch.int16, device=device)
+    _check(LIB.gga_q3_init(ctypes.byref(_as_params(params)), ctypes.byref(cfg), int(C), P, _ptr(fields),
+                           _ptr(cells), _stream(stream)))
+    return fields, cells
+
+
+def q3_run(params, cfg, C, dose, gap, nfrac, n0, nsteps, fields, cells, traj=False, ws=None, stream=None):
+    """Advance quasi-3D states in place by nsteps from step n0; returns (live[P, R], traj)."""
+    P, K = _protocols(dose, gap, nfrac)
+    n = P * cfg.R
+    if fields.shape != (n, 3, cfg.L, cfg.L) or fields.dtype != torch.float32 or not fields.is_contiguous():
+        raise ValueError("fields must be a contiguous float32 [P*R, 3, L, L] tensor")
+    if cells.shape != (n, int(C), cfg.L, cfg.L) or cells.dtype != torch.int16 or not cells.is_contiguous():
+        raise ValueError("cells must be a contiguous int16 [P*R, C, L, L] tensor")
+    ws = q3_workspace(cfg, C, P, K, dose.device) if ws is None else ws
+    live = torch.empty((P, cfg.R), dtype=torch.int32, device=dose.device)
+    tr = torch.empty((P, cfg.R, max(nsteps, 0)), dtype=torch.int32, device=dose.device) if traj else None
+    _check(LIB.gga_q3_run(ctypes.byref(_as_params(params)), ctypes.byref(cfg), int(C), _ptr(dose), _ptr(gap),
+                          _ptr(nfrac), P, K, int(n0), int(nsteps), _ptr(fields), _ptr(cells), _ptr(ws), ws.numel(),
+                          _ptr(live), _ptr(tr), _stream(stream)))
+    return live, tr
+
+
+def simulate_q3(params, cfg, C, dose, gap, nfrac, traj=False, ws=None, out=None, stream=None):
+    """simulate() for the quasi-3D variant with C cell slots per site; returns (live[P, R], fitness[P], traj)."""
+    P, K = _protocols(dose, gap, nfrac)
+    dev = dose.device
+    ws = q3_workspace(cfg, C, P, K, dev) if ws is None else ws
+    if out is None:
+        live = torch.empty((P, cfg.R), dtype=torch.int32, device=dev)
+        fit = torch.empty((P,), dtype=torch.float32, device=dev)
+        tr = torch.empty((P, cfg.R, cfg.horizon), dtype=torch.int32, device=dev) if traj else None
+    else:
+        live, fit, tr = out
+    _check(LIB.gga_simulate_q3(ctypes.byref(_as_params(params)), ctypes.byref(cfg), int(C), _ptr(dose), _ptr(gap),
+                               _ptr(nfrac), P, K, _ptr(ws), ws.numel(), _ptr(live), _ptr(fit), _ptr(tr),
+                               _stream(stream)))
+    return live, fit, tr
 
 
 # ---------------------------------------------------------------- GA

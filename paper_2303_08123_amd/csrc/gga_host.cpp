@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "gga_internal.h"
+#include "quasi3d.h"
 #include "mlp_internal.h"
 #include "peaks.h"
 #include "slots.h"
@@ -1454,6 +1455,179 @@ int gga_autotune(const gga_params* params, const gga_sim_cfg* cfg, const float* 
     if (best_res >= 0) gga::set_variant_choice(L, best_res);
     gga::set_variant_choice(L, best);
     return best;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Quasi-3D variant: C cell slots per site.
+namespace {
+
+int check_q3_cfg(const gga_sim_cfg* c, int32_t C) {
+    if (!c) return GGA_E_ARG;
+    if (c->struct_size != sizeof(gga_sim_cfg)) return GGA_E_ABI;
+    if ((c->flags & ~GGA_SIM_HALF_HOUR) != 0 || c->R < 1 || c->horizon < 0 || c->horizon > (1 << 30)) return GGA_E_ARG;
+    if (!std::isfinite(c->dose_cap)) return GGA_E_ARG;
+    if (C < 1 || C > gga::Q3_MAX_SLOTS) return GGA_E_ARG;
+    if (c->L < gga::Q3_MIN_L || c->L > gga::Q3_MAX_L || c->substeps < 1 || c->substeps > 64) return GGA_E_UNSUPPORTED;
+    if ((long long)C * c->L * c->L > gga::Q3_MAX_SLOT_SITES) return GGA_E_UNSUPPORTED;
+    return GGA_OK;
+}
+
+// instances x blocks per instance must stay below 2^31 (one-dimensional grid)
+bool q3_grid_ok(int32_t L, long long n_inst) {
+    const long long nbx = ((long long)L * L + 255) / 256;
+    return n_inst * nbx <= (1LL << 31) - 8;
+}
+
+struct Q3Plan {
+    size_t off_step, off_frac, off_f2, off_react, off_nfree, off_nxt, off_keys, off_prop, off_fields, off_cells, total;
+};
+
+Q3Plan q3_plan(int32_t L, int32_t C, int32_t P, int32_t R, int32_t K) {
+    Q3Plan q;
+    const size_t n = (size_t)P * R, L2 = (size_t)L * L, CL2 = (size_t)C * L2;
+    size_t o = align256(sizeof(int32_t) * 2 * (size_t)P);
+    q.off_step = o;
+    o += align256(sizeof(int32_t) * (size_t)P * K);
+    q.off_frac = o;
+    o += align256(sizeof(gga::EventFraction) * (size_t)P * K);
+    q.off_f2 = o;
+    o += align256(sizeof(float) * 3 * L2 * n);
+    q.off_react = o;
+    o += align256(sizeof(float) * L2 * n);
+    q.off_nfree = o;
+    o += align256(L2 * n);
+    q.off_nxt = o;
+    o += align256(sizeof(uint16_t) * CL2 * n);
+    q.off_keys = o;
+    o += align256(sizeof(unsigned long long) * CL2 * n);
+    q.off_prop = o;
+    o += align256(sizeof(uint32_t) * CL2 * n);
+    q.off_fields = o;
+    o += align256(sizeof(float) * 3 * L2 * n);
+    q.off_cells = o;
+    o += align256(sizeof(uint16_t) * CL2 * n);
+    q.total = o;
+    return q;
+}
+
+gga::Q3Args q3_args(const gga_params* prm, const gga_sim_cfg* cfg, int32_t C, int32_t P, int32_t K) {
+    gga::Q3Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.prm = *prm;
+    a.L = cfg->L;
+    a.C = C;
+    a.R = cfg->R;
+    a.K = K;
+    a.substeps = cfg->substeps;
+    a.half = (cfg->flags & GGA_SIM_HALF_HOUR) ? 1 : 0;
+    a.n_inst = P * cfg->R;
+    a.seed_lo = static_cast<uint32_t>(cfg->seed);
+    a.seed_hi = static_cast<uint32_t>(cfg->seed >> 32);
+    return a;
+}
+
+// Carves the workspace, builds the event table and runs steps n0 .. n0+nsteps-1
+// on the state in a.fields / a.cells.
+hipError_t q3_enqueue(gga::Q3Args a, const gga_params* prm, const gga_sim_cfg* cfg, const float* dose,
+                      const int32_t* gap, const int32_t* nfrac, int32_t P, int32_t K, char* ws, const Q3Plan& q,
+                      int32_t n0, int32_t nsteps, bool init, hipStream_t stream) {
+    int32_t* valid = reinterpret_cast<int32_t*>(ws);
+    int32_t* count = valid + P;
+    int32_t* step = reinterpret_cast<int32_t*>(ws + q.off_step);
+    gga::EventFraction* frac = reinterpret_cast<gga::EventFraction*>(ws + q.off_frac);
+    gga::SimArgs s = make_args(prm, cfg, dose, gap, nfrac, K);
+    hipError_t e = gga::launch_event_table(s, P, valid, count, step, frac, stream);
+    if (e != hipSuccess) return e;
+    a.ev_valid = valid;
+    a.ev_count = count;
+    a.ev_step = step;
+    a.ev_frac = frac;
+    a.fields2 = reinterpret_cast<float*>(ws + q.off_f2);
+    a.react = reinterpret_cast<float*>(ws + q.off_react);
+    a.nfree = reinterpret_cast<uint8_t*>(ws + q.off_nfree);
+    a.nxt = reinterpret_cast<uint16_t*>(ws + q.off_nxt);
+    a.keys = reinterpret_cast<unsigned long long*>(ws + q.off_keys);
+    a.prop = reinterpret_cast<uint32_t*>(ws + q.off_prop);
+    if (init && (e = gga::q3_init(a, stream)) != hipSuccess) return e;
+    return gga::q3_run(a, n0, nsteps, stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gga_q3_workspace_bytes(int32_t L, int32_t C, int32_t P, int32_t R, int32_t K) {
+    if (L < gga::Q3_MIN_L || L > gga::Q3_MAX_L || C < 1 || C > gga::Q3_MAX_SLOTS || R < 1 ||
+        (long long)C * L * L > gga::Q3_MAX_SLOT_SITES || check_batch(P, K, R))
+        return 0;
+    return q3_plan(L, C, P, R, K).total;
+}
+
+int gga_q3_init(const gga_params* params, const gga_sim_cfg* cfg, int32_t C, int32_t P, float* fields_d,
+                uint16_t* cells_d, hipStream_t stream) {
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((rc = check_q3_cfg(cfg, C))) return rc;
+    if ((rc = check_batch(P, 0, cfg->R))) return rc;
+    if (!q3_grid_ok(cfg->L, (long long)P * cfg->R)) return GGA_E_ARG;
+    if (P == 0) return GGA_OK;
+    if (!fields_d || !cells_d) return GGA_E_ARG;
+    gga::Q3Args a = q3_args(params, cfg, C, P, 0);
+    a.fields = fields_d;
+    a.cells = cells_d;
+    const hipError_t e = gga::q3_init(a, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_q3_run(const gga_params* params, const gga_sim_cfg* cfg, int32_t C, const float* dose_d,
+               const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P, int32_t K, int32_t n0, int32_t nsteps,
+               float* fields_d, uint16_t* cells_d, void* ws_d, size_t ws_bytes, int32_t* live_d, int32_t* traj_d,
+               hipStream_t stream) {
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((rc = check_q3_cfg(cfg, C))) return rc;
+    if ((rc = check_batch(P, K, cfg->R))) return rc;
+    if (n0 < 0 || nsteps < 0 || (long long)n0 + nsteps > (1LL << 30)) return GGA_E_ARG;
+    if (!q3_grid_ok(cfg->L, (long long)P * cfg->R)) return GGA_E_ARG;
+    if (P == 0) return GGA_OK;
+    if (!nfrac_d || !fields_d || !cells_d || !ws_d || misaligned16(ws_d) || (K > 0 && (!dose_d || !gap_h_d)))
+        return GGA_E_ARG;
+    const Q3Plan q = q3_plan(cfg->L, C, P, cfg->R, K);
+    if (ws_bytes < q.total) return GGA_E_ARG;
+    gga::Q3Args a = q3_args(params, cfg, C, P, K);
+    a.fields = fields_d;
+    a.cells = cells_d;
+    a.live = live_d;
+    a.traj = traj_d;
+    const hipError_t e = q3_enqueue(a, params, cfg, dose_d, gap_h_d, nfrac_d, P, K, static_cast<char*>(ws_d), q, n0,
+                                    nsteps, false, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
+}
+
+int gga_simulate_q3(const gga_params* params, const gga_sim_cfg* cfg, int32_t C, const float* dose_d,
+                    const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P, int32_t K, void* ws_d, size_t ws_bytes,
+                    int32_t* live_d, float* fitness_d, int32_t* traj_d, hipStream_t stream) {
+    int rc = check_params(params);
+    if (rc) return rc;
+    if ((rc = check_q3_cfg(cfg, C))) return rc;
+    if ((rc = check_batch(P, K, cfg->R))) return rc;
+    if (!q3_grid_ok(cfg->L, (long long)P * cfg->R)) return GGA_E_ARG;
+    if (P == 0) return GGA_OK;
+    if (!nfrac_d || !live_d || !fitness_d || !ws_d || misaligned16(ws_d) || (K > 0 && (!dose_d || !gap_h_d)))
+        return GGA_E_ARG;
+    const Q3Plan q = q3_plan(cfg->L, C, P, cfg->R, K);
+    if (ws_bytes < q.total) return GGA_E_ARG;
+    char* ws = static_cast<char*>(ws_d);
+    gga::Q3Args a = q3_args(params, cfg, C, P, K);
+    a.fields = reinterpret_cast<float*>(ws + q.off_fields);
+    a.cells = reinterpret_cast<uint16_t*>(ws + q.off_cells);
+    a.live = live_d;
+    a.traj = traj_d;
+    hipError_t e = q3_enqueue(a, params, cfg, dose_d, gap_h_d, nfrac_d, P, K, ws, q, 0, cfg->horizon, true, stream);
+    if (e == hipSuccess) e = gga::launch_fitness(live_d, P, cfg->R, fitness_d, stream);
+    return e == hipSuccess ? GGA_OK : hip_fail(e);
 }
 
 }  // extern "C"

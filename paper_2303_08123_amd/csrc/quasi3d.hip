@@ -1,0 +1,424 @@
+// Quasi-3D variant of the simulation: every lattice site holds C cell slots
+// (the paper's model is quasi-three-dimensional, with many cells to a site),
+// while oxygen, glucose and acidity stay two-dimensional.
+//
+// Rules beyond the 2D model (with C = 1 they are the 2D model's):
+//   - slot z of site s draws the Philox block of site counter z L^2 + s;
+//   - a site's reaction term is the mean over its slots of -kappa_O act[state];
+//   - a ready cell's free places are the EMPTY slots of its own site and of its
+//     four von Neumann neighbours, in the order own, N, E, S, W and by slot
+//     within a site; it proposes the k-th, k = floor(w0 m / 2^32), with the
+//     64-bit key ((w2 >> 3) << 8) | (d << 5) | z (d = 4 for its own site,
+//     otherwise its direction seen from the target: N 0, E 1, S 2, W 3), and
+//     every EMPTY slot takes the smallest key.
+//
+// Layout and launches.  The state of instance i is fields[i][3][L][L] and
+// cells[i][C][L][L]: slot planes, so that for every slot the 64 lanes of a
+// wave touch 64 consecutive sites.  A slot column of a 128^2 lattice with 8
+// slots is 256 KiB of words plus 192 KiB of fields, more than a compute unit's
+// LDS, so the state stays in device memory and a step is a chain of launches
+// over all instances at once: fraction, the FTCS sub-steps (one launch each,
+// two field buffers), a fraction at the half hour, cell update, resolution.
+// Each launch has one thread per site; an instance's blocks are numbered so
+// that they run on one XCD (blocks are dealt to the 8 XCDs in turn), keeping
+// the rows a block shares with its neighbours in one L2.
+#include "quasi3d.h"
+#include "sim_kernel.h"
+
+namespace gga {
+namespace {
+
+constexpr int Q3_NT = 256;
+constexpr unsigned long long NONE_KEY64 = ~0ull;
+constexpr uint32_t NO_PROP = 0xFFFFFFFFu;
+
+__host__ __device__ inline unsigned q3_blocks_per_inst(int L) { return ((unsigned)L * L + Q3_NT - 1) / Q3_NT; }
+__host__ __device__ inline unsigned q3_per_xcd(const Q3Args& a) {
+    return ((unsigned)a.n_inst * q3_blocks_per_inst(a.L) + 7u) / 8u;
+}
+
+// Instance and site of this thread.  Hardware block b runs on XCD b mod 8;
+// logical block lb = (b mod 8) * per_xcd + b / 8 puts consecutive logical
+// blocks, and so the blocks of one instance, on one XCD.  False (for the whole
+// block) past the last logical block.
+__device__ __forceinline__ bool q3_place(const Q3Args& a, int& inst, int& site) {
+    const unsigned nbx = q3_blocks_per_inst(a.L);
+    const unsigned per = q3_per_xcd(a);
+    const unsigned b = blockIdx.x;
+    const unsigned lb = (b & 7u) * per + (b >> 3);
+    if (lb >= (unsigned)a.n_inst * nbx) return false;
+    inst = (int)(lb / nbx);
+    site = (int)(lb - (unsigned)inst * nbx) * Q3_NT + (int)threadIdx.x;
+    return true;
+}
+
+__device__ __forceinline__ int sens_class(uint32_t w, const gga_params& P) {
+    const int st = w & 3, age = (w >> 2) & 255;
+    return st == QUIESC ? 3 : (age < P.class_age[0] ? 0 : (age < P.class_age[1] ? 1 : 2));
+}
+
+// Reaction term of a site: the mean of -kappa_O act[state] over its slots
+// (the sum alone for one slot, so that C = 1 reproduces the 2D term exactly).
+__device__ __forceinline__ float site_react(const float* s_react, const uint16_t* cw, int C, int L2, int site) {
+    float acc = s_react[cw[site] & 3];
+    for (int z = 1; z < C; ++z) acc += s_react[cw[(size_t)z * L2 + site] & 3];
+    return C > 1 ? acc * (1.0f / (float)C) : acc;
+}
+
+__device__ __forceinline__ void set_react_table(const gga_params& P, float* s_react) {
+    if (threadIdx.x < 4) s_react[threadIdx.x] = -P.kappa[0] * P.activity[threadIdx.x];
+}
+
+// Adds the block's live count to *dst (no-op for a null dst).
+__device__ __forceinline__ void block_count(int cnt, int32_t* dst, int* s_part) {
+    cnt = wave_sum(cnt);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0 && dst) {
+        int t = 0;
+        for (int w = 0; w < Q3_NT / 64; ++w) t += s_part[w];
+        atomicAdd(dst, t);
+    }
+}
+
+// Initial state: uniform fields, slot 0 the 2D model's seed disc (Philox ages
+// from the block at step 0xFFFFFFFF), the other slots EMPTY.
+__global__ void __launch_bounds__(Q3_NT) q3_init_kernel(Q3Args a) {
+    int inst, site;
+    if (!q3_place(a, inst, site)) return;
+    const int L = a.L, L2 = L * L;
+    if (site >= L2) return;
+    const int p = inst / a.R, r = inst - p * a.R;
+    float* F = a.fields + (size_t)inst * 3 * L2;
+    for (int f = 0; f < 3; ++f) F[(size_t)f * L2 + site] = to_field_units(a.prm, f, a.prm.init[f]);
+    uint16_t* cw = a.cells + (size_t)inst * a.C * L2;
+    const int y = site / L, x = site - y * L, ctr = L / 2;
+    uint16_t w = 0;
+    if ((x - ctr) * (x - ctr) + (y - ctr) * (y - ctr) <= a.prm.seed_radius * a.prm.seed_radius) {
+        const Block4 b = philox10((uint32_t)site, INIT_STEP, (uint32_t)r, (uint32_t)p, a.seed_lo, a.seed_hi);
+        const uint32_t age = (uint32_t)(((uint64_t)b.w0 * (uint32_t)a.prm.A0) >> 32);
+        w = (uint16_t)(PROLIF | (age << 2));
+    }
+    cw[site] = w;
+    for (int z = 1; z < a.C; ++z) cw[(size_t)z * L2 + site] = 0;
+}
+
+// live[i] = 0 and traj[i][*] = 0 for valid protocols, -1 otherwise; one
+// thread per entry of rows [traj[i][0 .. nsteps-1], live[i]] (live alone
+// without a trajectory).
+__global__ void q3_counts_kernel(Q3Args a, int nsteps) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t row = a.traj ? (size_t)nsteps + 1 : 1;
+    if (k >= (size_t)a.n_inst * row) return;
+    const int inst = (int)(k / row);
+    const size_t j = k - (size_t)inst * row;
+    const int v = a.ev_valid[inst / a.R] ? 0 : -1;
+    if (j == row - 1) {
+        if (a.live) a.live[inst] = v;
+    } else {
+        a.traj[(size_t)inst * nsteps + j] = v;
+    }
+}
+
+// Per-site working data from the cells: reaction term, number of EMPTY slots,
+// and no key on any EMPTY slot; with count set, the live cells into live[].
+__global__ void __launch_bounds__(Q3_NT) q3_prepare_kernel(Q3Args a, int count) {
+    int inst, site;
+    if (!q3_place(a, inst, site)) return;
+    if (!a.ev_valid[inst / a.R]) return;
+    __shared__ float s_react[4];
+    __shared__ int s_part[Q3_NT / 64];
+    set_react_table(a.prm, s_react);
+    __syncthreads();
+    const int L2 = a.L * a.L, C = a.C;
+    int cnt = 0;
+    if (site < L2) {
+        const uint16_t* cw = a.cells + (size_t)inst * C * L2;
+        unsigned long long* ky = a.keys + (size_t)inst * C * L2;
+        int nf = 0;
+        for (int z = 0; z < C; ++z) {
+            const uint32_t st = cw[(size_t)z * L2 + site] & 3u;
+            if (st == EMPTY) {
+                ++nf;
+                ky[(size_t)z * L2 + site] = NONE_KEY64;
+            }
+            cnt += (st == PROLIF || st == QUIESC);
+        }
+        a.nfree[(size_t)inst * L2 + site] = (uint8_t)nf;
+        a.react[(size_t)inst * L2 + site] = site_react(s_react, cw, C, L2, site);
+    }
+    if (count) block_count(cnt, a.live ? a.live + inst : nullptr, s_part);
+}
+
+// A fraction at half-hour 2n + mid of the protocol, if there is one: every live
+// cell survives iff its w1 < T[class] (with the oxygen effect T[class][bin of
+// the site's O in F]); a killed cell becomes DEAD, or is marked with mitotic
+// death.  The reaction term is then rebuilt from the surviving cells.
+__global__ void __launch_bounds__(Q3_NT) q3_fraction_kernel(Q3Args a, const float* F, int n, int mid) {
+    int inst, site;
+    if (!q3_place(a, inst, site)) return;
+    const int p = inst / a.R, r = inst - p * a.R;
+    if (!a.ev_valid[p]) return;
+    __shared__ int s_j;
+    __shared__ uint32_t s_thr[4][GGA_OER_BINS];
+    __shared__ float s_react[4];
+    const gga_params& P = a.prm;
+    if (threadIdx.x == 0) {                       // the fraction at this half-hour, by bisection
+        const int32_t* st = a.ev_step + (size_t)p * a.K;
+        const int cnt = a.ev_count[p];
+        const int tau = 2 * n + mid;
+        int lo = 0, hi = cnt;
+        while (lo < hi) {
+            const int md = (lo + hi) >> 1;
+            if (st[md] < tau) lo = md + 1; else hi = md;
+        }
+        s_j = (lo < cnt && st[lo] == tau) ? lo : -1;
+    }
+    __syncthreads();
+    const int j = s_j;
+    if (j < 0) return;                            // block-uniform
+    const EventFraction ef = a.ev_frac[(size_t)p * a.K + j];
+    const bool oer = P.oer_max > 1.0;
+    if (oer) {
+        if (threadIdx.x < 4 * GGA_OER_BINS) {
+            const int c = threadIdx.x / GGA_OER_BINS, b = threadIdx.x % GGA_OER_BINS;
+            const double f = oxygen_modification(P, b);
+            s_thr[c][b] = lq_threshold(f * (double)ef.dose, P.m[c], P.alpha, P.beta, f * ef.prior);
+        }
+    } else if (threadIdx.x < 4) {
+        s_thr[threadIdx.x][0] = lq_threshold((double)ef.dose, P.m[threadIdx.x], P.alpha, P.beta, ef.prior);
+    }
+    set_react_table(P, s_react);
+    __syncthreads();
+    const int L2 = a.L * a.L, C = a.C;
+    if (site >= L2) return;
+    const int bin = oer ? oxygen_bin(F[(size_t)inst * 3 * L2 + site], P) : 0;
+    uint16_t* cw = a.cells + (size_t)inst * C * L2;
+    const uint32_t step_word = (uint32_t)n | ((uint32_t)mid << 31);
+    for (int z = 0; z < C; ++z) {
+        const uint32_t w = cw[(size_t)z * L2 + site];
+        const uint32_t st = w & 3u;
+        if (st != PROLIF && st != QUIESC) continue;
+        const Block4 b = philox10((uint32_t)(z * L2 + site), step_word, (uint32_t)r, (uint32_t)p, a.seed_lo, a.seed_hi);
+        if (b.w1 >= s_thr[sens_class(w, P)][bin])
+            cw[(size_t)z * L2 + site] = P.mitotic_death ? (uint16_t)(w | DOOM_BIT) : (uint16_t)DEAD;
+    }
+    a.react[(size_t)inst * L2 + site] = site_react(s_react, cw, C, L2, site);
+}
+
+// One FTCS sub-step of the three fields in field units (boundary 0):
+// c' = lam ((N + S) + (W + E)) + (c (1 - 4 lam) + r), O and G clamped at the
+// units' zero.
+__global__ void __launch_bounds__(Q3_NT) q3_diffuse_kernel(Q3Args a, const float* src, float* dst) {
+    int inst, site;
+    if (!q3_place(a, inst, site)) return;
+    if (!a.ev_valid[inst / a.R]) return;
+    const int L = a.L, L2 = L * L;
+    if (site >= L2) return;
+    const int y = site / L, x = site - y * L;
+    const float R = a.react[(size_t)inst * L2 + site];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const float* s = src + ((size_t)inst * 3 + f) * L2;
+        const float lam = a.prm.lambda[f], cen = 1.0f - 4.0f * a.prm.lambda[f];
+        const float up = y > 0 ? s[site - L] : 0.0f, below = y < L - 1 ? s[site + L] : 0.0f;
+        const float west = x > 0 ? s[site - 1] : 0.0f, east = x < L - 1 ? s[site + 1] : 0.0f;
+        const float sum = (up + below) + (west + east);
+        float v = fmaf(lam, sum, fmaf(s[site], cen, R));
+        if (f < 2) v = fmaxf(v, to_field_units(a.prm, f, 0.0));
+        dst[((size_t)inst * 3 + f) * L2 + site] = v;
+    }
+}
+
+// Cell update from the snapshot (cells, after the fractions) and the fields
+// after the sub-steps; writes each slot's word before births (nxt), and for a
+// ready proposer its target and code (prop) after taking the minimum of its
+// key into the target's key.
+__global__ void __launch_bounds__(Q3_NT) q3_update_kernel(Q3Args a, const float* F, int n) {
+    int inst, site;
+    if (!q3_place(a, inst, site)) return;
+    const int p = inst / a.R, r = inst - p * a.R;
+    if (!a.ev_valid[p]) return;
+    __shared__ CellConst s_k;
+    const gga_params& P = a.prm;
+    if (threadIdx.x == 0) {
+        s_k.thOq = to_field_units(P, 0, P.theta_O_quiesce);
+        s_k.thGq = to_field_units(P, 1, P.theta_G_quiesce);
+        s_k.thOd = to_field_units(P, 0, P.theta_O_death);
+        s_k.thGd = to_field_units(P, 1, P.theta_G_death);
+        s_k.thHd = to_field_units(P, 2, P.theta_H_death);
+        s_k.T_div = (P.P_div >= 1.0) ? 0xFFFFFFFFu : (uint32_t)floor(P.P_div * 4294967296.0);
+    }
+    __syncthreads();
+    const int L = a.L, L2 = L * L, C = a.C;
+    if (site >= L2) return;
+    const float* Fi = F + (size_t)inst * 3 * L2;
+    const float O = Fi[site], Gl = Fi[L2 + site], H = Fi[2 * L2 + site];
+    // H's units have a negative scale, so H > theta reads H^ < theta^
+    const bool nec = (Gl < s_k.thGd) || (O < s_k.thOd) || (H < s_k.thHd);
+    const bool starv = (O < s_k.thOq) || (Gl < s_k.thGq);
+    const uint8_t* nf = a.nfree + (size_t)inst * L2;
+    const int y = site / L, x = site - y * L;
+    // free places by group: own site, N, E, S, W
+    const int cnt[5] = {nf[site], y > 0 ? nf[site - L] : 0, x < L - 1 ? nf[site + 1] : 0,
+                        y < L - 1 ? nf[site + L] : 0, x > 0 ? nf[site - 1] : 0};
+    const uint32_t m = (uint32_t)(cnt[0] + cnt[1] + cnt[2] + cnt[3] + cnt[4]);
+    const uint16_t* cw = a.cells + (size_t)inst * C * L2;
+    uint16_t* nw = a.nxt + (size_t)inst * C * L2;
+    uint32_t* pr = a.prop + (size_t)inst * C * L2;
+    unsigned long long* ky = a.keys + (size_t)inst * C * L2;
+    const uint32_t T_div = s_k.T_div;
+    for (int z = 0; z < C; ++z) {
+        const size_t at = (size_t)z * L2 + site;
+        const uint32_t w = cw[at];
+        const uint32_t st = w & 3u, age = (w >> 2) & 255u, doom = w & DOOM_BIT;
+        const uint32_t older = age < 255u ? age + 1u : 255u;
+        uint32_t out, prop = NO_PROP;
+        if (st == EMPTY) {
+            out = 0;
+        } else if (st == DEAD) {
+            out = (int)older >= P.T_lys ? 0u : ((uint32_t)DEAD | (older << 2));
+        } else if (nec) {
+            out = DEAD;
+        } else if (starv) {
+            out = (uint32_t)QUIESC | (w & ~3u);
+        } else {
+            out = (uint32_t)PROLIF | (older << 2) | doom;
+            if ((int)age >= P.T_min) {
+                const uint32_t idx = (uint32_t)(z * L2 + site);
+                if (P.mitotic_death && doom) {           // a marked cell dies when ready
+                    const Block4 b = philox10(idx, (uint32_t)n, (uint32_t)r, (uint32_t)p, a.seed_lo, a.seed_hi);
+                    if (b.w3 < T_div) out = DEAD;
+                } else if (m >= 1u) {
+                    const Block4 b = philox10(idx, (uint32_t)n, (uint32_t)r, (uint32_t)p, a.seed_lo, a.seed_hi);
+                    if (b.w3 < T_div) {
+                        uint32_t k = (uint32_t)(((uint64_t)b.w0 * m) >> 32);
+                        int g = 0;
+                        while (g < 4 && k >= (uint32_t)cnt[g]) k -= (uint32_t)cnt[g++];
+                        const int t = site + (g == 1 ? -L : g == 2 ? 1 : g == 3 ? L : g == 4 ? -1 : 0);
+                        int tz = -1;
+                        for (int zz = 0; zz < C; ++zz)
+                            if ((cw[(size_t)zz * L2 + t] & 3u) == EMPTY) {
+                                if (k == 0) { tz = zz; break; }
+                                --k;
+                            }
+                        if (tz >= 0) {
+                            const uint32_t code = (g == 0 ? 4u : g == 1 ? 2u : g == 2 ? 3u : g == 3 ? 0u : 1u);
+                            const uint32_t low = (code << 5) | (uint32_t)z;
+                            const unsigned long long key = ((unsigned long long)(b.w2 >> 3) << 8) | low;
+                            const uint32_t target = (uint32_t)(tz * L2 + t);
+                            atomicMin(ky + target, key);
+                            prop = (target << 8) | low;
+                        }
+                    }
+                }
+            }
+        }
+        nw[at] = (uint16_t)out;
+        pr[at] = prop;
+    }
+}
+
+// Births and winners: an EMPTY slot with a key takes the daughter (PROLIF, age
+// 0), a proposer whose code holds its target's key is the parent (age 0).
+// Writes the cells in place, the next step's reaction term and free counts,
+// clears the keys of EMPTY slots, and adds the live count to traj_col[inst *
+// traj_stride] and live[inst] (either may be null).
+__global__ void __launch_bounds__(Q3_NT) q3_resolve_kernel(Q3Args a, int32_t* traj_col, int traj_stride,
+                                                          int32_t* live) {
+    int inst, site;
+    if (!q3_place(a, inst, site)) return;
+    if (!a.ev_valid[inst / a.R]) return;
+    __shared__ float s_react[4];
+    __shared__ int s_part[Q3_NT / 64];
+    set_react_table(a.prm, s_react);
+    __syncthreads();
+    const int L2 = a.L * a.L, C = a.C;
+    int cnt = 0;
+    if (site < L2) {
+        uint16_t* cw = a.cells + (size_t)inst * C * L2;
+        const uint16_t* nw = a.nxt + (size_t)inst * C * L2;
+        const uint32_t* pr = a.prop + (size_t)inst * C * L2;
+        unsigned long long* ky = a.keys + (size_t)inst * C * L2;
+        int nf = 0;
+        for (int z = 0; z < C; ++z) {
+            const size_t at = (size_t)z * L2 + site;
+            uint32_t w = nw[at];
+            if ((cw[at] & 3u) == EMPTY && ky[at] != NONE_KEY64) w = PROLIF;
+            const uint32_t pp = pr[at];
+            if (pp != NO_PROP && (uint32_t)(ky[pp >> 8] & 0xFFu) == (pp & 0xFFu)) w = (w & DOOM_BIT) | PROLIF;
+            cw[at] = (uint16_t)w;
+            const uint32_t st = w & 3u;
+            cnt += (st == PROLIF || st == QUIESC);
+            if (st == EMPTY) {
+                ++nf;
+                ky[at] = NONE_KEY64;     // no proposer reads it: it was no target, or stays EMPTY with no key
+            }
+        }
+        a.nfree[(size_t)inst * L2 + site] = (uint8_t)nf;
+        a.react[(size_t)inst * L2 + site] = site_react(s_react, cw, C, L2, site);
+    }
+    block_count(cnt, traj_col ? traj_col + (size_t)inst * traj_stride : nullptr, s_part);
+    // the same count once more for the final live count (s_part is unchanged
+    // since block_count's barrier and is read by thread 0 only)
+    if (threadIdx.x == 0 && live) {
+        int t = 0;
+        for (int w = 0; w < Q3_NT / 64; ++w) t += s_part[w];
+        atomicAdd(live + inst, t);
+    }
+}
+
+// fields of valid instances: dst <- src (the last sub-step's buffer)
+__global__ void __launch_bounds__(Q3_NT) q3_copy_fields_kernel(Q3Args a, const float* src, float* dst) {
+    int inst, site;
+    if (!q3_place(a, inst, site)) return;
+    if (!a.ev_valid[inst / a.R]) return;
+    const int L2 = a.L * a.L;
+    if (site >= L2) return;
+    for (int f = 0; f < 3; ++f) dst[((size_t)inst * 3 + f) * L2 + site] = src[((size_t)inst * 3 + f) * L2 + site];
+}
+
+dim3 q3_grid(const Q3Args& a) { return dim3(q3_per_xcd(a) * 8u); }
+
+}  // namespace
+
+hipError_t q3_init(const Q3Args& a, hipStream_t stream) {
+    if (a.n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(q3_init_kernel, q3_grid(a), dim3(Q3_NT), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t q3_run(const Q3Args& a, int n0, int nsteps, hipStream_t stream) {
+    if (a.n_inst <= 0) return hipSuccess;
+    const dim3 grid = q3_grid(a), block(Q3_NT);
+    const size_t nc = (size_t)a.n_inst * (a.traj ? (size_t)nsteps + 1 : 1);
+    hipLaunchKernelGGL(q3_counts_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, stream, a, nsteps);
+    hipLaunchKernelGGL(q3_prepare_kernel, grid, block, 0, stream, a, nsteps == 0 ? 1 : 0);
+    float* cur = a.fields;
+    float* oth = a.fields2;
+    auto diffuse = [&](int k) {
+        for (int s = 0; s < k; ++s) {
+            hipLaunchKernelGGL(q3_diffuse_kernel, grid, block, 0, stream, a, (const float*)cur, oth);
+            std::swap(cur, oth);
+        }
+    };
+    const int first = a.half ? a.substeps / 2 : a.substeps;
+    for (int i = 0; i < nsteps; ++i) {
+        const int n = n0 + i;
+        hipLaunchKernelGGL(q3_fraction_kernel, grid, block, 0, stream, a, (const float*)cur, n, 0);
+        diffuse(first);
+        if (a.half) {
+            hipLaunchKernelGGL(q3_fraction_kernel, grid, block, 0, stream, a, (const float*)cur, n, 1);
+            diffuse(a.substeps - first);
+        }
+        hipLaunchKernelGGL(q3_update_kernel, grid, block, 0, stream, a, (const float*)cur, n);
+        hipLaunchKernelGGL(q3_resolve_kernel, grid, block, 0, stream, a, a.traj ? a.traj + i : nullptr, nsteps,
+                           i == nsteps - 1 ? a.live : nullptr);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (cur != a.fields) hipLaunchKernelGGL(q3_copy_fields_kernel, grid, block, 0, stream, a, (const float*)cur, a.fields);
+    return hipGetLastError();
+}
+
+}  // namespace gga

@@ -23,6 +23,10 @@ CONFIG2 = dict(name="batched-1024x4-128x128-20d", L=128, R=4, horizon=480, subst
 CONFIG3 = dict(name="uneven-8192x8-64to256-10to40d", R=8, substeps=10, seed=0, dose_cap=30.0, P=8192, K=40,
                kmin=3, dose_quantum=0.5, dose_q=list(range(1, 11)), gaps=list(range(6, 61, 6)),
                sides=(64, 128, 256), days=(10, 40))
+# Quasi-3D variant: the batched workload's protocols (first 256) on 128 x 128
+# sites with 8 cell slots each, 20 days.
+CONFIG_Q3 = dict(name="quasi3d-256x4-128x128x8-20d", L=128, C=8, R=4, horizon=480, substeps=10, seed=0,
+                 dose_cap=20.0, P=256, K=10)
 CONFIG2_DOSES = np.array([0.5, 1.0, 1.5, 2.0, 2.5], np.float32)
 CONFIG2_GAPS = np.arange(6, 61, 6, dtype=np.int32)
 

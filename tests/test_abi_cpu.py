@@ -28,7 +28,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(gga):
     names = declared_functions()
-    assert len(names) == 46
+    assert len(names) == 50
     for n in names:
         assert hasattr(gga.LIB, n), n
     assert set(names) == set(gga.EXPORTS)
@@ -187,6 +187,33 @@ def test_uneven_argument_errors_before_any_launch(gga):
     rc = gga.LIB.gga_state_run_variant(ctypes.byref(p), ctypes.byref(cfg), 5, fake, fake, fake, 2, 1, 0, 1,
                                        fake, fake, fake, fake, fake, 1 << 20, fake, None)
     assert rc == -1                                           # a 256 variant on a 64 lattice
+
+
+def test_quasi3d_arguments_are_checked_before_any_launch(gga):
+    p = gga.make_params(gga.load_model())
+    fake, odd = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1008)
+    ws = gga.LIB.gga_q3_workspace_bytes(128, 8, 4, 2, 3)
+    # event table, then per instance: fields twice, reaction term, free counts,
+    # words twice, 64-bit keys and 32-bit proposals per slot
+    per = 128 * 128 * (12 * 2 + 4 + 1 + 8 * (2 * 2 + 8 + 4))
+    assert per * 8 <= ws <= per * 8 + 12 * 256 + 4 * 3 * 24
+    for L, C in ((128, 0), (128, 33), (4, 1), (1024, 8)):
+        assert gga.LIB.gga_q3_workspace_bytes(L, C, 4, 2, 3) == 0
+    call = lambda cfg, C, ws_ptr, nbytes: gga.LIB.gga_simulate_q3(
+        ctypes.byref(p), ctypes.byref(cfg), C, fake, fake, fake, 4, 3, ws_ptr, nbytes, fake, fake, None, None)
+    cfg = gga.make_cfg(128, 10, 2)
+    assert call(cfg, 0, fake, ws) == -1                           # no slots
+    assert call(cfg, 33, fake, ws) == -1                          # too many slots
+    assert call(cfg, 8, fake, ws - 1) == -1                       # workspace too small
+    assert call(cfg, 8, odd, ws) == -1                            # misaligned workspace
+    assert call(gga.make_cfg(4, 10, 2), 1, fake, ws) == -3        # lattice too small
+    assert call(gga.make_cfg(512, 10, 2), 64, fake, ws) == -1
+    assert call(gga.make_cfg(128, 10, 2, substeps=65), 8, fake, ws) == -3
+    rc = gga.LIB.gga_q3_run(ctypes.byref(p), ctypes.byref(cfg), 8, fake, fake, fake, 4, 3, (1 << 30) - 4, 5, fake,
+                            fake, fake, ws, fake, None, None)
+    assert rc == -1                                               # n0 + nsteps beyond 2^30
+    bad = gga.make_params(dict(gga.load_model(), mitotic_death=2))
+    assert gga.LIB.gga_q3_init(ctypes.byref(bad), ctypes.byref(cfg), 8, 4, fake, fake, None) == -5
 
 
 def test_ga_operator_settings_are_checked_before_any_launch(gga):

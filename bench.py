@@ -526,15 +526,16 @@ def uneven_bench(gga, workloads, md, args):
     }
 
 
-def q3_bytes_per_site_step(C, S):
-    """Algorithmic HBM bytes of one quasi-3D step per site: each FTCS sub-step
-    reads three fields and the reaction term and writes three fields (28 B);
-    the cell update reads the C words, three fields and the free count and
-    writes C words and C 4-byte proposals (13 + 8 C); the resolution reads the
-    words before and after the update and the proposals and writes the words,
-    the reaction term and the free count (5 + 10 C).  Key traffic (8 B per
-    EMPTY slot and proposal) and the steps with a fraction are not counted."""
-    return 28 * S + (13 + 8 * C) + (5 + 10 * C)
+def q3_bytes_per_site_step(C):
+    """Algorithmic HBM bytes of one quasi-3D step per site (hourly protocols):
+    the fused sub-steps read three fields and the reaction term and write three
+    fields once (28 B); the cell update reads the C words, three fields, the
+    site's EMPTY mask and the previous step's targeted mask and writes that
+    mask, the changed words (counted as all C) and the proposer mask
+    (28 + 4 C); the resolution reads the targeted and proposer masks and the C
+    words and writes the EMPTY mask and the reaction term (16 + 2 C).  Keys,
+    proposals and births (a few per site and step) are not counted."""
+    return 28 + (28 + 4 * C) + (16 + 2 * C)
 
 
 def q3_cpu_baseline(md, wl, dose, gap, nfrac, n_replicas=2):
@@ -590,7 +591,7 @@ def q3_bench(gga, workloads, md, args):
     assert np.all(live >= 0) and np.all(np.isfinite(fit))
     site_steps = float(P * R * L * L * N)
     s = wall / args.steps
-    achieved = q3_bytes_per_site_step(C, S) * site_steps / call_s
+    achieved = q3_bytes_per_site_step(C) * site_steps / call_s
     result = {
         "metric": "protocols/sec (quasi-3D batch: 256 protocols x 4 replicas, 128x128 sites x 8 slots, 20 days)",
         "value": P / s, "unit": "protocols/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -601,7 +602,7 @@ def q3_bench(gga, workloads, md, args):
         "site_steps_per_s": site_steps / s,
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_BYTES, "traffic": None, "kernel": "whole step chain",
-                     "bytes_per_site_step": q3_bytes_per_site_step(C, S), "call_ms": call_s * 1000.0},
+                     "bytes_per_site_step": q3_bytes_per_site_step(C), "call_ms": call_s * 1000.0},
         "mean_live_cells": float(live.mean()),
     }
     if not args.no_cpu_baseline:

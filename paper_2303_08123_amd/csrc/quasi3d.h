@@ -20,10 +20,12 @@ struct Q3Args {
     float* fields;                          // [inst][3][L][L] state, field units
     float* fields2;                         // second field buffer, same shape
     uint16_t* cells;                        // [inst][C][L][L] state
-    uint16_t* nxt;                          // [inst][C][L][L] words after the cell update, before births
     float* react;                           // [inst][L][L] reaction term of the site
-    uint8_t* nfree;                         // [inst][L][L] EMPTY slots of the site
-    unsigned long long* keys;               // [inst][C][L][L] smallest proposal key of an EMPTY slot
+    uint32_t* emask;                        // [inst][L][L] EMPTY slots of the site (bit z)
+    uint32_t* tmask;                        // [2][inst][L][L] slots targeted by a proposal, by step parity
+    uint32_t* pmask;                        // [inst][L][L] slots whose cell proposed this step
+    unsigned long long* keys;               // [inst][C][L][L] smallest proposal key of a targeted slot;
+                                            // all ones on every other slot
     uint32_t* prop;                         // [inst][C][L][L] a proposer's target slot << 8 | its code
     int32_t* live;                          // [inst] or null
     int32_t* traj;                          // [inst][nsteps] or null

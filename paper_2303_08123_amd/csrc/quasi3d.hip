@@ -17,11 +17,11 @@
 // wave touch 64 consecutive sites.  A slot column of a 128^2 lattice with 8
 // slots is 256 KiB of words plus 192 KiB of fields, more than a compute unit's
 // LDS, so the state stays in device memory and a step is a chain of launches
-// over all instances at once: fraction, the FTCS sub-steps (one launch each,
-// two field buffers), a fraction at the half hour, cell update, resolution.
-// Each launch has one thread per site; an instance's blocks are numbered so
-// that they run on one XCD (blocks are dealt to the 8 XCDs in turn), keeping
-// the rows a block shares with its neighbours in one L2.
+// over all instances at once: fraction, the FTCS sub-steps (fused in LDS
+// tiles, two field buffers), a fraction at the half hour, cell update,
+// resolution.  The per-site launches have one thread per site; an instance's
+// blocks are numbered so that they run on one XCD (blocks are dealt to the 8
+// XCDs in turn), keeping the rows a block shares with its neighbours in one L2.
 #include "quasi3d.h"
 #include "sim_kernel.h"
 
@@ -30,7 +30,6 @@ namespace {
 
 constexpr int Q3_NT = 256;
 constexpr unsigned long long NONE_KEY64 = ~0ull;
-constexpr uint32_t NO_PROP = 0xFFFFFFFFu;
 
 __host__ __device__ inline unsigned q3_blocks_per_inst(int L) { return ((unsigned)L * L + Q3_NT - 1) / Q3_NT; }
 __host__ __device__ inline unsigned q3_per_xcd(const Q3Args& a) {
@@ -120,8 +119,9 @@ __global__ void q3_counts_kernel(Q3Args a, int nsteps) {
     }
 }
 
-// Per-site working data from the cells: reaction term, number of EMPTY slots,
-// and no key on any EMPTY slot; with count set, the live cells into live[].
+// Per-site working data from the cells: reaction term, mask of EMPTY slots,
+// no key on any slot and no targeted slot; with count set, the live cells into
+// live[].
 __global__ void __launch_bounds__(Q3_NT) q3_prepare_kernel(Q3Args a, int count) {
     int inst, site;
     if (!q3_place(a, inst, site)) return;
@@ -135,17 +135,18 @@ __global__ void __launch_bounds__(Q3_NT) q3_prepare_kernel(Q3Args a, int count) 
     if (site < L2) {
         const uint16_t* cw = a.cells + (size_t)inst * C * L2;
         unsigned long long* ky = a.keys + (size_t)inst * C * L2;
-        int nf = 0;
+        uint32_t em = 0;
         for (int z = 0; z < C; ++z) {
             const uint32_t st = cw[(size_t)z * L2 + site] & 3u;
-            if (st == EMPTY) {
-                ++nf;
-                ky[(size_t)z * L2 + site] = NONE_KEY64;
-            }
+            if (st == EMPTY) em |= 1u << z;
             cnt += (st == PROLIF || st == QUIESC);
+            ky[(size_t)z * L2 + site] = NONE_KEY64;
         }
-        a.nfree[(size_t)inst * L2 + site] = (uint8_t)nf;
-        a.react[(size_t)inst * L2 + site] = site_react(s_react, cw, C, L2, site);
+        const size_t at = (size_t)inst * L2 + site, plane = (size_t)a.n_inst * L2;
+        a.emask[at] = em;
+        a.tmask[at] = 0;
+        a.tmask[plane + at] = 0;
+        a.react[at] = site_react(s_react, cw, C, L2, site);
     }
     if (count) block_count(cnt, a.live ? a.live + inst : nullptr, s_part);
 }
@@ -206,34 +207,96 @@ __global__ void __launch_bounds__(Q3_NT) q3_fraction_kernel(Q3Args a, const floa
     a.react[(size_t)inst * L2 + site] = site_react(s_react, cw, C, L2, site);
 }
 
-// One FTCS sub-step of the three fields in field units (boundary 0):
+// The FTCS sub-steps of the three fields in field units (boundary 0),
 // c' = lam ((N + S) + (W + E)) + (c (1 - 4 lam) + r), O and G clamped at the
-// units' zero.
-__global__ void __launch_bounds__(Q3_NT) q3_diffuse_kernel(Q3Args a, const float* src, float* dst) {
-    int inst, site;
-    if (!q3_place(a, inst, site)) return;
-    if (!a.ev_valid[inst / a.R]) return;
+// units' zero, fused up to Q3_MAX_HALO per launch: a workgroup loads a
+// T x T tile of owned sites with a halo of h sites (the launch's sub-step
+// count) of the three fields and the reaction term into LDS, runs h sub-steps
+// there (sub-step k updates the region at least k + 1 sites inside the loaded
+// square, which its inputs fully determine), and stores the owned sites.
+// Sites outside the lattice hold 0, the boundary value in field units, and
+// every site's arithmetic is the 2D kernels' (so C = 1 reproduces them).
+constexpr int Q3_TILE = 32, Q3_TILE_NT = 512, Q3_MAX_HALO = 16;
+__host__ __device__ inline unsigned q3_tiles_per_inst(int L) {
+    const unsigned t = ((unsigned)L + Q3_TILE - 1) / Q3_TILE;
+    return t * t;
+}
+
+template <int EMAX>
+__global__ void __launch_bounds__(Q3_TILE_NT) q3_diffuse_tile_kernel(Q3Args a, const float* src, float* dst, int h) {
+    __shared__ float s_f[2][3][EMAX * EMAX];
+    __shared__ float s_r[EMAX * EMAX];
     const int L = a.L, L2 = L * L;
-    if (site >= L2) return;
-    const int y = site / L, x = site - y * L;
-    const float R = a.react[(size_t)inst * L2 + site];
+    const int tpr = (L + Q3_TILE - 1) / Q3_TILE;
+    const unsigned tiles = q3_tiles_per_inst(L);
+    const unsigned total = (unsigned)a.n_inst * tiles, per = (total + 7u) / 8u;
+    const unsigned lb = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);     // XCD-grouped, as q3_place
+    if (lb >= total) return;
+    const int inst = (int)(lb / tiles), tile = (int)(lb - (unsigned)inst * tiles);
+    if (!a.ev_valid[inst / a.R]) return;
+    const int y0 = (tile / tpr) * Q3_TILE - h, x0 = (tile % tpr) * Q3_TILE - h;   // lattice site of LDS (0, 0)
+    const int E = Q3_TILE + 2 * h;
+    const float* S = src + (size_t)inst * 3 * L2;
+    const float* Rg = a.react + (size_t)inst * L2;
+    for (int i = threadIdx.x; i < E * E; i += Q3_TILE_NT) {
+        const int ly = i / E, lx = i - ly * E;
+        const int gy = y0 + ly, gx = x0 + lx, o = ly * EMAX + lx;
+        const bool in = gy >= 0 && gy < L && gx >= 0 && gx < L;
+        const size_t g = (size_t)gy * L + gx;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) s_f[0][f][o] = in ? S[(size_t)f * L2 + g] : 0.0f;
+        s_r[o] = in ? Rg[g] : 0.0f;
+    }
+    float lam[3], cen[3], lo[2];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        const float* s = src + ((size_t)inst * 3 + f) * L2;
-        const float lam = a.prm.lambda[f], cen = 1.0f - 4.0f * a.prm.lambda[f];
-        const float up = y > 0 ? s[site - L] : 0.0f, below = y < L - 1 ? s[site + L] : 0.0f;
-        const float west = x > 0 ? s[site - 1] : 0.0f, east = x < L - 1 ? s[site + 1] : 0.0f;
-        const float sum = (up + below) + (west + east);
-        float v = fmaf(lam, sum, fmaf(s[site], cen, R));
-        if (f < 2) v = fmaxf(v, to_field_units(a.prm, f, 0.0));
-        dst[((size_t)inst * 3 + f) * L2 + site] = v;
+        lam[f] = a.prm.lambda[f];
+        cen[f] = 1.0f - 4.0f * a.prm.lambda[f];
+    }
+    lo[0] = to_field_units(a.prm, 0, 0.0);
+    lo[1] = to_field_units(a.prm, 1, 0.0);
+    __syncthreads();
+    int cur = 0;
+    for (int k = 0; k < h; ++k) {
+        const int r0 = k + 1, w = E - 2 * (k + 1);
+        for (int i = threadIdx.x; i < w * w; i += Q3_TILE_NT) {
+            const int qy = i / w;
+            const int ly = r0 + qy, lx = r0 + (i - qy * w);
+            const int gy = y0 + ly, gx = x0 + lx, o = ly * EMAX + lx;
+            const bool in = gy >= 0 && gy < L && gx >= 0 && gx < L;
+            const float R = s_r[o];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const float* c = s_f[cur][f];
+                const float sum = (c[o - EMAX] + c[o + EMAX]) + (c[o - 1] + c[o + 1]);
+                float v = fmaf(lam[f], sum, fmaf(c[o], cen[f], R));
+                if (f < 2) v = fmaxf(v, lo[f]);
+                s_f[cur ^ 1][f][o] = in ? v : 0.0f;
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    float* D = dst + (size_t)inst * 3 * L2;
+    for (int i = threadIdx.x; i < Q3_TILE * Q3_TILE; i += Q3_TILE_NT) {
+        const int qy = i / Q3_TILE;
+        const int ly = h + qy, lx = h + (i - qy * Q3_TILE);
+        const int gy = y0 + ly, gx = x0 + lx;
+        if (gy >= L || gx >= L) continue;
+        const size_t g = (size_t)gy * L + gx;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) D[(size_t)f * L2 + g] = s_f[cur][f][ly * EMAX + lx];
     }
 }
 
-// Cell update from the snapshot (cells, after the fractions) and the fields
-// after the sub-steps; writes each slot's word before births (nxt), and for a
-// ready proposer its target and code (prop) after taking the minimum of its
-// key into the target's key.
+// Cell update from the snapshot (cells, after the fractions; its EMPTY slots
+// in emask) and the fields after the sub-steps, in place: every slot's word
+// before births.  A ready proposer takes the minimum of its key into the
+// target slot's key, marks the target in this step's targeted mask and keeps
+// its target and code (prop, and its bit in pmask).  First the keys of the
+// slots targeted in the previous step are cleared (those slots now hold cells,
+// so no proposal of this step reaches them) and that mask is zeroed for the
+// next step.
 __global__ void __launch_bounds__(Q3_NT) q3_update_kernel(Q3Args a, const float* F, int n) {
     int inst, site;
     if (!q3_place(a, inst, site)) return;
@@ -252,31 +315,37 @@ __global__ void __launch_bounds__(Q3_NT) q3_update_kernel(Q3Args a, const float*
     __syncthreads();
     const int L = a.L, L2 = L * L, C = a.C;
     if (site >= L2) return;
+    const size_t plane = (size_t)a.n_inst * L2;
+    uint32_t* t_now = a.tmask + (n & 1) * plane + (size_t)inst * L2;
+    uint32_t* t_prev = a.tmask + ((n + 1) & 1) * plane + (size_t)inst * L2;
+    unsigned long long* ky = a.keys + (size_t)inst * C * L2;
+    for (uint32_t tp = t_prev[site]; tp; tp &= tp - 1) ky[(size_t)__builtin_ctz(tp) * L2 + site] = NONE_KEY64;
+    t_prev[site] = 0;
+
     const float* Fi = F + (size_t)inst * 3 * L2;
     const float O = Fi[site], Gl = Fi[L2 + site], H = Fi[2 * L2 + site];
     // H's units have a negative scale, so H > theta reads H^ < theta^
     const bool nec = (Gl < s_k.thGd) || (O < s_k.thOd) || (H < s_k.thHd);
     const bool starv = (O < s_k.thOq) || (Gl < s_k.thGq);
-    const uint8_t* nf = a.nfree + (size_t)inst * L2;
+    const uint32_t* em = a.emask + (size_t)inst * L2;
     const int y = site / L, x = site - y * L;
-    // free places by group: own site, N, E, S, W
-    const int cnt[5] = {nf[site], y > 0 ? nf[site - L] : 0, x < L - 1 ? nf[site + 1] : 0,
-                        y < L - 1 ? nf[site + L] : 0, x > 0 ? nf[site - 1] : 0};
-    const uint32_t m = (uint32_t)(cnt[0] + cnt[1] + cnt[2] + cnt[3] + cnt[4]);
-    const uint16_t* cw = a.cells + (size_t)inst * C * L2;
-    uint16_t* nw = a.nxt + (size_t)inst * C * L2;
+    // EMPTY-slot masks by group: own site, N, E, S, W (none outside the lattice)
+    const uint32_t gm[5] = {em[site], y > 0 ? em[site - L] : 0u, x < L - 1 ? em[site + 1] : 0u,
+                            y < L - 1 ? em[site + L] : 0u, x > 0 ? em[site - 1] : 0u};
+    const uint32_t m = (uint32_t)(__builtin_popcount(gm[0]) + __builtin_popcount(gm[1]) + __builtin_popcount(gm[2]) +
+                                  __builtin_popcount(gm[3]) + __builtin_popcount(gm[4]));
+    uint16_t* cw = a.cells + (size_t)inst * C * L2;
     uint32_t* pr = a.prop + (size_t)inst * C * L2;
-    unsigned long long* ky = a.keys + (size_t)inst * C * L2;
     const uint32_t T_div = s_k.T_div;
+    uint32_t proposed = 0;
     for (int z = 0; z < C; ++z) {
         const size_t at = (size_t)z * L2 + site;
         const uint32_t w = cw[at];
         const uint32_t st = w & 3u, age = (w >> 2) & 255u, doom = w & DOOM_BIT;
+        if (st == EMPTY) continue;
         const uint32_t older = age < 255u ? age + 1u : 255u;
-        uint32_t out, prop = NO_PROP;
-        if (st == EMPTY) {
-            out = 0;
-        } else if (st == DEAD) {
+        uint32_t out;
+        if (st == DEAD) {
             out = (int)older >= P.T_lys ? 0u : ((uint32_t)DEAD | (older << 2));
         } else if (nec) {
             out = DEAD;
@@ -294,37 +363,32 @@ __global__ void __launch_bounds__(Q3_NT) q3_update_kernel(Q3Args a, const float*
                     if (b.w3 < T_div) {
                         uint32_t k = (uint32_t)(((uint64_t)b.w0 * m) >> 32);
                         int g = 0;
-                        while (g < 4 && k >= (uint32_t)cnt[g]) k -= (uint32_t)cnt[g++];
+                        while (g < 4 && k >= (uint32_t)__builtin_popcount(gm[g])) k -= (uint32_t)__builtin_popcount(gm[g++]);
                         const int t = site + (g == 1 ? -L : g == 2 ? 1 : g == 3 ? L : g == 4 ? -1 : 0);
-                        int tz = -1;
-                        for (int zz = 0; zz < C; ++zz)
-                            if ((cw[(size_t)zz * L2 + t] & 3u) == EMPTY) {
-                                if (k == 0) { tz = zz; break; }
-                                --k;
-                            }
-                        if (tz >= 0) {
-                            const uint32_t code = (g == 0 ? 4u : g == 1 ? 2u : g == 2 ? 3u : g == 3 ? 0u : 1u);
-                            const uint32_t low = (code << 5) | (uint32_t)z;
-                            const unsigned long long key = ((unsigned long long)(b.w2 >> 3) << 8) | low;
-                            const uint32_t target = (uint32_t)(tz * L2 + t);
-                            atomicMin(ky + target, key);
-                            prop = (target << 8) | low;
-                        }
+                        uint32_t free_slots = gm[g];
+                        for (; k; --k) free_slots &= free_slots - 1;      // the k-th EMPTY slot of site t
+                        const int tz = __builtin_ctz(free_slots);
+                        const uint32_t code = (g == 0 ? 4u : g == 1 ? 2u : g == 2 ? 3u : g == 3 ? 0u : 1u);
+                        const uint32_t low = (code << 5) | (uint32_t)z;
+                        const uint32_t target = (uint32_t)(tz * L2 + t);
+                        atomicMin(ky + target, ((unsigned long long)(b.w2 >> 3) << 8) | low);
+                        atomicOr(t_now + t, 1u << tz);
+                        pr[at] = (target << 8) | low;
+                        proposed |= 1u << z;
                     }
                 }
             }
         }
-        nw[at] = (uint16_t)out;
-        pr[at] = prop;
+        if (out != w) cw[at] = (uint16_t)out;
     }
+    a.pmask[(size_t)inst * L2 + site] = proposed;
 }
 
-// Births and winners: an EMPTY slot with a key takes the daughter (PROLIF, age
-// 0), a proposer whose code holds its target's key is the parent (age 0).
-// Writes the cells in place, the next step's reaction term and free counts,
-// clears the keys of EMPTY slots, and adds the live count to traj_col[inst *
-// traj_stride] and live[inst] (either may be null).
-__global__ void __launch_bounds__(Q3_NT) q3_resolve_kernel(Q3Args a, int32_t* traj_col, int traj_stride,
+// Births and winners: a targeted slot takes the daughter (PROLIF, age 0), a
+// proposer whose code holds its target's key is the parent (age 0).  Then the
+// next step's reaction term and EMPTY mask, and the live count added to
+// traj_col[inst * traj_stride] and live[inst] (either may be null).
+__global__ void __launch_bounds__(Q3_NT) q3_resolve_kernel(Q3Args a, int n, int32_t* traj_col, int traj_stride,
                                                           int32_t* live) {
     int inst, site;
     if (!q3_place(a, inst, site)) return;
@@ -336,27 +400,27 @@ __global__ void __launch_bounds__(Q3_NT) q3_resolve_kernel(Q3Args a, int32_t* tr
     const int L2 = a.L * a.L, C = a.C;
     int cnt = 0;
     if (site < L2) {
+        const size_t plane = (size_t)a.n_inst * L2, at0 = (size_t)inst * L2 + site;
         uint16_t* cw = a.cells + (size_t)inst * C * L2;
-        const uint16_t* nw = a.nxt + (size_t)inst * C * L2;
         const uint32_t* pr = a.prop + (size_t)inst * C * L2;
-        unsigned long long* ky = a.keys + (size_t)inst * C * L2;
-        int nf = 0;
-        for (int z = 0; z < C; ++z) {
-            const size_t at = (size_t)z * L2 + site;
-            uint32_t w = nw[at];
-            if ((cw[at] & 3u) == EMPTY && ky[at] != NONE_KEY64) w = PROLIF;
+        const unsigned long long* ky = a.keys + (size_t)inst * C * L2;
+        for (uint32_t tm = a.tmask[(n & 1) * plane + at0]; tm; tm &= tm - 1)
+            cw[(size_t)__builtin_ctz(tm) * L2 + site] = PROLIF;
+        for (uint32_t pm = a.pmask[at0]; pm; pm &= pm - 1) {
+            const size_t at = (size_t)__builtin_ctz(pm) * L2 + site;
             const uint32_t pp = pr[at];
-            if (pp != NO_PROP && (uint32_t)(ky[pp >> 8] & 0xFFu) == (pp & 0xFFu)) w = (w & DOOM_BIT) | PROLIF;
-            cw[at] = (uint16_t)w;
-            const uint32_t st = w & 3u;
-            cnt += (st == PROLIF || st == QUIESC);
-            if (st == EMPTY) {
-                ++nf;
-                ky[at] = NONE_KEY64;     // no proposer reads it: it was no target, or stays EMPTY with no key
-            }
+            if ((uint32_t)(ky[pp >> 8] & 0xFFu) == (pp & 0xFFu)) cw[at] = (uint16_t)((cw[at] & DOOM_BIT) | PROLIF);
         }
-        a.nfree[(size_t)inst * L2 + site] = (uint8_t)nf;
-        a.react[(size_t)inst * L2 + site] = site_react(s_react, cw, C, L2, site);
+        uint32_t em = 0;
+        float acc = 0.0f;
+        for (int z = 0; z < C; ++z) {
+            const uint32_t st = cw[(size_t)z * L2 + site] & 3u;
+            if (st == EMPTY) em |= 1u << z;
+            cnt += (st == PROLIF || st == QUIESC);
+            acc = z == 0 ? s_react[st] : acc + s_react[st];
+        }
+        a.emask[at0] = em;
+        a.react[at0] = C > 1 ? acc * (1.0f / (float)C) : acc;
     }
     block_count(cnt, traj_col ? traj_col + (size_t)inst * traj_stride : nullptr, s_part);
     // the same count once more for the final live count (s_part is unchanged
@@ -396,10 +460,18 @@ hipError_t q3_run(const Q3Args& a, int n0, int nsteps, hipStream_t stream) {
     hipLaunchKernelGGL(q3_prepare_kernel, grid, block, 0, stream, a, nsteps == 0 ? 1 : 0);
     float* cur = a.fields;
     float* oth = a.fields2;
+    const dim3 tile_grid(((unsigned)a.n_inst * q3_tiles_per_inst(a.L) + 7u) / 8u * 8u);
     auto diffuse = [&](int k) {
-        for (int s = 0; s < k; ++s) {
-            hipLaunchKernelGGL(q3_diffuse_kernel, grid, block, 0, stream, a, (const float*)cur, oth);
+        while (k > 0) {              // sub-steps fused in LDS tiles, Q3_MAX_HALO at most per launch
+            const int h = k < Q3_MAX_HALO ? k : Q3_MAX_HALO;
+            if (h <= 10)
+                hipLaunchKernelGGL(q3_diffuse_tile_kernel<Q3_TILE + 20>, tile_grid, dim3(Q3_TILE_NT), 0, stream, a,
+                                   (const float*)cur, oth, h);
+            else
+                hipLaunchKernelGGL(q3_diffuse_tile_kernel<Q3_TILE + 2 * Q3_MAX_HALO>, tile_grid, dim3(Q3_TILE_NT), 0,
+                                   stream, a, (const float*)cur, oth, h);
             std::swap(cur, oth);
+            k -= h;
         }
     };
     const int first = a.half ? a.substeps / 2 : a.substeps;
@@ -412,7 +484,7 @@ hipError_t q3_run(const Q3Args& a, int n0, int nsteps, hipStream_t stream) {
             diffuse(a.substeps - first);
         }
         hipLaunchKernelGGL(q3_update_kernel, grid, block, 0, stream, a, (const float*)cur, n);
-        hipLaunchKernelGGL(q3_resolve_kernel, grid, block, 0, stream, a, a.traj ? a.traj + i : nullptr, nsteps,
+        hipLaunchKernelGGL(q3_resolve_kernel, grid, block, 0, stream, a, n, a.traj ? a.traj + i : nullptr, nsteps,
                            i == nsteps - 1 ? a.live : nullptr);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

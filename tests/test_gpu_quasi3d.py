@@ -214,3 +214,26 @@ def test_ragged_lattice_and_batch(gga, model_dict):
             ref, certain = oracle_certain_prefix(prm, L, H, 10, ev, p, r, seed)
             assert certain >= 20
             assert np.array_equal(traj[p, r, :certain], ref[:certain]), (p, r)
+
+
+@pytest.mark.parametrize("substeps,half", [(13, False), (16, False), (20, False), (25, True), (37, False)])
+def test_sub_step_counts_and_chunks(gga, model_dict, substeps, half):
+    """More sub-steps per hour than one launch of the fused kernel takes at
+    the narrow tile (over 10: the wide tile; over 16: several launches per
+    run of sub-steps; with the half-hour split 12 + 13): still the 2D kernel's
+    results bit for bit at C = 1."""
+    L, H, R = 64, 60, 2
+    print(f"quasi-3D C=1 vs 2D, {substeps} sub-steps, half={half}", flush=True)
+    dose, gap, nfrac = protocols(half)
+    dd = _dev(dose, gap, nfrac)
+    cfg = gga.make_cfg(L, H, R, seed=21, substeps=substeps, dose_cap=20.0, half_hour=half)
+    live2, _, tr2 = gga.simulate(model_dict, cfg, *dd, traj=True)
+    live3, _, tr3 = gga.simulate_q3(model_dict, cfg, 1, *dd, traj=True)
+    torch.cuda.synchronize()
+    assert torch.equal(live2[:2], live3[:2]) and torch.equal(tr2[:2], tr3[:2])
+    f2, c2 = gga.state_init(model_dict, cfg, 3)
+    f3, c3 = gga.q3_init(model_dict, cfg, 1, 3)
+    gga.state_run(model_dict, cfg, *dd, 0, 30, f2, c2)
+    gga.q3_run(model_dict, cfg, 1, *dd, 0, 30, f3, c3)
+    torch.cuda.synchronize()
+    assert torch.equal(f2[:4], f3[:4]) and torch.equal(c2[:4], c3[:4, 0])

@@ -238,14 +238,29 @@ __global__ void __launch_bounds__(Q3_TILE_NT) q3_diffuse_tile_kernel(Q3Args a, c
     const int E = Q3_TILE + 2 * h;
     const float* S = src + (size_t)inst * 3 * L2;
     const float* Rg = a.react + (size_t)inst * L2;
-    for (int i = threadIdx.x; i < E * E; i += Q3_TILE_NT) {
-        const int ly = i / E, lx = i - ly * E;
-        const int gy = y0 + ly, gx = x0 + lx, o = ly * EMAX + lx;
-        const bool in = gy >= 0 && gy < L && gx >= 0 && gx < L;
-        const size_t g = (size_t)gy * L + gx;
+    // all of a thread's global loads are issued before its first LDS write
+    constexpr int LOADS = (EMAX * EMAX + Q3_TILE_NT - 1) / Q3_TILE_NT;
+    float ld[LOADS][4];
 #pragma unroll
-        for (int f = 0; f < 3; ++f) s_f[0][f][o] = in ? S[(size_t)f * L2 + g] : 0.0f;
-        s_r[o] = in ? Rg[g] : 0.0f;
+    for (int j = 0; j < LOADS; ++j) {
+        const int i = (int)threadIdx.x + j * Q3_TILE_NT;
+        const int ly = i / E, lx = i - ly * E;
+        const int gy = y0 + ly, gx = x0 + lx;
+        const bool in = i < E * E && gy >= 0 && gy < L && gx >= 0 && gx < L;
+        const size_t g = in ? (size_t)gy * L + gx : 0;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) ld[j][f] = in ? S[(size_t)f * L2 + g] : 0.0f;
+        ld[j][3] = in ? Rg[g] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < LOADS; ++j) {
+        const int i = (int)threadIdx.x + j * Q3_TILE_NT;
+        if (i < E * E) {
+            const int ly = i / E, o = ly * EMAX + (i - ly * E);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) s_f[0][f][o] = ld[j][f];
+            s_r[o] = ld[j][3];
+        }
     }
     float lam[3], cen[3], lo[2];
 #pragma unroll
@@ -256,22 +271,40 @@ __global__ void __launch_bounds__(Q3_TILE_NT) q3_diffuse_tile_kernel(Q3Args a, c
     lo[0] = to_field_units(a.prm, 0, 0.0);
     lo[1] = to_field_units(a.prm, 1, 0.0);
     __syncthreads();
+    // Sub-step k computes the w x w square starting at (k + 1, k + 1).  Each
+    // thread takes one column of it and a run of consecutive rows, walking
+    // down with the rows above and at the site kept in registers: three LDS
+    // reads per site and field (below, west, east) instead of five.
     int cur = 0;
     for (int k = 0; k < h; ++k) {
         const int r0 = k + 1, w = E - 2 * (k + 1);
-        for (int i = threadIdx.x; i < w * w; i += Q3_TILE_NT) {
-            const int qy = i / w;
-            const int ly = r0 + qy, lx = r0 + (i - qy * w);
-            const int gy = y0 + ly, gx = x0 + lx, o = ly * EMAX + lx;
-            const bool in = gy >= 0 && gy < L && gx >= 0 && gx < L;
-            const float R = s_r[o];
+        const int nseg = Q3_TILE_NT / w, rows = (w + nseg - 1) / nseg;
+        const int col = (int)threadIdx.x % w, seg = (int)threadIdx.x / w;
+        const int ly0 = r0 + seg * rows, ly1 = min(ly0 + rows, r0 + w);
+        if (seg < nseg && ly0 < ly1) {
+            const int lx = r0 + col, gx = x0 + lx;
+            const bool col_in = gx >= 0 && gx < L;
+            const float* c0 = s_f[cur][0];
+            const float* c1 = s_f[cur][1];
+            const float* c2 = s_f[cur][2];
+            int o = ly0 * EMAX + lx;
+            float up[3] = {c0[o - EMAX], c1[o - EMAX], c2[o - EMAX]};
+            float mid[3] = {c0[o], c1[o], c2[o]};
+            for (int ly = ly0; ly < ly1; ++ly, o += EMAX) {
+                const int gy = y0 + ly;
+                const bool in = col_in && gy >= 0 && gy < L;
+                const float R = s_r[o];
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                const float* c = s_f[cur][f];
-                const float sum = (c[o - EMAX] + c[o + EMAX]) + (c[o - 1] + c[o + 1]);
-                float v = fmaf(lam[f], sum, fmaf(c[o], cen[f], R));
-                if (f < 2) v = fmaxf(v, lo[f]);
-                s_f[cur ^ 1][f][o] = in ? v : 0.0f;
+                for (int f = 0; f < 3; ++f) {
+                    const float* c = f == 0 ? c0 : (f == 1 ? c1 : c2);
+                    const float below = c[o + EMAX];
+                    const float sum = (up[f] + below) + (c[o - 1] + c[o + 1]);
+                    float v = fmaf(lam[f], sum, fmaf(mid[f], cen[f], R));
+                    if (f < 2) v = fmaxf(v, lo[f]);
+                    s_f[cur ^ 1][f][o] = in ? v : 0.0f;
+                    up[f] = mid[f];
+                    mid[f] = below;
+                }
             }
         }
         __syncthreads();

@@ -224,7 +224,7 @@ __host__ __device__ inline unsigned q3_tiles_per_inst(int L) {
 
 template <int EMAX>
 __global__ void __launch_bounds__(Q3_TILE_NT) q3_diffuse_tile_kernel(Q3Args a, const float* src, float* dst, int h) {
-    __shared__ float s_f[2][3][EMAX * EMAX];
+    __shared__ float s_f[3][EMAX * EMAX];
     __shared__ float s_r[EMAX * EMAX];
     const int L = a.L, L2 = L * L;
     const int tpr = (L + Q3_TILE - 1) / Q3_TILE;
@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(Q3_TILE_NT) q3_diffuse_tile_kernel(Q3Args a, c
         if (i < E * E) {
             const int ly = i / E, o = ly * EMAX + (i - ly * E);
 #pragma unroll
-            for (int f = 0; f < 3; ++f) s_f[0][f][o] = ld[j][f];
+            for (int f = 0; f < 3; ++f) s_f[f][o] = ld[j][f];
             s_r[o] = ld[j][3];
         }
     }
@@ -272,43 +272,53 @@ __global__ void __launch_bounds__(Q3_TILE_NT) q3_diffuse_tile_kernel(Q3Args a, c
     lo[1] = to_field_units(a.prm, 1, 0.0);
     __syncthreads();
     // Sub-step k computes the w x w square starting at (k + 1, k + 1).  Each
-    // thread takes one column of it and a run of consecutive rows, walking
-    // down with the rows above and at the site kept in registers: three LDS
-    // reads per site and field (below, west, east) instead of five.
-    int cur = 0;
+    // thread takes one column of it and a run of at most RUN consecutive rows,
+    // walking down with the rows above and at the site in registers (three LDS
+    // reads per site and field: below, west, east); the new values wait in
+    // registers until every thread has read the old ones, so one LDS copy of
+    // the fields serves (more workgroups per CU).
+    constexpr int RUN = EMAX <= 52 ? 5 : 8;    // ceil(w / (Q3_TILE_NT / w)) for w <= EMAX - 2
     for (int k = 0; k < h; ++k) {
         const int r0 = k + 1, w = E - 2 * (k + 1);
         const int nseg = Q3_TILE_NT / w, rows = (w + nseg - 1) / nseg;
         const int col = (int)threadIdx.x % w, seg = (int)threadIdx.x / w;
         const int ly0 = r0 + seg * rows, ly1 = min(ly0 + rows, r0 + w);
-        if (seg < nseg && ly0 < ly1) {
-            const int lx = r0 + col, gx = x0 + lx;
+        const bool act = seg < nseg && ly0 < ly1;
+        const int lx = r0 + col, gx = x0 + lx;
+        float nv[RUN][3];
+        if (act) {
             const bool col_in = gx >= 0 && gx < L;
-            const float* c0 = s_f[cur][0];
-            const float* c1 = s_f[cur][1];
-            const float* c2 = s_f[cur][2];
             int o = ly0 * EMAX + lx;
-            float up[3] = {c0[o - EMAX], c1[o - EMAX], c2[o - EMAX]};
-            float mid[3] = {c0[o], c1[o], c2[o]};
-            for (int ly = ly0; ly < ly1; ++ly, o += EMAX) {
-                const int gy = y0 + ly;
-                const bool in = col_in && gy >= 0 && gy < L;
-                const float R = s_r[o];
+            float up[3] = {s_f[0][o - EMAX], s_f[1][o - EMAX], s_f[2][o - EMAX]};
+            float mid[3] = {s_f[0][o], s_f[1][o], s_f[2][o]};
 #pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    const float* c = f == 0 ? c0 : (f == 1 ? c1 : c2);
-                    const float below = c[o + EMAX];
-                    const float sum = (up[f] + below) + (c[o - 1] + c[o + 1]);
-                    float v = fmaf(lam[f], sum, fmaf(mid[f], cen[f], R));
-                    if (f < 2) v = fmaxf(v, lo[f]);
-                    s_f[cur ^ 1][f][o] = in ? v : 0.0f;
-                    up[f] = mid[f];
-                    mid[f] = below;
+            for (int q = 0; q < RUN; ++q, o += EMAX) {
+                if (ly0 + q < ly1) {
+                    const int gy = y0 + ly0 + q;
+                    const bool in = col_in && gy >= 0 && gy < L;
+                    const float R = s_r[o];
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        const float below = s_f[f][o + EMAX];
+                        const float sum = (up[f] + below) + (s_f[f][o - 1] + s_f[f][o + 1]);
+                        float v = fmaf(lam[f], sum, fmaf(mid[f], cen[f], R));
+                        if (f < 2) v = fmaxf(v, lo[f]);
+                        nv[q][f] = in ? v : 0.0f;
+                        up[f] = mid[f];
+                        mid[f] = below;
+                    }
                 }
             }
         }
         __syncthreads();
-        cur ^= 1;
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < RUN; ++q)
+                if (ly0 + q < ly1)
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) s_f[f][(ly0 + q) * EMAX + lx] = nv[q][f];
+        }
+        __syncthreads();
     }
     float* D = dst + (size_t)inst * 3 * L2;
     for (int i = threadIdx.x; i < Q3_TILE * Q3_TILE; i += Q3_TILE_NT) {
@@ -318,7 +328,7 @@ __global__ void __launch_bounds__(Q3_TILE_NT) q3_diffuse_tile_kernel(Q3Args a, c
         if (gy >= L || gx >= L) continue;
         const size_t g = (size_t)gy * L + gx;
 #pragma unroll
-        for (int f = 0; f < 3; ++f) D[(size_t)f * L2 + g] = s_f[cur][f][ly * EMAX + lx];
+        for (int f = 0; f < 3; ++f) D[(size_t)f * L2 + g] = s_f[f][ly * EMAX + lx];
     }
 }
 

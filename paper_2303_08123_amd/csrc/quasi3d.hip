@@ -380,12 +380,19 @@ __global__ void __launch_bounds__(Q3_NT) q3_update_kernel(Q3Args a, const float*
     uint16_t* cw = a.cells + (size_t)inst * C * L2;
     uint32_t* pr = a.prop + (size_t)inst * C * L2;
     const uint32_t T_div = s_k.T_div;
-    uint32_t proposed = 0;
-    for (int z = 0; z < C; ++z) {
-        const size_t at = (size_t)z * L2 + site;
-        const uint32_t w = cw[at];
+    // All of the site's words are loaded first (independent loads, issued
+    // together; the loop is unrolled to the slot limit so they stay in
+    // registers), then the transitions; the Philox blocks are drawn only for the
+    // candidates, taken from bit masks.
+    uint32_t wv[Q3_MAX_SLOTS];
+#pragma unroll
+    for (int z = 0; z < Q3_MAX_SLOTS; ++z) wv[z] = z < C ? (uint32_t)cw[(size_t)z * L2 + site] : 0u;
+    uint32_t cand = 0, marked = 0;
+#pragma unroll
+    for (int z = 0; z < Q3_MAX_SLOTS; ++z) {
+        const uint32_t w = wv[z];
         const uint32_t st = w & 3u, age = (w >> 2) & 255u, doom = w & DOOM_BIT;
-        if (st == EMPTY) continue;
+        if (z >= C || st == EMPTY) continue;
         const uint32_t older = age < 255u ? age + 1u : 255u;
         uint32_t out;
         if (st == DEAD) {
@@ -397,32 +404,36 @@ __global__ void __launch_bounds__(Q3_NT) q3_update_kernel(Q3Args a, const float*
         } else {
             out = (uint32_t)PROLIF | (older << 2) | doom;
             if ((int)age >= P.T_min) {
-                const uint32_t idx = (uint32_t)(z * L2 + site);
-                if (P.mitotic_death && doom) {           // a marked cell dies when ready
-                    const Block4 b = philox10(idx, (uint32_t)n, (uint32_t)r, (uint32_t)p, a.seed_lo, a.seed_hi);
-                    if (b.w3 < T_div) out = DEAD;
-                } else if (m >= 1u) {
-                    const Block4 b = philox10(idx, (uint32_t)n, (uint32_t)r, (uint32_t)p, a.seed_lo, a.seed_hi);
-                    if (b.w3 < T_div) {
-                        uint32_t k = (uint32_t)(((uint64_t)b.w0 * m) >> 32);
-                        int g = 0;
-                        while (g < 4 && k >= (uint32_t)__builtin_popcount(gm[g])) k -= (uint32_t)__builtin_popcount(gm[g++]);
-                        const int t = site + (g == 1 ? -L : g == 2 ? 1 : g == 3 ? L : g == 4 ? -1 : 0);
-                        uint32_t free_slots = gm[g];
-                        for (; k; --k) free_slots &= free_slots - 1;      // the k-th EMPTY slot of site t
-                        const int tz = __builtin_ctz(free_slots);
-                        const uint32_t code = (g == 0 ? 4u : g == 1 ? 2u : g == 2 ? 3u : g == 3 ? 0u : 1u);
-                        const uint32_t low = (code << 5) | (uint32_t)z;
-                        const uint32_t target = (uint32_t)(tz * L2 + t);
-                        atomicMin(ky + target, ((unsigned long long)(b.w2 >> 3) << 8) | low);
-                        atomicOr(t_now + t, 1u << tz);
-                        pr[at] = (target << 8) | low;
-                        proposed |= 1u << z;
-                    }
-                }
+                if (P.mitotic_death && doom) marked |= 1u << z;     // a marked cell dies when ready
+                else if (m >= 1u) cand |= 1u << z;
             }
         }
-        if (out != w) cw[at] = (uint16_t)out;
+        if (out != w) cw[(size_t)z * L2 + site] = (uint16_t)out;
+    }
+    uint32_t proposed = 0;
+    for (uint32_t cm = cand | marked; cm; cm &= cm - 1) {
+        const int z = __builtin_ctz(cm);
+        const size_t at = (size_t)z * L2 + site;
+        const Block4 b = philox10((uint32_t)at, (uint32_t)n, (uint32_t)r, (uint32_t)p, a.seed_lo, a.seed_hi);
+        if (b.w3 >= T_div) continue;
+        if ((marked >> z) & 1u) {
+            cw[at] = (uint16_t)DEAD;
+            continue;
+        }
+        uint32_t k = (uint32_t)(((uint64_t)b.w0 * m) >> 32);
+        int g = 0;
+        while (g < 4 && k >= (uint32_t)__builtin_popcount(gm[g])) k -= (uint32_t)__builtin_popcount(gm[g++]);
+        const int t = site + (g == 1 ? -L : g == 2 ? 1 : g == 3 ? L : g == 4 ? -1 : 0);
+        uint32_t free_slots = gm[g];
+        for (; k; --k) free_slots &= free_slots - 1;      // the k-th EMPTY slot of site t
+        const int tz = __builtin_ctz(free_slots);
+        const uint32_t code = (g == 0 ? 4u : g == 1 ? 2u : g == 2 ? 3u : g == 3 ? 0u : 1u);
+        const uint32_t low = (code << 5) | (uint32_t)z;
+        const uint32_t target = (uint32_t)(tz * L2 + t);
+        atomicMin(ky + target, ((unsigned long long)(b.w2 >> 3) << 8) | low);
+        atomicOr(t_now + t, 1u << tz);
+        pr[at] = (target << 8) | low;
+        proposed |= 1u << z;
     }
     a.pmask[(size_t)inst * L2 + site] = proposed;
 }

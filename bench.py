@@ -531,11 +531,12 @@ def q3_bytes_per_site_step(C):
     the fused sub-steps read three fields and the reaction term and write three
     fields once (28 B); the cell update reads the C words, three fields, the
     site's EMPTY mask and the previous step's targeted mask and writes that
-    mask, the changed words (counted as all C) and the proposer mask
-    (28 + 4 C); the resolution reads the targeted and proposer masks and the C
-    words and writes the EMPTY mask and the reaction term (16 + 2 C).  Keys,
-    proposals and births (a few per site and step) are not counted."""
-    return 28 + (28 + 4 * C) + (16 + 2 * C)
+    mask, the changed words (counted as all C), the proposer mask and the
+    8-byte vector of slot states (36 + 4 C); the resolution reads the targeted
+    and proposer masks and the state vector and writes the EMPTY mask and the
+    reaction term (24 B).  Keys, proposals and births (a few per site and step)
+    are not counted."""
+    return 28 + (36 + 4 * C) + 24
 
 
 def q3_cpu_baseline(md, wl, dose, gap, nfrac, n_replicas=2):

@@ -1481,8 +1481,8 @@ bool q3_grid_ok(int32_t L, long long n_inst) {
 }
 
 struct Q3Plan {
-    size_t off_step, off_frac, off_f2, off_react, off_emask, off_tmask, off_pmask, off_keys, off_prop, off_fields,
-        off_cells, total;
+    size_t off_step, off_frac, off_f2, off_react, off_emask, off_tmask, off_pmask, off_svec, off_keys, off_prop,
+        off_fields, off_cells, total;
 };
 
 Q3Plan q3_plan(int32_t L, int32_t C, int32_t P, int32_t R, int32_t K) {
@@ -1503,6 +1503,8 @@ Q3Plan q3_plan(int32_t L, int32_t C, int32_t P, int32_t R, int32_t K) {
     o += align256(sizeof(uint32_t) * 2 * L2 * n);
     q.off_pmask = o;
     o += align256(sizeof(uint32_t) * L2 * n);
+    q.off_svec = o;
+    o += align256(sizeof(unsigned long long) * L2 * n);
     q.off_keys = o;
     o += align256(sizeof(unsigned long long) * CL2 * n);
     q.off_prop = o;
@@ -1552,6 +1554,7 @@ hipError_t q3_enqueue(gga::Q3Args a, const gga_params* prm, const gga_sim_cfg* c
     a.emask = reinterpret_cast<uint32_t*>(ws + q.off_emask);
     a.tmask = reinterpret_cast<uint32_t*>(ws + q.off_tmask);
     a.pmask = reinterpret_cast<uint32_t*>(ws + q.off_pmask);
+    a.svec = reinterpret_cast<unsigned long long*>(ws + q.off_svec);
     a.keys = reinterpret_cast<unsigned long long*>(ws + q.off_keys);
     a.prop = reinterpret_cast<uint32_t*>(ws + q.off_prop);
     if (init && (e = gga::q3_init(a, stream)) != hipSuccess) return e;

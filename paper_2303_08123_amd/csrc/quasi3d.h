@@ -24,6 +24,7 @@ struct Q3Args {
     uint32_t* emask;                        // [inst][L][L] EMPTY slots of the site (bit z)
     uint32_t* tmask;                        // [2][inst][L][L] slots targeted by a proposal, by step parity
     uint32_t* pmask;                        // [inst][L][L] slots whose cell proposed this step
+    unsigned long long* svec;               // [inst][L][L] slot states after the cell update, 2 bits each
     unsigned long long* keys;               // [inst][C][L][L] smallest proposal key of a targeted slot;
                                             // all ones on every other slot
     uint32_t* prop;                         // [inst][C][L][L] a proposer's target slot << 8 | its code

@@ -388,6 +388,7 @@ __global__ void __launch_bounds__(Q3_NT) q3_update_kernel(Q3Args a, const float*
 #pragma unroll
     for (int z = 0; z < Q3_MAX_SLOTS; ++z) wv[z] = z < C ? (uint32_t)cw[(size_t)z * L2 + site] : 0u;
     uint32_t cand = 0, marked = 0;
+    unsigned long long states = 0;          // 2 bits per slot, for the resolution
 #pragma unroll
     for (int z = 0; z < Q3_MAX_SLOTS; ++z) {
         const uint32_t w = wv[z];
@@ -409,6 +410,7 @@ __global__ void __launch_bounds__(Q3_NT) q3_update_kernel(Q3Args a, const float*
             }
         }
         if (out != w) cw[(size_t)z * L2 + site] = (uint16_t)out;
+        states |= (unsigned long long)(out & 3u) << (2 * z);
     }
     uint32_t proposed = 0;
     for (uint32_t cm = cand | marked; cm; cm &= cm - 1) {
@@ -418,6 +420,7 @@ __global__ void __launch_bounds__(Q3_NT) q3_update_kernel(Q3Args a, const float*
         if (b.w3 >= T_div) continue;
         if ((marked >> z) & 1u) {
             cw[at] = (uint16_t)DEAD;
+            states |= (unsigned long long)DEAD << (2 * z);
             continue;
         }
         uint32_t k = (uint32_t)(((uint64_t)b.w0 * m) >> 32);
@@ -436,12 +439,14 @@ __global__ void __launch_bounds__(Q3_NT) q3_update_kernel(Q3Args a, const float*
         proposed |= 1u << z;
     }
     a.pmask[(size_t)inst * L2 + site] = proposed;
+    a.svec[(size_t)inst * L2 + site] = states;
 }
 
 // Births and winners: a targeted slot takes the daughter (PROLIF, age 0), a
-// proposer whose code holds its target's key is the parent (age 0).  Then the
-// next step's reaction term and EMPTY mask, and the live count added to
-// traj_col[inst * traj_stride] and live[inst] (either may be null).
+// proposer whose code holds its target's key is the parent (age 0).  Then,
+// from the update's slot states with the births applied (no word is read
+// again), the next step's reaction term and EMPTY mask, and the live count
+// added to traj_col[inst * traj_stride] and live[inst] (either may be null).
 __global__ void __launch_bounds__(Q3_NT) q3_resolve_kernel(Q3Args a, int n, int32_t* traj_col, int traj_stride,
                                                           int32_t* live) {
     int inst, site;
@@ -458,8 +463,11 @@ __global__ void __launch_bounds__(Q3_NT) q3_resolve_kernel(Q3Args a, int n, int3
         uint16_t* cw = a.cells + (size_t)inst * C * L2;
         const uint32_t* pr = a.prop + (size_t)inst * C * L2;
         const unsigned long long* ky = a.keys + (size_t)inst * C * L2;
-        for (uint32_t tm = a.tmask[(n & 1) * plane + at0]; tm; tm &= tm - 1)
+        unsigned long long states = a.svec[at0];
+        for (uint32_t tm = a.tmask[(n & 1) * plane + at0]; tm; tm &= tm - 1) {
             cw[(size_t)__builtin_ctz(tm) * L2 + site] = PROLIF;
+            states |= (unsigned long long)PROLIF << (2 * __builtin_ctz(tm));    // the slot was EMPTY
+        }
         for (uint32_t pm = a.pmask[at0]; pm; pm &= pm - 1) {
             const size_t at = (size_t)__builtin_ctz(pm) * L2 + site;
             const uint32_t pp = pr[at];
@@ -467,8 +475,8 @@ __global__ void __launch_bounds__(Q3_NT) q3_resolve_kernel(Q3Args a, int n, int3
         }
         uint32_t em = 0;
         float acc = 0.0f;
-        for (int z = 0; z < C; ++z) {
-            const uint32_t st = cw[(size_t)z * L2 + site] & 3u;
+        for (int z = 0; z < C; ++z) {              // winners keep their state: the vector is final
+            const uint32_t st = (uint32_t)(states >> (2 * z)) & 3u;
             if (st == EMPTY) em |= 1u << z;
             cnt += (st == PROLIF || st == QUIESC);
             acc = z == 0 ? s_react[st] : acc + s_react[st];

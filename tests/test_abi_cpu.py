@@ -194,9 +194,9 @@ def test_quasi3d_arguments_are_checked_before_any_launch(gga):
     fake, odd = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1008)
     ws = gga.LIB.gga_q3_workspace_bytes(128, 8, 4, 2, 3)
     # event table, then per instance and site: fields twice, reaction term, the
-    # EMPTY, targeted (two) and proposer masks, and per slot a word, a 64-bit
-    # key and a 32-bit proposal
-    per = 128 * 128 * (12 * 2 + 4 + 4 * 4 + 8 * (2 + 8 + 4))
+    # EMPTY, targeted (two) and proposer masks, the 2-bit slot states, and per
+    # slot a word, a 64-bit key and a 32-bit proposal
+    per = 128 * 128 * (12 * 2 + 4 + 4 * 4 + 8 + 8 * (2 + 8 + 4))
     assert per * 8 <= ws <= per * 8 + 12 * 256 + 4 * 3 * 24
     for L, C in ((128, 0), (128, 33), (4, 1), (1024, 8)):
         assert gga.LIB.gga_q3_workspace_bytes(L, C, 4, 2, 3) == 0

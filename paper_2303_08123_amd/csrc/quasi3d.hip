@@ -14,9 +14,9 @@
 //
 // Layout and launches.  The state of instance i is fields[i][3][L][L] and
 // cells[i][C][L][L]: slot planes, so that for every slot the 64 lanes of a
-// wave touch 64 consecutive sites.  A slot column of a 128^2 lattice with 8
-// slots is 256 KiB of words plus 192 KiB of fields, more than a compute unit's
-// LDS, so the state stays in device memory and a step is a chain of launches
+// wave touch 64 consecutive sites.  An instance on a 128^2 lattice with 8
+// slots holds 256 KiB of words plus 192 KiB of fields, more than a compute
+// unit's LDS, so the state stays in device memory and a step is a chain of launches
 // over all instances at once: fraction, the FTCS sub-steps (fused in LDS
 // tiles, two field buffers), a fraction at the half hour, cell update,
 // resolution.  The per-site launches have one thread per site; an instance's

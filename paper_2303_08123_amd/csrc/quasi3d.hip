@@ -151,6 +151,35 @@ __global__ void __launch_bounds__(Q3_NT) q3_prepare_kernel(Q3Args a, int count) 
     if (count) block_count(cnt, a.live ? a.live + inst : nullptr, s_part);
 }
 
+// Index of protocol p's fraction at half-hour tau in its event table, or -1
+// (bisection over the increasing times).
+__device__ __forceinline__ int find_fraction(const Q3Args& a, int p, int tau) {
+    const int32_t* st = a.ev_step + (size_t)p * a.K;
+    const int cnt = a.ev_count[p];
+    int lo = 0, hi = cnt;
+    while (lo < hi) {
+        const int md = (lo + hi) >> 1;
+        if (st[md] < tau) lo = md + 1; else hi = md;
+    }
+    return (lo < cnt && st[lo] == tau) ? lo : -1;
+}
+
+// Survival thresholds of fraction j of protocol p by class (and oxygen bin
+// with the oxygen effect) into s_thr; threads 0 .. 63 of the block.
+__device__ __forceinline__ void fraction_thresholds(const Q3Args& a, int p, int j, uint32_t (*s_thr)[GGA_OER_BINS]) {
+    const gga_params& P = a.prm;
+    const EventFraction ef = a.ev_frac[(size_t)p * a.K + j];
+    if (P.oer_max > 1.0) {
+        if (threadIdx.x < 4 * GGA_OER_BINS) {
+            const int c = threadIdx.x / GGA_OER_BINS, b = threadIdx.x % GGA_OER_BINS;
+            const double f = oxygen_modification(P, b);
+            s_thr[c][b] = lq_threshold(f * (double)ef.dose, P.m[c], P.alpha, P.beta, f * ef.prior);
+        }
+    } else if (threadIdx.x < 4) {
+        s_thr[threadIdx.x][0] = lq_threshold((double)ef.dose, P.m[threadIdx.x], P.alpha, P.beta, ef.prior);
+    }
+}
+
 // A fraction at half-hour 2n + mid of the protocol, if there is one: every live
 // cell survives iff its w1 < T[class] (with the oxygen effect T[class][bin of
 // the site's O in F]); a killed cell becomes DEAD, or is marked with mitotic
@@ -164,31 +193,12 @@ __global__ void __launch_bounds__(Q3_NT) q3_fraction_kernel(Q3Args a, const floa
     __shared__ uint32_t s_thr[4][GGA_OER_BINS];
     __shared__ float s_react[4];
     const gga_params& P = a.prm;
-    if (threadIdx.x == 0) {                       // the fraction at this half-hour, by bisection
-        const int32_t* st = a.ev_step + (size_t)p * a.K;
-        const int cnt = a.ev_count[p];
-        const int tau = 2 * n + mid;
-        int lo = 0, hi = cnt;
-        while (lo < hi) {
-            const int md = (lo + hi) >> 1;
-            if (st[md] < tau) lo = md + 1; else hi = md;
-        }
-        s_j = (lo < cnt && st[lo] == tau) ? lo : -1;
-    }
+    if (threadIdx.x == 0) s_j = find_fraction(a, p, 2 * n + mid);
     __syncthreads();
     const int j = s_j;
     if (j < 0) return;                            // block-uniform
-    const EventFraction ef = a.ev_frac[(size_t)p * a.K + j];
     const bool oer = P.oer_max > 1.0;
-    if (oer) {
-        if (threadIdx.x < 4 * GGA_OER_BINS) {
-            const int c = threadIdx.x / GGA_OER_BINS, b = threadIdx.x % GGA_OER_BINS;
-            const double f = oxygen_modification(P, b);
-            s_thr[c][b] = lq_threshold(f * (double)ef.dose, P.m[c], P.alpha, P.beta, f * ef.prior);
-        }
-    } else if (threadIdx.x < 4) {
-        s_thr[threadIdx.x][0] = lq_threshold((double)ef.dose, P.m[threadIdx.x], P.alpha, P.beta, ef.prior);
-    }
+    fraction_thresholds(a, p, j, s_thr);
     set_react_table(P, s_react);
     __syncthreads();
     const int L2 = a.L * a.L, C = a.C;
@@ -445,17 +455,29 @@ __global__ void __launch_bounds__(Q3_NT) q3_update_kernel(Q3Args a, const float*
 // Births and winners: a targeted slot takes the daughter (PROLIF, age 0), a
 // proposer whose code holds its target's key is the parent (age 0).  Then,
 // from the update's slot states with the births applied (no word is read
-// again), the next step's reaction term and EMPTY mask, and the live count
-// added to traj_col[inst * traj_stride] and live[inst] (either may be null).
+// again), the live count added to traj_col[inst * traj_stride] and live[inst]
+// (either may be null); with `next` set, the start-of-hour fraction of step
+// n + 1 if the protocol has one (as q3_fraction_kernel applies it, from the
+// fields F that step starts from); and the next step's reaction term and
+// EMPTY mask.
 __global__ void __launch_bounds__(Q3_NT) q3_resolve_kernel(Q3Args a, int n, int32_t* traj_col, int traj_stride,
-                                                          int32_t* live) {
+                                                          int32_t* live, const float* F, int next) {
     int inst, site;
     if (!q3_place(a, inst, site)) return;
-    if (!a.ev_valid[inst / a.R]) return;
+    const int p = inst / a.R, r = inst - p * a.R;
+    if (!a.ev_valid[p]) return;
     __shared__ float s_react[4];
     __shared__ int s_part[Q3_NT / 64];
+    __shared__ int s_j;
+    __shared__ uint32_t s_thr[4][GGA_OER_BINS];
     set_react_table(a.prm, s_react);
+    if (threadIdx.x == 0) s_j = next ? find_fraction(a, p, 2 * (n + 1)) : -1;
     __syncthreads();
+    const int j = s_j;                            // step n + 1's fraction at the start of its hour
+    if (j >= 0) {
+        fraction_thresholds(a, p, j, s_thr);
+        __syncthreads();                          // block-uniform
+    }
     const int L2 = a.L * a.L, C = a.C;
     int cnt = 0;
     if (site < L2) {
@@ -473,12 +495,38 @@ __global__ void __launch_bounds__(Q3_NT) q3_resolve_kernel(Q3Args a, int n, int3
             const uint32_t pp = pr[at];
             if ((uint32_t)(ky[pp >> 8] & 0xFFu) == (pp & 0xFFu)) cw[at] = (uint16_t)((cw[at] & DOOM_BIT) | PROLIF);
         }
-        uint32_t em = 0;
-        float acc = 0.0f;
         for (int z = 0; z < C; ++z) {              // winners keep their state: the vector is final
             const uint32_t st = (uint32_t)(states >> (2 * z)) & 3u;
-            if (st == EMPTY) em |= 1u << z;
             cnt += (st == PROLIF || st == QUIESC);
+        }
+        if (j >= 0) {
+            // step n + 1's start-of-hour fraction on the counted states: every
+            // live cell survives iff its w1 < T[class] (and oxygen bin of the
+            // site's O in F, the fields step n + 1 starts from)
+            const bool oer = a.prm.oer_max > 1.0;
+            const int bin = oer ? oxygen_bin(F[(size_t)inst * 3 * L2 + site], a.prm) : 0;
+            for (int z = 0; z < C; ++z) {
+                const uint32_t st = (uint32_t)(states >> (2 * z)) & 3u;
+                if (st != PROLIF && st != QUIESC) continue;
+                const size_t at = (size_t)z * L2 + site;
+                const uint32_t w = cw[at];
+                const Block4 b = philox10((uint32_t)at, (uint32_t)(n + 1), (uint32_t)r, (uint32_t)p, a.seed_lo,
+                                          a.seed_hi);
+                if (b.w1 >= s_thr[sens_class(w, a.prm)][bin]) {
+                    if (a.prm.mitotic_death) {
+                        cw[at] = (uint16_t)(w | DOOM_BIT);
+                    } else {
+                        cw[at] = (uint16_t)DEAD;
+                        states |= (unsigned long long)DEAD << (2 * z);
+                    }
+                }
+            }
+        }
+        uint32_t em = 0;
+        float acc = 0.0f;
+        for (int z = 0; z < C; ++z) {
+            const uint32_t st = (uint32_t)(states >> (2 * z)) & 3u;
+            if (st == EMPTY) em |= 1u << z;
             acc = z == 0 ? s_react[st] : acc + s_react[st];
         }
         a.emask[at0] = em;
@@ -537,9 +585,11 @@ hipError_t q3_run(const Q3Args& a, int n0, int nsteps, hipStream_t stream) {
         }
     };
     const int first = a.half ? a.substeps / 2 : a.substeps;
+    // the start-of-hour fraction of step n0 here; those of later steps are
+    // applied by the previous step's resolution
+    if (nsteps > 0) hipLaunchKernelGGL(q3_fraction_kernel, grid, block, 0, stream, a, (const float*)cur, n0, 0);
     for (int i = 0; i < nsteps; ++i) {
         const int n = n0 + i;
-        hipLaunchKernelGGL(q3_fraction_kernel, grid, block, 0, stream, a, (const float*)cur, n, 0);
         diffuse(first);
         if (a.half) {
             hipLaunchKernelGGL(q3_fraction_kernel, grid, block, 0, stream, a, (const float*)cur, n, 1);
@@ -547,7 +597,7 @@ hipError_t q3_run(const Q3Args& a, int n0, int nsteps, hipStream_t stream) {
         }
         hipLaunchKernelGGL(q3_update_kernel, grid, block, 0, stream, a, (const float*)cur, n);
         hipLaunchKernelGGL(q3_resolve_kernel, grid, block, 0, stream, a, n, a.traj ? a.traj + i : nullptr, nsteps,
-                           i == nsteps - 1 ? a.live : nullptr);
+                           i == nsteps - 1 ? a.live : nullptr, (const float*)cur, i + 1 < nsteps ? 1 : 0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

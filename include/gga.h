@@ -452,6 +452,15 @@ int gga_slots_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga
 size_t gga_mlp_net_bytes(void);
 size_t gga_mlp_work_bytes(int32_t B);
 
+/* Test hook: byte offsets into a work buffer of batch B (B >= 0) of what the
+ * passes leave there, written to offsets[12] (host): X bf16[B][128] (encoded
+ * inputs), Z1, Z2, Z3 f32[B][512] (pre-activations), H1, H2, H3 bf16[B][512]
+ * (activations), y f32[B] (outputs), dy f32[B] (loss gradient), dZa, dZb
+ * bf16[B][512] (backward activation gradients), part (reduction partials).
+ * After gga_mlp_grad, dZa holds dZ1 and dZb holds dZ2; Z3 is overwritten by
+ * weight-gradient partials when B >= 1024.  Host only.  Errors: GGA_E_ARG. */
+int gga_mlp_work_layout(int32_t B, size_t* offsets);
+
 /* Initialise: weights uniform on +-1/sqrt(fan_in) from Philox keyed by seed,
  * biases and Adam state 0, norm (0, 1).  Synchronous.  Errors: GGA_E_ARG,
  * GGA_E_HIP. */

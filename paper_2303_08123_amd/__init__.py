@@ -115,6 +115,7 @@ def _load():
                         vp, vp, vp, vp], ctypes.c_int),
         "gga_mlp_net_bytes": ([], ctypes.c_size_t),
         "gga_mlp_work_bytes": ([i32], ctypes.c_size_t),
+        "gga_mlp_work_layout": ([i32, vp], ctypes.c_int),
         "gga_mlp_init": ([vp, u64, vp], ctypes.c_int),
         "gga_mlp_set_norm": ([vp, vp, i32, vp], ctypes.c_int),
         "gga_mlp_predict": ([vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
@@ -169,7 +170,8 @@ LIB = _load()
 EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
            "gga_population_random", "gga_simulate", "gga_state_init", "gga_state_run",
            "gga_philox_fill", "gga_ga_breed", "gga_ga_workspace_bytes", "gga_ga_set_generation",
-           "gga_ga_generation", "gga_ga_run", "gga_mlp_net_bytes", "gga_mlp_work_bytes", "gga_mlp_init",
+           "gga_ga_generation", "gga_ga_run", "gga_mlp_net_bytes", "gga_mlp_work_bytes", "gga_mlp_work_layout",
+           "gga_mlp_init",
            "gga_mlp_set_norm", "gga_mlp_predict", "gga_mlp_grad", "gga_mlp_train_step", "gga_mlp_gemm",
            "gga_sga_workspace_bytes", "gga_sga_init", "gga_sga_generation", "gga_sga_run",
            "gga_variant_count", "gga_variant_side", "gga_variant_is_slab", "gga_variant_name", "gga_get_variant",
@@ -749,6 +751,25 @@ def mlp_split(flat):
 
 def mlp_work(B, device="cuda"):
     return torch.empty(max(int(LIB.gga_mlp_work_bytes(B)), 1), dtype=torch.uint8, device=device)
+
+
+MLP_WORK_PARTS = ("X", "Z1", "Z2", "Z3", "H1", "H2", "H3", "y", "dy", "dZa", "dZb")
+
+
+def mlp_work_views(work, B):
+    """Views of what the MLP passes leave in a work buffer of batch B (test
+    hook): X, H1..H3, dZa, dZb as bfloat16, the rest float32 (layout from
+    gga_mlp_work_layout)."""
+    off = (ctypes.c_size_t * 12)()
+    _check(LIB.gga_mlp_work_layout(int(B), off))
+    shapes = {"X": (B, MLP_IN), "y": (B,), "dy": (B,)}
+    out = {}
+    for i, name in enumerate(MLP_WORK_PARTS):
+        shape = shapes.get(name, (B, MLP_HID))
+        half = name in ("X", "H1", "H2", "H3", "dZa", "dZb")
+        n = int(np.prod(shape)) * (2 if half else 4)
+        out[name] = work[off[i]:off[i] + n].view(torch.bfloat16 if half else torch.float32).view(shape)
+    return out
 
 
 def mlp_set_norm(net, target, stream=None):

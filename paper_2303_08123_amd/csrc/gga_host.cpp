@@ -752,26 +752,38 @@ MlpNet mlp_net(void* base) {
     return n;
 }
 
-size_t mlp_work_bytes(int B) {
+// Byte offsets of X, Z[3], H[3], y, dy, dZ[2] and part in a work buffer of batch B.
+void mlp_work_offsets(int B, size_t (&off)[12]) {
     const size_t b = static_cast<size_t>(B);
-    return align256(2 * b * MLP_IN) + 3 * align256(4 * b * MLP_HID) + 3 * align256(2 * b * MLP_HID) +
-           2 * align256(4 * b) + 2 * align256(2 * b * MLP_HID) + align256(4 * MLP_RED_CHUNKS * (MLP_HID + 1));
+    size_t at = 0;
+    auto take = [&](size_t bytes) { const size_t o = at; at += align256(bytes); return o; };
+    off[0] = take(2 * b * MLP_IN);
+    for (int l = 0; l < 3; ++l) off[1 + l] = take(4 * b * MLP_HID);
+    for (int l = 0; l < 3; ++l) off[4 + l] = take(2 * b * MLP_HID);
+    off[7] = take(4 * b);
+    off[8] = take(4 * b);
+    for (int l = 0; l < 2; ++l) off[9 + l] = take(2 * b * MLP_HID);
+    off[11] = take(4 * MLP_RED_CHUNKS * (MLP_HID + 1));
+}
+
+size_t mlp_work_bytes(int B) {
+    size_t off[12];
+    mlp_work_offsets(B, off);
+    return off[11] + align256(4 * MLP_RED_CHUNKS * (MLP_HID + 1));
 }
 
 MlpWork mlp_work(void* base, int B) {
-    const size_t b = static_cast<size_t>(B);
+    size_t off[12];
+    mlp_work_offsets(B, off);
     char* c = static_cast<char*>(base);
     MlpWork w{};
-    w.X = reinterpret_cast<__bf16*>(c);
-    c += align256(2 * b * MLP_IN);
-    for (int l = 0; l < 3; ++l) { w.Z[l] = reinterpret_cast<float*>(c); c += align256(4 * b * MLP_HID); }
-    for (int l = 0; l < 3; ++l) { w.H[l] = reinterpret_cast<__bf16*>(c); c += align256(2 * b * MLP_HID); }
-    w.y = reinterpret_cast<float*>(c);
-    c += align256(4 * b);
-    w.dy = reinterpret_cast<float*>(c);
-    c += align256(4 * b);
-    for (int l = 0; l < 2; ++l) { w.dZ[l] = reinterpret_cast<__bf16*>(c); c += align256(2 * b * MLP_HID); }
-    w.part = reinterpret_cast<float*>(c);
+    w.X = reinterpret_cast<__bf16*>(c + off[0]);
+    for (int l = 0; l < 3; ++l) w.Z[l] = reinterpret_cast<float*>(c + off[1 + l]);
+    for (int l = 0; l < 3; ++l) w.H[l] = reinterpret_cast<__bf16*>(c + off[4 + l]);
+    w.y = reinterpret_cast<float*>(c + off[7]);
+    w.dy = reinterpret_cast<float*>(c + off[8]);
+    for (int l = 0; l < 2; ++l) w.dZ[l] = reinterpret_cast<__bf16*>(c + off[9 + l]);
+    w.part = reinterpret_cast<float*>(c + off[11]);
     return w;
 }
 
@@ -795,6 +807,14 @@ extern "C" {
 size_t gga_mlp_net_bytes(void) { return gga::mlp_net_bytes(); }
 
 size_t gga_mlp_work_bytes(int32_t B) { return B < 0 ? 0 : gga::mlp_work_bytes(B); }
+
+int gga_mlp_work_layout(int32_t B, size_t* offsets) {
+    if (B < 0 || !offsets) return GGA_E_ARG;
+    size_t off[12];
+    gga::mlp_work_offsets(B, off);
+    for (int i = 0; i < 12; ++i) offsets[i] = off[i];
+    return GGA_OK;
+}
 
 int gga_mlp_init(void* net_d, uint64_t seed, hipStream_t stream) {
     if (!net_d || misaligned16(net_d)) return GGA_E_ARG;

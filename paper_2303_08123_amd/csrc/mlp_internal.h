@@ -50,6 +50,7 @@ struct MlpWork {
 size_t mlp_net_bytes();
 MlpNet mlp_net(void* base);
 size_t mlp_work_bytes(int B);
+void mlp_work_offsets(int B, size_t (&off)[12]);
 MlpWork mlp_work(void* base, int B);
 
 hipError_t launch_gemm(const MlpGemm& g, hipStream_t s);

@@ -3,17 +3,19 @@
 Tolerances come from the arithmetic: the GEMM multiplies bf16 values exactly
 and accumulates in fp32, so its error is a few fp32 roundings of the sum of
 |products|; the network also rounds every hidden activation (and, backwards,
-every dZ) to bf16, a relative error of at most 2^-9 per value.  Forward
+every dZ) to bf16, a relative error of at most 2^-8 per value.  Forward
 outputs are compared against the first-order bound of those roundings carried
 through the layers (|gelu'| <= 1.13), plus the error of the rational erf the
-kernels evaluate Phi with; gradients per tensor at 5 % relative Frobenius
-error with cosine similarity above 0.998.
+kernels evaluate Phi with.  Gradients are compared element by element stage by
+stage (every pass from the kernels' own stored inputs, tests/mlp_bounds.py),
+and end to end against the plain float64 oracle per tensor.
 """
 import numpy as np
 import pytest
 import torch
 
 from oracle import mlp as omlp
+import mlp_bounds as mb
 
 pytestmark = pytest.mark.gpu
 ALPHA_DOSES = [0.5, 1.0, 1.5, 2.0, 2.5]
@@ -79,7 +81,7 @@ def test_forward_matches_oracle(gga, B):
     params = _oracle_params(gga, net)
     X = bf16(omlp.encode(dose, gap, nfrac))
     y, (_, Z1, H1, Z2, H2, Z3, H3) = omlp.forward(params, X)
-    u = 2.0 ** -9                                    # bf16 rounding, relative
+    u = 2.0 ** -8                                    # bf16 unit roundoff (8 significant bits)
     # the kernels take GELU from a rational erf with |error| <= 1.5e-7, i.e.
     # 7.5e-8 |z|, plus the fp32 roundings of its evaluation (rcp, exp2 and five
     # Horner steps, each within an ulp: at most 3e-7 of the term |z| p e / 2):
@@ -94,8 +96,36 @@ def test_forward_matches_oracle(gga, B):
     assert err.max() < 0.3 * bound.max()             # the bound is not vacuous here
 
 
-@pytest.mark.parametrize("B", [256, 16600])          # both tile sizes of the forward and data-gradient GEMMs
-def test_gradients_match_oracle(gga, B):
+# 256 rows: one weight-gradient split, Z3 kept; 16,600: 8 splits, the larger tiles
+@pytest.mark.parametrize("B", [256, 16600])
+def test_gradients_match_oracle_pass_by_pass(gga, B):
+    """Every stored tensor of the forward and backward passes, and every
+    gradient, element by element against the oracle's arithmetic applied to
+    the kernels' own stored inputs of that pass (mlp_bounds.check_passes)."""
+    net = gga.mlp_net(seed=5)
+    dose, gap, nfrac = protocols(B, 10, 2)
+    rng = np.random.default_rng(9)
+    target = rng.normal(0.0, 1.0, size=B).astype(np.float32)
+    dd = [torch.from_numpy(x).cuda() for x in (dose, gap, nfrac)]
+    work = gga.mlp_work(B)
+    loss = gga.mlp_grad(net, *dd, torch.from_numpy(target).cuda(), work=work).item()
+    grads = gga.mlp_split(gga.mlp_block(net, "g").cpu().numpy().astype(np.float64))
+    v = {k: x.float().cpu().numpy().astype(np.float64) for k, x in gga.mlp_work_views(work, B).items()}
+    assert np.array_equal(v["X"], bf16(omlp.encode(dose, gap, nfrac)))
+    # norm is (0, 1): the targets enter as given; Z3 holds weight-gradient partials from 1,024 rows
+    shares = mb.check_passes(v, grads, _oracle_params(gga, net), target.astype(np.float64), loss, z3_kept=B < 1024)
+    print("open bf16 decisions", shares)
+    assert np.all(grads[0][120:] == 0)                # inputs 120..127 are always 0
+
+
+@pytest.mark.parametrize("B", [256, 16600])
+def test_gradients_track_the_float64_oracle(gga, B):
+    """End to end against the plain float64 oracle (no bf16 stores): the loss
+    within 2 %, each gradient tensor within 5 % relative Frobenius error and
+    cosine above 0.998, the size of the bf16 storage effect.  A worst-case
+    element bound carried through the three layers is vacuous here (it
+    exceeds the gradients themselves), so element-wise parity is the
+    stage-by-stage test above."""
     net = gga.mlp_net(seed=5)
     dose, gap, nfrac = protocols(B, 10, 2)
     rng = np.random.default_rng(9)
@@ -108,8 +138,6 @@ def test_gradients_match_oracle(gga, B):
     ref_loss, ref = omlp.loss_and_grads(params, X, target.astype(np.float64))
     assert abs(loss - ref_loss) <= 0.02 * ref_loss
     for i, (g, r) in enumerate(zip(grads, ref)):
-        if i == 0:                           # inputs 120..127 are always 0: their rows get no gradient
-            assert np.all(g[120:] == 0) and np.all(r[120:] == 0)
         rel = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
         cos = float(np.dot(g.ravel(), r.ravel()) / max(np.linalg.norm(g) * np.linalg.norm(r), 1e-30))
         assert rel < 0.05 and cos > 0.998, (i, rel, cos)

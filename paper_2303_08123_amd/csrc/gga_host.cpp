@@ -85,9 +85,89 @@ gga::SimArgs make_args(const gga_params* prm, const gga_sim_cfg* cfg, const floa
     return a;
 }
 
+int check_any_side_cfg(const gga_sim_cfg* c) {
+    if (!c) return GGA_E_ARG;
+    if (c->struct_size != sizeof(gga_sim_cfg)) return GGA_E_ABI;
+    if ((c->flags & ~GGA_SIM_HALF_HOUR) != 0 || c->R < 1 || c->horizon < 0 || c->horizon > (1 << 30)) return GGA_E_ARG;
+    if (!std::isfinite(c->dose_cap)) return GGA_E_ARG;
+    if (gga::side_index(c->L) < 0 || c->substeps < 1 || c->substeps > 64) return GGA_E_UNSUPPORTED;
+    return GGA_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+bool misaligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) != 0; }
+
+int slab_plan(int L, int RR, int H, gga::SimArgs* a);
+
+// gga_simulate's workspace for a side without a resident variant: the event
+// table (rows of GGA_KMAX fractions, so the size does not depend on K) and two
+// state buffers of P * R instances (one read, the other written each step).
+struct SimWs {
+    size_t off_valid, off_count, off_step, off_frac, off_state, state_bytes, total;
+};
+SimWs simulate_ws_layout(int L, int32_t P, int32_t R) {
+    SimWs w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t at = off; off += align256(bytes); return at; };
+    w.off_valid = take(sizeof(int32_t) * (size_t)P);
+    w.off_count = take(sizeof(int32_t) * (size_t)P);
+    w.off_step = take(sizeof(int32_t) * (size_t)P * GGA_KMAX);
+    w.off_frac = take(sizeof(gga::EventFraction) * (size_t)P * GGA_KMAX);
+    w.state_bytes = align256((size_t)L * L * (3 * sizeof(float) + sizeof(uint16_t)) * (size_t)P * R);
+    w.off_state = take(2 * w.state_bytes);
+    w.total = off;
+    return w;
+}
+
+// Slab-form simulation of all P * R instances for cfg->horizon steps: event
+// table, initial state, then one launch per step alternating the two state
+// buffers; the live count of the last step (and of every step into traj) is
+// summed over the slabs.
+hipError_t enqueue_simulate_slabs(gga::SimArgs a, const gga_sim_cfg* cfg, int32_t P, int32_t K, char* ws,
+                                  const SimWs& w, hipStream_t stream) {
+    const int v = gga::variant_choice(cfg->L, false);
+    if (v < 0 || !gga::variant_is_slab(v)) return hipErrorInvalidValue;
+    const gga::SimVariant& var = gga::SIM_VARIANTS[v];
+    if (slab_plan(cfg->L, var.rpt * var.nw, cfg->substeps + 2, &a) <= 0) return hipErrorInvalidValue;
+    int32_t* valid = reinterpret_cast<int32_t*>(ws + w.off_valid);
+    int32_t* count = reinterpret_cast<int32_t*>(ws + w.off_count);
+    int32_t* step = reinterpret_cast<int32_t*>(ws + w.off_step);
+    gga::EventFraction* frac = reinterpret_cast<gga::EventFraction*>(ws + w.off_frac);
+    a.ev_valid = valid;
+    a.ev_count = count;
+    a.ev_step = step;
+    a.ev_frac = frac;
+    a.count_at = cfg->horizon;
+    a.mode = 0;
+    const int n = P * cfg->R;
+    const size_t fbytes = (size_t)cfg->L * cfg->L * 3 * sizeof(float) * (size_t)n;
+    char* s0 = ws + w.off_state;
+    char* s1 = s0 + w.state_bytes;
+    float* fa = reinterpret_cast<float*>(s0);
+    uint16_t* ca = reinterpret_cast<uint16_t*>(s0 + fbytes);
+    float* fb = reinterpret_cast<float*>(s1);
+    uint16_t* cb = reinterpret_cast<uint16_t*>(s1 + fbytes);
+    hipError_t e = gga::launch_event_table(a, P, valid, count, step, frac, stream);
+    if (e == hipSuccess && a.traj) e = gga::launch_fill(a.traj, n * cfg->horizon, 0, stream);
+    if (e == hipSuccess) e = gga::launch_slab_init(a, cfg->L, n, fa, ca, stream);
+    for (int32_t t = 0; t < cfg->horizon && e == hipSuccess; ++t) {
+        a.n0 = t;
+        a.nsteps = 1;
+        a.fields = (t & 1) ? fb : fa;
+        a.cells = (t & 1) ? cb : ca;
+        a.fields_out = (t & 1) ? fa : fb;
+        a.cells_out = (t & 1) ? ca : cb;
+        a.n_active = n;
+        e = gga::launch_variant(v, a, gga::slab_blocks(n, a.n_slabs), stream);
+    }
+    return e;
+}
+
 }  // namespace
 
 namespace gga {
+int hip_error(hipError_t e) { return hip_fail(e); }
+
 // The parameter check of the simulation calls, for the JSON reader.
 int check_params_host(const gga_params* p) { return check_params(p); }
 }  // namespace gga
@@ -179,26 +259,50 @@ int gga_population_random(const gga_alphabet* a, int32_t P, int32_t K, uint64_t 
     return e == hipSuccess ? GGA_OK : hip_fail(e);
 }
 
+size_t gga_workspace_bytes(const gga_sim_cfg* cfg, int32_t P) {
+    if (!cfg || cfg->struct_size != sizeof(gga_sim_cfg) || check_batch(P, 0, cfg->R) || cfg->R < 1) return 0;
+    if (gga::side_index(cfg->L) < 0 || gga::sim_supported(cfg->L)) return 0;   // resident: state stays on the CU
+    return simulate_ws_layout(cfg->L, P, cfg->R).total;
+}
+
 int gga_simulate(const gga_params* params, const gga_sim_cfg* cfg, const float* dose_d,
-                 const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P, int32_t K,
-                 int32_t* live_d, float* fitness_d, int32_t* traj_d, hipStream_t stream) {
+                 const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P, int32_t K, void* ws_d,
+                 size_t ws_bytes, int32_t* live_d, float* fitness_d, int32_t* traj_d, hipStream_t stream) {
+    return gga::simulate_checked(params, cfg, dose_d, gap_h_d, nfrac_d, P, K, ws_d, ws_bytes, live_d, fitness_d,
+                                 traj_d, stream);
+}
+
+}  // extern "C"
+
+int gga::simulate_checked(const gga_params* params, const gga_sim_cfg* cfg, const float* dose_d,
+                          const int32_t* gap_h_d, const int32_t* nfrac_d, int32_t P, int32_t K, void* ws_d,
+                          size_t ws_bytes, int32_t* live_d, float* fitness_d, int32_t* traj_d, hipStream_t stream) {
     int rc = check_params(params);
     if (rc) return rc;
-    if ((rc = check_cfg(cfg))) return rc;
+    if ((rc = check_any_side_cfg(cfg))) return rc;
     if ((rc = check_batch(P, K, cfg->R))) return rc;
     if (P == 0) return GGA_OK;
     if (!nfrac_d || !live_d || !fitness_d || (K > 0 && (!dose_d || !gap_h_d))) return GGA_E_ARG;
     gga::SimArgs a = make_args(params, cfg, dose_d, gap_h_d, nfrac_d, K);
-    a.n0 = 0;
-    a.nsteps = cfg->horizon;
-    a.mode = 0;
     a.live = live_d;
     a.traj = traj_d;
-    hipError_t e = gga::launch_simulation(a, cfg->L, P * cfg->R, stream);
-    if (e != hipSuccess) return hip_fail(e);
-    e = gga::launch_fitness(live_d, P, cfg->R, fitness_d, stream);
-    return e == hipSuccess ? GGA_OK : hip_fail(e);
+    hipError_t e = hipSuccess;
+    if (gga::sim_supported(cfg->L)) {                // resident: one launch for the whole horizon
+        a.n0 = 0;
+        a.nsteps = cfg->horizon;
+        a.mode = 0;
+        e = gga::launch_simulation(a, cfg->L, P * cfg->R, stream);
+    } else {                                         // slabs: state in the workspace, one launch per step
+        const SimWs w = simulate_ws_layout(cfg->L, P, cfg->R);
+        if (!ws_d || misaligned16(ws_d) || ws_bytes < w.total) return GGA_E_ARG;
+        if (traj_d && (long long)P * cfg->R * cfg->horizon > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
+        e = enqueue_simulate_slabs(a, cfg, P, K, static_cast<char*>(ws_d), w, stream);
+    }
+    if (e == hipSuccess) e = gga::launch_fitness(live_d, P, cfg->R, fitness_d, stream);
+    return e == hipSuccess ? GGA_OK : (e == hipErrorInvalidValue ? GGA_E_UNSUPPORTED : hip_fail(e));
 }
+
+extern "C" {
 
 int gga_state_init(const gga_params* params, const gga_sim_cfg* cfg, int32_t P, float* fields_d,
                    uint16_t* cells_d, hipStream_t stream) {
@@ -290,7 +394,6 @@ struct GaWorkspace {
     int32_t* position;
 };
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t ga_ws_bytes(int32_t N, int32_t R) {
     return align256(sizeof(int32_t)) + align256(sizeof(int32_t) * (size_t)N * R) +
@@ -790,7 +893,6 @@ MlpWork mlp_work(void* base, int B) {
 }  // namespace gga
 
 namespace {
-bool misaligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) != 0; }
 
 int mlp_check(const void* net, int32_t B, int32_t K, const float* dose, const int32_t* gap, const int32_t* nfrac,
               const void* work, size_t work_bytes) {
@@ -1152,7 +1254,7 @@ int slab_plan(int L, int RR, int H, gga::SimArgs* a) {
     return ns <= gga::MAX_SLABS ? ns : -1;
 }
 
-int side_ok(int L) { return L == 64 || L == 128 || L == 256; }
+int side_ok(int L) { return gga::side_index(L) >= 0; }
 
 size_t state_bytes(int L) { return (size_t)L * L * (3 * sizeof(float) + sizeof(uint16_t)); }
 
@@ -1172,15 +1274,14 @@ struct UnevenPlan {
 // (longest first, then by index), and lay out the workspace.
 int plan_uneven(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, int32_t K, int32_t R,
                 const int* force, UnevenPlan* plan) {
-    const int sides[3] = {64, 128, 256};
     for (int32_t p = 0; p < P; ++p) {
         if (!side_ok(lattice_h[p])) return GGA_E_UNSUPPORTED;
         if (horizon_h[p] < 0 || horizon_h[p] > (1 << 30)) return GGA_E_ARG;
     }
     plan->host.clear();
     plan->groups.clear();
-    for (int si = 0; si < 3; ++si) {
-        const int L = sides[si];
+    for (int si = 0; si < gga::N_SIDES; ++si) {
+        const int L = 64 + 32 * si;
         std::vector<int32_t> list;
         for (int32_t p = 0; p < P; ++p)
             if (lattice_h[p] == L)
@@ -1412,10 +1513,10 @@ size_t gga_autotune_workspace_bytes(int32_t L, int32_t P, int32_t K, int32_t R, 
     if (!side_ok(L) || P < 1 || R < 1 || horizon < 0 || check_batch(P, K, R)) return 0;
     std::vector<int32_t> lat((size_t)P, L), hor((size_t)P, horizon);
     size_t most = 0;
-    const int si = L == 64 ? 0 : L == 128 ? 1 : 2;
+    const int si = gga::side_index(L);
     for (int v = 0; v < gga::N_SIM_VARIANTS; ++v) {
         if (gga::SIM_VARIANTS[v].L != L) continue;
-        int force[3] = {-1, -1, -1};
+        int force[gga::N_SIDES] = {-1, -1, -1, -1, -1, -1, -1};
         force[si] = v;
         UnevenPlan plan;
         if (plan_uneven(lat.data(), hor.data(), P, K, R, force, &plan) == GGA_OK) most = std::max(most, plan.total);
@@ -1433,7 +1534,7 @@ int gga_autotune(const gga_params* params, const gga_sim_cfg* cfg, const float* 
     if (!side_ok(cfg->L)) return GGA_E_UNSUPPORTED;
     if (P < 1 || cfg->horizon < 0 || !nfrac_d || !live_d || !fitness_d || !ws_d || (K > 0 && (!dose_d || !gap_h_d)))
         return GGA_E_ARG;
-    const int L = cfg->L, si = L == 64 ? 0 : L == 128 ? 1 : 2;
+    const int L = cfg->L, si = gga::side_index(L);
     std::vector<int32_t> lat((size_t)P, L), hor((size_t)P, cfg->horizon);
     const gga::SimArgs base = make_args(params, cfg, dose_d, gap_h_d, nfrac_d, K);
     char* ws = static_cast<char*>(ws_d);
@@ -1445,7 +1546,7 @@ int gga_autotune(const gga_params* params, const gga_sim_cfg* cfg, const float* 
     for (int v = 0; v < gga::N_SIM_VARIANTS && e == hipSuccess; ++v) {
         if (ms_h) ms_h[v] = std::numeric_limits<float>::quiet_NaN();
         if (gga::SIM_VARIANTS[v].L != L) continue;
-        int force[3] = {-1, -1, -1};
+        int force[gga::N_SIDES] = {-1, -1, -1, -1, -1, -1, -1};
         force[si] = v;
         UnevenPlan plan;
         if (plan_uneven(lat.data(), hor.data(), P, K, cfg->R, force, &plan) != GGA_OK) continue;

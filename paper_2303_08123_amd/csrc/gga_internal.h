@@ -51,13 +51,15 @@ struct SimArgs {
     const int32_t* ev_count;  // [P]
     const int32_t* ev_step;   // [P][K] times of the positive-dose fractions in half-hours, in order
     const EventFraction* ev_frac;   // [P][K] dose and unrepaired dose of each of those fractions
-    int32_t count_at;         // slab form without horizon[]: the step whose end is counted
+    int32_t count_at;         // slab form without horizon[]: the step whose end is counted (and the
+                              // row length of traj, which then receives every slab's count per step)
     int32_t lib_n;            // resident form with MODE_LOAD: replica r loads state r mod lib_n (0: its own)
 };
 constexpr int MAX_SLABS = 16;
 
-// Kernel variants: columns per lane, rows per thread, waves; RR = rpt * nw
-// rows per workgroup (slab form when RR < L = 64 * cpl).
+// Kernel variants: lattice side L, columns per lane, rows per thread, waves;
+// RR = rpt * nw rows per workgroup (slab form when RR < L); row pitch on the
+// CU 64 * cpl >= L.  Sides 64, 96, .., 256 (N_SIDES of them).
 struct SimVariant {
     int L, cpl, rpt, nw;
     const char* name;
@@ -72,10 +74,31 @@ constexpr SimVariant SIM_VARIANTS[] = {
     {256, 4, 8, 8, "L256 slabs of 64 rows, 8x4 x8 waves"},
     {64, 1, 8, 8, "L64 resident 8x1 x8 waves"},
     {64, 1, 16, 4, "L64 resident 16x1 x4 waves"},
+    // sides below the row pitch 64 * cpl: the lanes past the lattice hold padding
+    {96, 2, 6, 16, "L96 resident 6x2 x16 waves (48 of 64 lanes)"},
+    {96, 2, 12, 8, "L96 resident 12x2 x8 waves (48 of 64 lanes)"},
+    {160, 4, 4, 16, "L160 slabs of 64 rows, 4x4 x16 waves (40 of 64 lanes)"},
+    {160, 4, 8, 8, "L160 slabs of 64 rows, 8x4 x8 waves (40 of 64 lanes)"},
+    {192, 4, 4, 16, "L192 slabs of 64 rows, 4x4 x16 waves (48 of 64 lanes)"},
+    {192, 4, 8, 8, "L192 slabs of 64 rows, 8x4 x8 waves (48 of 64 lanes)"},
+    {224, 4, 4, 16, "L224 slabs of 64 rows, 4x4 x16 waves (56 of 64 lanes)"},
+    {224, 4, 8, 8, "L224 slabs of 64 rows, 8x4 x8 waves (56 of 64 lanes)"},
+    {96, 2, 4, 16, "L96 slabs of 64 rows, 4x2 x16 waves (48 of 64 lanes)"},
 };
 constexpr int N_SIM_VARIANTS = sizeof(SIM_VARIANTS) / sizeof(SIM_VARIANTS[0]);
 constexpr bool variant_is_slab(int v) { return SIM_VARIANTS[v].rpt * SIM_VARIANTS[v].nw < SIM_VARIANTS[v].L; }
 
+// GGA_E_HIP for e, kept as the thread's last HIP error (gga_last_hip_error)
+int hip_error(hipError_t e);
+// gga_simulate's checks and work, for the entry points that share them
+int simulate_checked(const gga_params* params, const gga_sim_cfg* cfg, const float* dose_d, const int32_t* gap_h_d,
+                     const int32_t* nfrac_d, int32_t P, int32_t K, void* ws_d, size_t ws_bytes, int32_t* live_d,
+                     float* fitness_d, int32_t* traj_d, hipStream_t stream);
+
+constexpr int N_SIDES = 7;
+// index of lattice side L in 64, 96, .., 256, or -1
+int side_index(int L);
+// sides with a resident variant (gga_simulate's path)
 bool sim_supported(int L);
 // resident launch with the variant chosen for L (gga_simulate's path)
 hipError_t launch_simulation(const SimArgs& a, int L, int n_inst, hipStream_t stream);

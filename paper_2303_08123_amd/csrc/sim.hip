@@ -31,25 +31,25 @@ __global__ void philox_fill_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1
     out[4 * i + 3] = b.w3;
 }
 
-template <int CPL, int RPT, int NW>
+template <int CPL, int RPT, int NW, int LW = 64 * CPL>
 hipError_t launch_sim(const SimArgs& a, int n_blocks, hipStream_t stream) {
-    using G = Geo<CPL, RPT, NW>;
+    using G = Geo<CPL, RPT, NW, LW>;
     static_assert(!G::SLAB, "slab variants are built in sim_slab.hip");
     if (a.prm.oer_max > 1.0 || a.prm.mitotic_death)   // the extended radiobiology instantiation
-        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, true>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
+        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, LW, true>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
     else
-        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, false>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
+        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, LW, false>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
     return hipGetLastError();
 }
 
-// chosen variant per lattice side (index into SIM_VARIANTS): [0] any form, [1] resident only
-std::atomic<int> g_choice[2][3] = {{{0}, {2}, {5}}, {{0}, {2}, {-1}}};
-
-int side_index(int L) { return L == 64 ? 0 : L == 128 ? 1 : L == 256 ? 2 : -1; }
+// chosen variant per lattice side 64, 96, .., 256 (index into SIM_VARIANTS):
+// [0] any form, [1] resident only (-1: the side has no resident variant)
+std::atomic<int> g_choice[2][N_SIDES] = {{{0}, {9}, {2}, {11}, {13}, {15}, {5}},
+                                         {{0}, {9}, {2}, {-1}, {-1}, {-1}, {-1}}};
 
 }  // namespace
 
-bool sim_supported(int L) { return L == 64 || L == 128; }
+bool sim_supported(int L) { return side_index(L) >= 0 && g_choice[1][side_index(L)].load() >= 0; }
 
 hipError_t launch_variant(int v, const SimArgs& a, int n_blocks, hipStream_t stream) {
     if (n_blocks <= 0) return hipSuccess;
@@ -59,11 +59,15 @@ hipError_t launch_variant(int v, const SimArgs& a, int n_blocks, hipStream_t str
         case 3: return launch_sim<2, 16, 8>(a, n_blocks, stream);
         case 7: return launch_sim<1, 8, 8>(a, n_blocks, stream);
         case 8: return launch_sim<1, 16, 4>(a, n_blocks, stream);
+        case 9: return launch_sim<2, 6, 16, 96>(a, n_blocks, stream);
+        case 10: return launch_sim<2, 12, 8, 96>(a, n_blocks, stream);
         default:
             if (v >= 0 && v < N_SIM_VARIANTS && variant_is_slab(v)) return launch_slab_variant(v, a, n_blocks, stream);
             return hipErrorInvalidValue;
     }
 }
+
+int side_index(int L) { return (L % 32 == 0 && L >= 64 && L <= 256) ? L / 32 - 2 : -1; }
 
 int variant_choice(int L, bool resident_only) {
     const int i = side_index(L);

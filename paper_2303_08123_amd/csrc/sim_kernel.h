@@ -4,16 +4,22 @@
 // rows of a larger lattice by one step, from one state buffer in device memory
 // to the other (see Geo).
 //
-// Layout.  L = 64 * CPL.  Wave w owns rows [w*RPT, (w+1)*RPT) of the
-// workgroup's RR rows; lane l owns columns [l*CPL, (l+1)*CPL).  The three
+// Layout.  Row pitch L = 64 * CPL; the lattice side LW <= L is a multiple of
+// CPL.  Wave w owns rows [w*RPT, (w+1)*RPT) of the workgroup's RR rows; lane l
+// owns columns [l*CPL, (l+1)*CPL).  The three
 // float32 fields of a thread's RPT x CPL sites live in VGPRs for the whole run
 // (resident) or step (slab); the uint16 cell words live in LDS.  One diffusion sub-step needs, per wave, only the row above and the
 // row below its slab from the neighbouring waves (an LDS exchange of 2 rows),
 // while left/right neighbours come from the adjacent lane through DPP lane
 // shifts fused into the VALU adds.  A wave's 64 lanes span a whole lattice row,
 // so the lane shifts' zero fill at lanes 0 and 63 is exactly the missing
-// neighbour outside the lattice; the Dirichlet ghost value enters through a
-// per-site constant added to the reaction term.
+// neighbour outside the lattice (the Dirichlet value is 0 in field units).
+//
+// Padding.  When LW < L (sides 96, 160, 192, 224), the lanes past the lattice
+// hold padding sites: fields 0 with a diffusion number of 0, so they stay 0
+// and the last real lane reads the boundary value from its right neighbour as
+// at lane 63; cell words EMPTY, never free and never irradiated.  Philox
+// counters and device-memory state use lattice coordinates (row pitch LW).
 //
 // Slabs.  A slab edge that is not a lattice edge is treated as if it were
 // one; the error this makes reaches `substeps` rows into the slab through the
@@ -166,20 +172,23 @@ __device__ __forceinline__ void store_keys(uint32_t* p, const uint32_t (&k)[CPL]
     }
 }
 
-// L = 64 * CPL columns; NW waves of RPT rows hold RR = NW * RPT rows.  RR = L:
-// the whole lattice (resident).  RR < L: a slab of a larger lattice advanced by
+// L = 64 * CPL columns (LW of them the lattice's); NW waves of RPT rows hold
+// RR = NW * RPT rows.  RR = LW: the whole lattice (resident).  RR < LW: a slab of a larger lattice advanced by
 // one step per launch (the rows within `substeps + 2` of a slab edge that is
 // not a lattice edge are a halo, recomputed by the neighbouring slab).
 // Register slot of row i after k forward rotating sub-steps (S = RPT + 1 slots).
 template <int S>
 constexpr int rot_slot(int i, int k) { return ((i - k) % S + S) % S; }
 
-template <int CPL, int RPT, int NW>
+template <int CPL, int RPT, int NW, int LW = 64 * CPL>
 struct Geo {
-    static constexpr int L = 64 * CPL;
+    static constexpr int L = 64 * CPL;                // row pitch on the CU
+    static constexpr int SIDE = LW;                   // lattice side
+    static constexpr bool PAD = LW < L;               // lanes past the lattice hold padding
+    static constexpr int LOG2L = CPL == 1 ? 6 : CPL == 2 ? 7 : 8;
     static constexpr int NWAVE = NW;
     static constexpr int RR = NW * RPT;
-    static constexpr bool SLAB = RR < L;
+    static constexpr bool SLAB = RR < LW;
     static constexpr int NT = 64 * NWAVE;
     static constexpr int BLK = 2 * 3 * L;             // one wave's halo block: [top/bottom][field][L]
     // Halo area [ghost][buffer 0: NW blocks][ghost]([buffer 1][ghost]): the ghost
@@ -190,7 +199,8 @@ struct Geo {
     static constexpr int NBUF = (RR * L * 2 + area(2) * 4 + RR * L / 8 + 4096 <= 160 * 1024) ? 2 : 1;
     static constexpr int AREA = area(NBUF);
     static constexpr int POOL = (AREA > RR * L) ? AREA : RR * L;
-    static_assert(RR <= L && NWAVE <= 16, "workgroup above 1024 threads");
+    static_assert(RR <= LW && NWAVE <= 16, "workgroup above 1024 threads");
+    static_assert(LW <= L && LW % CPL == 0 && (1 << LOG2L) == L, "padding is whole lanes");
     static_assert(RPT * CPL <= 32, "per-thread site masks are 32 bits wide");
     static constexpr uint32_t ALL = (RPT * CPL == 32) ? 0xFFFFFFFFu : ((1u << (RPT * CPL)) - 1u);
     // mask bits of the first / last column of every row (bit idx = i * CPL + c)
@@ -206,10 +216,11 @@ struct Geo {
 // EXT: the extended radiobiology (the oxygen effect on radiosensitivity,
 // gga_params.oer_max > 1, and mitotic death, gga_params.mitotic_death), a
 // separate instantiation so that runs without them keep their register budget.
-template <int CPL, int RPT, int NW, bool EXT>
+template <int CPL, int RPT, int NW, int LW, bool EXT>
 __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
-    using G = Geo<CPL, RPT, NW>;
+    using G = Geo<CPL, RPT, NW, LW>;
     constexpr int L = G::L;
+    constexpr bool PAD = G::PAD;
     constexpr int RR = G::RR;
     constexpr int NWAVE = G::NWAVE;
     constexpr bool SLAB = G::SLAB;
@@ -257,10 +268,15 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     // the slab's first lattice row, and its own (non-halo) rows [iy0, iy1) of the slab
     const int ys = SLAB ? a.slab_ys[slab] : 0;
     const int iy0 = SLAB ? a.slab_i0[slab] : 0, iy1 = SLAB ? a.slab_i1[slab] : RR;
-    const int gofs = ys * L;                         // slab site index + gofs = lattice site index
+    const int lat0 = ys * LW;                        // lattice index of the slab's first site
     const int nsteps = (!SLAB && a.horizon) ? a.horizon[p] : a.nsteps;
     const int y0 = wave * RPT;
     const int x0 = lane * CPL;
+    const bool real = !PAD || x0 < LW;               // lanes past the lattice hold padding
+    // lattice index (the Philox site counter) of slab site index `site` (pitch L)
+    auto lat_id = [&](int site) {
+        return PAD ? (site >> G::LOG2L) * LW + (site & (L - 1)) + lat0 : site + lat0;
+    };
     const gga_params& P = a.prm;
     // Philox key; `a` itself stays unmodified (a written kernel argument would
     // be copied to scratch memory)
@@ -355,28 +371,28 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 
     // ---- state: fields in registers, cells in LDS ----
     float F[3][RPT + 1][CPL];                  // slot RPT: spare row for the rotating sub-steps
-    const size_t plane = (size_t)L * L;
+    const size_t plane = (size_t)LW * LW;      // device-memory state: [3][LW][LW] fields, [LW][LW] cells
     if (SLAB || (a.mode & MODE_LOAD)) {
-        const float* src = a.fields + (size_t)slot * 3 * plane + gofs;
+        const float* src = a.fields + (size_t)slot * 3 * plane + lat0;
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
-                    F[f][i][c] = src[f * plane + (size_t)(y0 + i) * L + x0 + c];
-        const uint16_t* cs = a.cells + (size_t)slot * plane + gofs;
+                    F[f][i][c] = real ? src[f * plane + (size_t)(y0 + i) * LW + x0 + c] : 0.0f;
+        const uint16_t* cs = a.cells + (size_t)slot * plane + lat0;
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
 #pragma unroll
             for (int c = 0; c < CPL; ++c)
-                s_cell[(y0 + i) * L + x0 + c] = cs[(size_t)(y0 + i) * L + x0 + c];
+                s_cell[(y0 + i) * L + x0 + c] = real ? cs[(size_t)(y0 + i) * LW + x0 + c] : (uint16_t)0;
     } else {
-        const int ctr = L / 2;
+        const int ctr = LW / 2;
         const int rad2 = P.seed_radius * P.seed_radius;
         float f0[3];
 #pragma unroll
-        for (int f = 0; f < 3; ++f) f0[f] = to_field_units(P, f, P.init[f]);
+        for (int f = 0; f < 3; ++f) f0[f] = real ? to_field_units(P, f, P.init[f]) : 0.0f;
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
@@ -389,8 +405,8 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             for (int c = 0; c < CPL; ++c) {
                 const int y = y0 + i, x = x0 + c;
                 uint16_t w = 0;
-                if ((x - ctr) * (x - ctr) + (y - ctr) * (y - ctr) <= rad2) {
-                    const Block4 b = philox10(y * L + x, INIT_STEP, r, p, seed_lo, seed_hi);
+                if (real && (x - ctr) * (x - ctr) + (y - ctr) * (y - ctr) <= rad2) {
+                    const Block4 b = philox10(y * LW + x, INIT_STEP, r, p, seed_lo, seed_hi);
                     const uint32_t age = (uint32_t)(((uint64_t)b.w0 * (uint32_t)P.A0) >> 32);
                     w = (uint16_t)(PROLIF | (age << 2));
                 }
@@ -401,14 +417,15 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     // Per-field constants (field units, see to_field_units): the update and the
     // lower clamp of O and G (c >= 0 reads c^ >= -g / rho, rho_O = 1 and
     // rho_G > 0); the one reaction rate kappa'_O enters through s_react.
+    // Padding lanes take lam = 0 and no clamp, so their fields stay 0.
     float lam[3], cen[3], lo[2];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        lam[f] = P.lambda[f];
+        lam[f] = real ? P.lambda[f] : 0.0f;
         cen[f] = 1.0f - 4.0f * P.lambda[f];
     }
 #pragma unroll
-    for (int f = 0; f < 2; ++f) lo[f] = to_field_units(P, f, 0.0);
+    for (int f = 0; f < 2; ++f) lo[f] = real ? to_field_units(P, f, 0.0) : -INFINITY;
     // reaction term per cell state, -kappa'_O a[state], looked up in LDS by
     // each site's state (one LDS read instead of a chain of selects)
     if (tid < 4) s_react[tid] = -P.kappa[0] * P.activity[tid];
@@ -603,7 +620,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                         const int cls = (st == QUIESC) ? 3 : (age < ca0 ? 0 : (age < ca1 ? 1 : 2));
                         thr = s_oer_thr[cls][(w >> 10) & 15u];
                     }
-                    const Block4 b = philox10(site + gofs, (uint32_t)n | (half << 31), r, p, seed_lo, seed_hi);
+                    const Block4 b = philox10(lat_id(site), (uint32_t)n | (half << 31), r, p, seed_lo, seed_hi);
                     // mitotic death: the cell lives on, marked, until it next divides
                     if (b.w1 >= thr) s_cell[site] = mitotic ? (uint16_t)(w | DOOM_BIT) : (uint16_t)DEAD;
                 }
@@ -621,7 +638,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) Ro[i][c] = s_react[cellp[i * L + c] & 3];
+                for (int c = 0; c < CPL; ++c) Ro[i][c] = real ? s_react[cellp[i * L + c] & 3] : 0.0f;
             // (3) the sub-steps up to a fraction at the half hour, or to the end of the hour
             const int stop = (half == 0 && ev < nev && s_ev_step[ev] == rel + 1) ? a.substeps / 2 : a.substeps;
             for (; s + 2 <= stop; s += 2) {
@@ -676,7 +693,9 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         for (int k = tid; k < RR * L / 32; k += G::NT) s_claim[k] = 0u;
         __syncthreads();   // boundary rows read, claims reset: own rows may now be rewritten
         // Per site: lysis and environment transitions, written back row by row.
-        uint32_t empty_m = ALL_SITES, cyc_m = 0, old_m = 0, alive_m = 0, doom_m = 0;
+        // padding sites are never free
+        const uint32_t real_m = real ? ALL_SITES : 0u;
+        uint32_t empty_m = real_m, cyc_m = 0, old_m = 0, alive_m = 0, doom_m = 0;
         if (__builtin_amdgcn_ballot_w64(occupied != 0u) != 0) {   // wave-uniform; else all EMPTY
             // Environment flags of the thread's sites, from the fields after the
             // sub-steps (x < th  <=>  sign bit of x - th: the difference of two
@@ -728,6 +747,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                 }
                 store_words<CPL>(cellp + i * L, w);
             }
+            if constexpr (PAD) empty_m &= real_m;
         }
         constexpr uint32_t C0 = G::COL_FIRST, CL = G::COL_LAST;
         const uint32_t fN = ((empty_m << CPL) | top) & ALL_SITES;
@@ -744,7 +764,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                 const int idx = __builtin_ctz(m);
                 m &= m - 1;
                 const int site = own + (idx / CPL) * L + idx % CPL;
-                const Block4 b = philox10(site + gofs, n, r, p, seed_lo, seed_hi);
+                const Block4 b = philox10(lat_id(site), n, r, p, seed_lo, seed_hi);
                 if (b.w3 < s_k.T_div) {
                     cellp[(idx / CPL) * L + idx % CPL] = (uint16_t)DEAD;
                     alive_m &= ~(1u << idx);
@@ -759,7 +779,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                 const int idx = __builtin_ctz(m);
                 m &= m - 1;
                 const int site = own + (idx / CPL) * L + idx % CPL;
-                const Block4 b = philox10(site + gofs, n, r, p, seed_lo, seed_hi);
+                const Block4 b = philox10(lat_id(site), n, r, p, seed_lo, seed_hi);
                 if (b.w3 < s_k.T_div) {
                     const uint32_t fm = ((fN >> idx) & 1u) | (((fE >> idx) & 1u) << 1) |
                                         (((fS >> idx) & 1u) << 2) | (((fW >> idx) & 1u) << 3);
@@ -819,6 +839,8 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             count = s_count[n & 1];
             s_count[(n + 1) & 1] = 0;
             if (!SLAB && a.traj) a.traj[(size_t)inst * a.nsteps + (n - a.n0)] = count;
+            // slabs (one step per launch): this slab's share of step n's count
+            if (SLAB && a.traj) atomicAdd(&a.traj[(size_t)inst * a.count_at + n], count);
         }
     }
 
@@ -845,23 +867,23 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 
     if (SLAB || (a.mode & MODE_STORE)) {
         // slabs write their own rows into the other state buffer
-        float* dst = (SLAB ? a.fields_out : a.fields) + (size_t)slot * 3 * plane + gofs;
+        float* dst = (SLAB ? a.fields_out : a.fields) + (size_t)slot * 3 * plane + lat0;
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
-                if (!SLAB || (y0 + i >= iy0 && y0 + i < iy1))
+                if (real && (!SLAB || (y0 + i >= iy0 && y0 + i < iy1)))
 #pragma unroll
                     for (int c = 0; c < CPL; ++c)
-                        dst[f * plane + (size_t)(y0 + i) * L + x0 + c] = F[f][i][c];
+                        dst[f * plane + (size_t)(y0 + i) * LW + x0 + c] = F[f][i][c];
         __syncthreads();
-        uint16_t* cd = (SLAB ? a.cells_out : a.cells) + (size_t)slot * plane + gofs;
+        uint16_t* cd = (SLAB ? a.cells_out : a.cells) + (size_t)slot * plane + lat0;
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
-            if (!SLAB || (y0 + i >= iy0 && y0 + i < iy1))
+            if (real && (!SLAB || (y0 + i >= iy0 && y0 + i < iy1)))
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
-                    cd[(size_t)(y0 + i) * L + x0 + c] = s_cell[(y0 + i) * L + x0 + c];
+                    cd[(size_t)(y0 + i) * LW + x0 + c] = s_cell[(y0 + i) * L + x0 + c];
     }
 }
 

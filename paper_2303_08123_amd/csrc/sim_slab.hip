@@ -75,14 +75,14 @@ __global__ void slab_init_kernel(SimArgs a, int L, int n, float* fields, uint16_
     cells[(size_t)k * plane + site] = w;
 }
 
-template <int CPL, int RPT, int NW>
+template <int CPL, int RPT, int NW, int LW = 64 * CPL>
 hipError_t launch_slab(const SimArgs& a, int n_blocks, hipStream_t stream) {
-    using G = Geo<CPL, RPT, NW>;
+    using G = Geo<CPL, RPT, NW, LW>;
     static_assert(G::SLAB, "resident variants are built in sim.hip");
     if (a.prm.oer_max > 1.0 || a.prm.mitotic_death)   // the extended radiobiology instantiation
-        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, true>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
+        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, LW, true>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
     else
-        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, false>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
+        hipLaunchKernelGGL((sim_kernel<CPL, RPT, NW, LW, false>), dim3(n_blocks), dim3(G::NT), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -95,6 +95,13 @@ hipError_t launch_slab_variant(int v, const SimArgs& a, int n_blocks, hipStream_
         case 4: return launch_slab<2, 4, 16>(a, n_blocks, stream);
         case 5: return launch_slab<4, 4, 16>(a, n_blocks, stream);
         case 6: return launch_slab<4, 8, 8>(a, n_blocks, stream);
+        case 11: return launch_slab<4, 4, 16, 160>(a, n_blocks, stream);
+        case 12: return launch_slab<4, 8, 8, 160>(a, n_blocks, stream);
+        case 13: return launch_slab<4, 4, 16, 192>(a, n_blocks, stream);
+        case 14: return launch_slab<4, 8, 8, 192>(a, n_blocks, stream);
+        case 15: return launch_slab<4, 4, 16, 224>(a, n_blocks, stream);
+        case 16: return launch_slab<4, 8, 8, 224>(a, n_blocks, stream);
+        case 17: return launch_slab<2, 4, 16, 96>(a, n_blocks, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -16,13 +16,13 @@ BMI = (np.full(8, 1.25, np.float32), np.array([0, 6, 18, 6, 18, 6, 18, 6], np.in
 CONFIG1 = dict(name="plain-64x64-bmii", L=64, R=4, horizon=240, substeps=10, seed=0, dose_cap=20.0)
 CONFIG2 = dict(name="batched-1024x4-128x128-20d", L=128, R=4, horizon=480, substeps=10, seed=0,
                dose_cap=20.0, P=1024, K=10)
-# Uneven batch: lattice side uniform over {64, 128, 256} per protocol, 3-40
+# Uneven batch: lattice side uniform over {64, 96, .., 256} per protocol, 3-40
 # fractions of 0.5-5 Gy (0.5 Gy steps) with delays from the batched workload's
 # alphabet, total <= 30 Gy (drawn on the device, uniform over the feasible set
 # for each fraction count), horizon uniform over 10-40 whole days.
 CONFIG3 = dict(name="uneven-8192x8-64to256-10to40d", R=8, substeps=10, seed=0, dose_cap=30.0, P=8192, K=40,
                kmin=3, dose_quantum=0.5, dose_q=list(range(1, 11)), gaps=list(range(6, 61, 6)),
-               sides=(64, 128, 256), days=(10, 40))
+               sides=(64, 96, 128, 160, 192, 224, 256), days=(10, 40))
 # Quasi-3D variant: the batched workload's protocols (first 256) on 128 x 128
 # sites with 8 cell slots each, 20 days.
 CONFIG_Q3 = dict(name="quasi3d-256x4-128x128x8-20d", L=128, C=8, R=4, horizon=480, substeps=10, seed=0,
@@ -82,7 +82,7 @@ def random_state(L, seed, tumour_radius=None, field_lo=0.0, field_hi=1.0):
     return fields, cells
 
 
-def config3_shapes(P, seed=0, sides=(64, 128, 256), days=(10, 40)):
+def config3_shapes(P, seed=0, sides=(64, 96, 128, 160, 192, 224, 256), days=(10, 40)):
     """Per-protocol lattice side and horizon (steps) of the uneven batch."""
     rng = np.random.default_rng(seed)
     lattice = rng.choice(np.asarray(sides, np.int32), size=P).astype(np.int32)

@@ -71,7 +71,7 @@ def test_struct_layout_matches_python_mirror(gga, tmp_path):
 
 
 def test_version_and_errors(gga):
-    assert gga.version() == 1
+    assert gga.version() == 2
     for code in (0, -1, -2, -3, -4, -5, -6, -99):
         assert gga.LIB.gga_strerror(code)
 
@@ -104,15 +104,20 @@ def test_abi_argument_errors(gga):
     prm = gga.make_params(gga.load_model())
     prm.lambda_[0] = 0.3
     n = ctypes.c_void_p(0)
-    assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfg), n, n, n, 1, 1, n, n, n, n) == -5
+    assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfg), n, n, n, 1, 1, n, 0, n, n, n, n) == -5
     for f, v in ((1, 0.0), (2, 0.0), (2, 1e-20), (1, 1e20)):   # rates must be positive, ratios in [1e-12, 1e12]
         prm = gga.make_params(gga.load_model())
         prm.kappa[f] = v
-        assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfg), n, n, n, 1, 1, n, n, n, n) == -5, (f, v)
+        assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfg), n, n, n, 1, 1, n, 0, n, n, n, n) == -5, (f, v)
     prm = gga.make_params(gga.load_model())
-    assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfg), n, n, n, 1, 1, n, n, n, n) == -1
-    cfg96 = gga.make_cfg(96, 10, 1)
-    assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfg96), n, n, n, 1, 1, n, n, n, n) == -3
+    assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfg), n, n, n, 1, 1, n, 0, n, n, n, n) == -1
+    for side in (48, 80, 100, 288):                # multiples of 32 in 64 .. 256 only
+        cfgx = gga.make_cfg(side, 10, 1)
+        assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfgx), n, n, n, 1, 1, n, 0, n, n, n, n) == -3
+        assert gga.LIB.gga_workspace_bytes(ctypes.byref(cfgx), 1) == 0
+    # sides without a resident variant need the workspace: a missing one is an argument error
+    cfg160 = gga.make_cfg(160, 10, 1)
+    assert gga.LIB.gga_simulate(ctypes.byref(prm), ctypes.byref(cfg160), n, n, n, 1, 1, n, 0, n, n, n, n) == -1
     ab = gga.make_alphabet(0.5, [1, 2], [6], 5, 5, 2.0)   # 5 fractions of >= 0.5 Gy exceed 2 Gy
     assert gga.LIB.gga_population_random(ctypes.byref(ab), 0, 5, 0, n, n, n, n) == -6
     assert gga.LIB.gga_population_random(ctypes.byref(ab), 1, 5, 0, n, n, n, n) == -1
@@ -146,12 +151,17 @@ def test_mlp_work_layout_fits_the_work_buffer(gga):
 
 def test_variant_table_and_choices(gga):
     vs = gga.variants()
-    assert [v[1] for v in vs] == [64, 64, 128, 128, 128, 256, 256, 64, 64]
-    assert [v[2] for v in vs] == [False, True, False, False, True, True, True, False, False]
+    assert [v[1] for v in vs] == [64, 64, 128, 128, 128, 256, 256, 64, 64, 96, 96, 160, 160, 192, 192, 224, 224, 96]
+    assert [v[2] for v in vs] == [False, True, False, False, True, True, True, False, False,
+                                  False, False, True, True, True, True, True, True, True]
     assert gga.get_variant(64) == 0 and gga.get_variant(128) == 2 and gga.get_variant(256) == 5
-    assert gga.get_variant(128, resident_only=True) == 2
+    assert [gga.get_variant(L) for L in (96, 160, 192, 224)] == [9, 11, 13, 15]
+    assert gga.get_variant(128, resident_only=True) == 2 and gga.get_variant(96, resident_only=True) == 9
+    for L in (160, 192, 224, 256):
+        with pytest.raises(gga.GGAError):
+            gga.get_variant(L, resident_only=True)          # no resident form above 128
     with pytest.raises(gga.GGAError):
-        gga.get_variant(256, resident_only=True)            # no resident form for 256
+        gga.get_variant(80)                                  # not a multiple of 32
     with pytest.raises(gga.GGAError):
         gga.set_variant(64, 2)                               # a variant of another side
     gga.set_variant(128, 4)
@@ -181,7 +191,10 @@ def test_uneven_workspace_holds_two_states_per_slab_instance(gga):
         assert _uneven_bytes(gga, [64, 128, 64], [10, 20, 30], 8, 4) >= 2 * 4 * 128 * 128 * 14
     finally:
         gga.set_variant(128, 2)
-    assert _uneven_bytes(gga, [64, 96], [10, 10], 8, 1) == 0     # unsupported side
+    assert _uneven_bytes(gga, [64, 96], [10, 10], 8, 1) > 0      # 96 is resident: lists and tables only
+    assert _uneven_bytes(gga, [64, 96], [10, 10], 8, 1) < 1 << 20
+    assert _uneven_bytes(gga, [64, 160], [10, 10], 8, 1) >= 2 * 160 * 160 * 14
+    assert _uneven_bytes(gga, [64, 80], [10, 10], 8, 1) == 0     # unsupported side
     assert _uneven_bytes(gga, [64, 64], [10, -1], 8, 1) == 0     # negative horizon
 
 
@@ -189,7 +202,7 @@ def test_uneven_argument_errors_before_any_launch(gga):
     p = gga.make_params(gga.load_model())
     cfg = gga.make_cfg(64, 0, 1)
     fake = ctypes.c_void_p(0x1000)
-    lat = np.array([64, 96], np.int32)
+    lat = np.array([64, 80], np.int32)
     hor = np.array([5, 5], np.int32)
     rc = gga.LIB.gga_simulate_uneven(ctypes.byref(p), ctypes.byref(cfg), fake, fake, fake, 2, 1,
                                      lat.ctypes.data_as(ctypes.c_void_p), hor.ctypes.data_as(ctypes.c_void_p),
@@ -369,3 +382,19 @@ def test_params_from_json_reads_the_model_file(gga, tmp_path):
     assert gga.LIB.gga_params_from_json(b"/nonexistent/model.json", ctypes.byref(p)) == -1
     p.struct_size = 4
     assert gga.LIB.gga_params_from_json(path.encode(), ctypes.byref(p)) == -2
+
+
+def test_simulate_workspace_sizes(gga):
+    """gga_workspace_bytes: none for the resident sides; the event table and
+    two state buffers per instance for the slab sides."""
+    for L in (64, 96, 128):
+        assert gga.workspace_bytes(gga.make_cfg(L, 10, 4), 100) == 0
+    for L in (160, 192, 224, 256):
+        cfg = gga.make_cfg(L, 10, 4)
+        n = gga.workspace_bytes(cfg, 100)
+        state = 2 * 400 * L * L * 14
+        assert state <= n <= state + 100 * (8 + 20 * 64) + 6 * 256, (L, n)
+        assert gga.workspace_bytes(cfg, 0) < 1 << 12
+    bad = gga.make_cfg(160, 10, 4)
+    bad.struct_size = 3
+    assert gga.workspace_bytes(bad, 10) == 0 and gga.workspace_bytes(gga.make_cfg(160, 10, 4), -1) == 0

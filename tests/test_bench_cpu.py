@@ -24,3 +24,15 @@ def test_traffic_record_matches_the_kernel_sources():
     import bench
     t = bench.measured_traffic()
     assert t is not None and 1e5 < t < 1e8
+
+
+def test_config3_sides_are_uniform_over_all_seven():
+    """The uneven workload draws every side 64, 96, .., 256 (lattices 64 x 64
+    to 256 x 256, uniform per protocol) and whole-day horizons of 10-40 days."""
+    import numpy as np
+    from paper_2303_08123_amd import workloads
+    lattice, horizon = workloads.config3_shapes(8192, seed=0)
+    counts = np.bincount(lattice // 32 - 2, minlength=7)
+    assert set(np.unique(lattice).tolist()) == {64, 96, 128, 160, 192, 224, 256}
+    assert counts.min() > 8192 / 7 * 0.85
+    assert horizon.min() >= 240 and horizon.max() <= 960 and np.all(horizon % 24 == 0)

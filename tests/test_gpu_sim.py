@@ -50,7 +50,7 @@ def test_philox_matches_oracle(gga):
     assert np.array_equal(out, ref)
 
 
-@pytest.mark.parametrize("L", [64, 128])
+@pytest.mark.parametrize("L", [64, 96, 128])
 def test_initial_state_is_bit_exact(gga, model_dict, L):
     prm = Params.from_dict(model_dict)
     P, R, seed = 3, 2, 11
@@ -270,8 +270,9 @@ def test_zero_and_edge_sizes(gga, model_dict):
     cfg0 = gga.make_cfg(64, 0, 3, seed=0)
     live, fit, _ = gga.simulate(model_dict, cfg0, z, z.int(), n)
     assert np.all(live.cpu().numpy() == 113)
-    with pytest.raises(gga.GGAError):
-        gga.simulate(model_dict, gga.make_cfg(96, 10, 1), z, z.int(), n)
+    for side in (80, 288):                                 # multiples of 32 in 64 .. 256 only
+        with pytest.raises(gga.GGAError):
+            gga.simulate(model_dict, gga.make_cfg(side, 10, 1), z, z.int(), n)
 
 
 def test_outputs_are_deterministic(gga, model_dict):

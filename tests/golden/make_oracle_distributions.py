@@ -1,7 +1,8 @@
 """Write tests/golden/oracle_distributions.json: final live counts of many
 independent oracle replicas for a few protocols (with --batched16:
 tests/golden/oracle_batched16.json, 16 batched-workload protocols as one
-batch).
+batch; with --growth: tests/golden/oracle_growth.json, the live count every
+24 steps of untreated tumours on the plain and batched workloads' lattices).
 
 Calls only the oracle and the seeded input generators.  Run from the
 repository root:  python tests/golden/make_oracle_distributions.py
@@ -59,7 +60,20 @@ def one(args):
     prm = Params.from_dict(model(c["model"]))
     ev = protocol.events(np.array(c["dose"], np.float32), np.array(c["gap"]), c["nfrac"], c["horizon"], prm)
     # protocol index c["p"] of the batch (0 unless given), replica r, under the oracle's own run seed
-    return name, r, int(sim.run_instance(prm, c["L"], c["horizon"], 10, ev, c.get("p", 0), r, ORACLE_SEED)[2][-1])
+    traj = sim.run_instance(prm, c["L"], c["horizon"], 10, ev, c.get("p", 0), r, ORACLE_SEED)[2]
+    if c.get("every"):
+        return name, r, [int(v) for v in traj[c["every"] - 1::c["every"]]]
+    return name, r, int(traj[-1])
+
+
+# Unirradiated growth: the plain workload's 64 x 64 lattice over 10 days and
+# the batched workload's 128 x 128 lattice over 20 days, no fraction; the live
+# count after every 24th step.
+def growth_cases():
+    return {
+        "growth_64": dict(model="default", L=64, horizon=240, R=256, dose=[], gap=[], nfrac=0, every=24),
+        "growth_128": dict(model="default", L=128, horizon=480, R=200, dose=[], gap=[], nfrac=0, every=24),
+    }
 
 
 def family_cases():
@@ -71,12 +85,17 @@ def family_cases():
 
 def main():
     family = "--batched16" in sys.argv
-    cs = family_cases() if family else cases()
+    growth = "--growth" in sys.argv
+    cs = family_cases() if family else growth_cases() if growth else cases()
     jobs = [(name, c, r) for name, c in cs.items() for r in range(c["R"])]
     t0 = time.time()
     with mp.Pool(os.cpu_count()) as pool:
         res = pool.map(one, jobs, chunksize=4)
-    if family:
+    if growth:
+        about = ("live counts after every 24th step (days 1, 2, ..) of independent untreated oracle replicas "
+                 f"(protocol index 0, no fraction, replica r = 0..R-1, run seed {ORACLE_SEED}); written by "
+                 "tests/golden/make_oracle_distributions.py --growth")
+    elif family:
         about = ("final live counts of independent oracle replicas of 16 batched-workload protocols simulated "
                  f"as one batch (batch position p, replica r = 0..R-1, run seed {ORACLE_SEED}); written by "
                  "tests/golden/make_oracle_distributions.py --batched16")
@@ -90,7 +109,7 @@ def main():
             if n == name:
                 live[r] = v
         out[name] = dict(c, live=live)
-    fname = "oracle_batched16.json" if family else "oracle_distributions.json"
+    fname = "oracle_batched16.json" if family else "oracle_growth.json" if growth else "oracle_distributions.json"
     with open(os.path.join(ROOT, "tests", "golden", fname), "w") as fh:
         json.dump(out, fh, indent=1)
     print(f"done in {time.time() - t0:.0f} s")

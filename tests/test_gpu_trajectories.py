@@ -127,6 +127,45 @@ def test_batched_family_distributions_match_oracle(gga, model_dict, family):
     assert match >= 0.25
 
 
+@pytest.mark.parametrize("name", ["growth_64", "growth_128"])
+def test_unirradiated_growth_matches_oracle(gga, model_dict, name):
+    """Untreated growth on the plain (64 x 64, 10 days) and batched (128 x 128,
+    20 days) workloads' lattices: the live count after every 24th step of the
+    HIP path's replicas under one run seed against stored oracle replicas under
+    another.  Each day's means agree by Welch's test at the Bonferroni level
+    0.05 / days, and the final counts by Welch and two-sample KS at 0.05; under
+    the oracle's seed, the share of replicas whose whole growth curve equals
+    the oracle's exactly is reported (at least a quarter)."""
+    with open(os.path.join(HERE, "golden", "oracle_growth.json")) as fh:
+        case = json.load(fh)[name]
+    seed_oracle = 1000
+    ref = np.array(case["live"], np.float64)                # [R][days]
+    every, R = case["every"], case["R"]
+    z = torch.zeros((1, 0), dtype=torch.float32, device="cuda")
+    nfrac = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def curves(seed):
+        cfg = gga.make_cfg(case["L"], case["horizon"], R, seed=seed, substeps=10, dose_cap=100.0)
+        live, fit, traj = gga.simulate(model_dict, cfg, z, z.int(), nfrac, traj=True)
+        tr = traj.cpu().numpy()[0]
+        assert np.array_equal(tr[:, -1], live.cpu().numpy()[0])
+        return tr[:, every - 1::every].astype(np.float64)
+
+    got, same = curves(GPU_SEED), curves(seed_oracle)
+    days = ref.shape[1]
+    for d in range(days):
+        t = stats.ttest_ind(got[:, d], ref[:, d], equal_var=False)
+        assert t.pvalue > 0.05 / days, (d + 1, got[:, d].mean(), ref[:, d].mean(), t.pvalue)
+    t = stats.ttest_ind(got[:, -1], ref[:, -1], equal_var=False)
+    ks = stats.ks_2samp(got[:, -1], ref[:, -1])
+    match = float(np.mean(np.all(same == ref, axis=1)))
+    print(f"{name}: day means gpu {np.round(got.mean(0), 1).tolist()} | oracle {np.round(ref.mean(0), 1).tolist()} | "
+          f"final Welch p {t.pvalue:.3f} KS p {ks.pvalue:.3f} | same-seed whole-curve match {match:.3f}")
+    assert t.pvalue > 0.05 and ks.pvalue > 0.05
+    assert match >= 0.25
+    assert np.all(np.diff(got.mean(0)) > 0)                   # the untreated tumour grows every day
+
+
 def test_full_size_batched_workload(gga, model_dict):
     """Bench configuration: sampled instances equal the oracle step by step
     until their first near-threshold site; properties of every output."""

@@ -47,6 +47,7 @@ extern "C" {
 #define GGA_E_HIP (-4)          /* HIP runtime error; see gga_last_hip_error()  */
 #define GGA_E_PARAM (-5)        /* model constant out of range (e.g. lambda)    */
 #define GGA_E_ALPHABET (-6)     /* alphabet admits no protocol / too large      */
+#define GGA_E_SCRATCH (-7)      /* batch exceeds gga_simulate_noalloc's scratch */
 
 /* Per-protocol status written by gga_validate (and used by gga_simulate). */
 #define GGA_PROTO_OK 0
@@ -233,6 +234,26 @@ int gga_simulate(const gga_params* params, const gga_sim_cfg* cfg,
                  const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d,
                  int32_t P, int32_t K, void* ws_d, size_t ws_bytes,
                  int32_t* live_d, float* fitness_d, int32_t* traj_d, hipStream_t stream);
+
+/*
+ * gga_simulate for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments without the workspace, and the same kernels and results.
+ * The slab-form sides use a fixed scratch array of GGA_NOALLOC_SCRATCH_BYTES
+ * in device memory instead, one per GPU the library runs on, held until the
+ * process ends; batches whose gga_workspace_bytes(cfg, P) exceeds it return
+ * GGA_E_SCRATCH before any work is enqueued (at most 36 instances at
+ * 256 x 256, 47 at 224, 64 at 192, 93 at 160, one replica each).  Resident sides use no scratch.  The call allocates and
+ * frees nothing (its first call on a device looks up that device's scratch
+ * address).  Calls share their GPU's scratch: two calls whose work overlaps
+ * on one GPU (other streams, other host threads) race; calls ordered on one
+ * stream do not.  Errors: as gga_simulate, and GGA_E_SCRATCH.
+ */
+#define GGA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int gga_simulate_noalloc(const gga_params* params, const gga_sim_cfg* cfg,
+                         const float* dose_d, const int32_t* gap_h_d, const int32_t* nfrac_d,
+                         int32_t P, int32_t K, int32_t* live_d, float* fitness_d, int32_t* traj_d,
+                         hipStream_t stream);
 
 /*
  * Write the initial state of P * cfg->R instances: fields_d[P*R][3][L][L]

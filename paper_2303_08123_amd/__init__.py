@@ -20,7 +20,9 @@ DATA = os.path.join(HERE, "data")
 GGA_OK = 0
 KMAX = 64
 ERRORS = {-1: "GGA_E_ARG", -2: "GGA_E_ABI", -3: "GGA_E_UNSUPPORTED", -4: "GGA_E_HIP",
-          -5: "GGA_E_PARAM", -6: "GGA_E_ALPHABET"}
+          -5: "GGA_E_PARAM", -6: "GGA_E_ALPHABET", -7: "GGA_E_SCRATCH"}
+E_SCRATCH = -7
+NOALLOC_SCRATCH_BYTES = 64 << 20     # GGA_NOALLOC_SCRATCH_BYTES
 PROTO_OK, PROTO_NFRAC, PROTO_DOSE, PROTO_CAP, PROTO_GAP = 0, 1, 2, 3, 4
 
 
@@ -104,6 +106,7 @@ def _load():
         "gga_population_random": ([vp, i32, i32, u64, vp, vp, vp, vp], ctypes.c_int),
         "gga_workspace_bytes": ([vp, i32], ctypes.c_size_t),
         "gga_simulate": ([vp, vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, vp, vp, vp], ctypes.c_int),
+        "gga_simulate_noalloc": ([vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
         "gga_state_init": ([vp, vp, i32, vp, vp, vp], ctypes.c_int),
         "gga_state_run": ([vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "gga_philox_fill": ([vp, u64, vp, i64, vp], ctypes.c_int),
@@ -169,7 +172,7 @@ def _load():
 
 LIB = _load()
 EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
-           "gga_population_random", "gga_workspace_bytes", "gga_simulate", "gga_state_init", "gga_state_run",
+           "gga_population_random", "gga_workspace_bytes", "gga_simulate", "gga_simulate_noalloc", "gga_state_init", "gga_state_run",
            "gga_philox_fill", "gga_ga_breed", "gga_ga_workspace_bytes", "gga_ga_set_generation",
            "gga_ga_generation", "gga_ga_run", "gga_mlp_net_bytes", "gga_mlp_work_bytes", "gga_mlp_work_layout",
            "gga_mlp_init",
@@ -184,7 +187,9 @@ EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
 
 
 class GGAError(RuntimeError):
-    pass
+    def __init__(self, msg, code=None):
+        super().__init__(msg)
+        self.code = code
 
 
 def _check(rc):
@@ -192,7 +197,7 @@ def _check(rc):
         msg = LIB.gga_strerror(rc).decode()
         if rc == -4:
             msg += f" (hipError {LIB.gga_last_hip_error()})"
-        raise GGAError(f"{ERRORS.get(rc, rc)}: {msg}")
+        raise GGAError(f"{ERRORS.get(rc, rc)}: {msg}", rc)
 
 
 def _ptr(t):
@@ -341,6 +346,23 @@ def simulate(params, cfg, dose, gap, nfrac, traj=False, out=None, ws=None, strea
     nws = 0 if ws is None else ws.numel() * ws.element_size()
     _check(LIB.gga_simulate(ctypes.byref(_as_params(params)), ctypes.byref(cfg), _ptr(dose), _ptr(gap),
                             _ptr(nfrac), P, K, _ptr(ws), nws, _ptr(live), _ptr(fit), _ptr(tr), _stream(stream)))
+    return live, fit, tr
+
+
+def simulate_noalloc(params, cfg, dose, gap, nfrac, traj=False, out=None, stream=None):
+    """gga_simulate_noalloc: as simulate, with the library's fixed scratch in
+    place of a workspace (the call itself allocates no device memory; the
+    outputs are allocated here unless given)."""
+    P, K = _protocols(dose, gap, nfrac)
+    dev = dose.device
+    if out is None:
+        live = torch.empty((P, cfg.R), dtype=torch.int32, device=dev)
+        fit = torch.empty((P,), dtype=torch.float32, device=dev)
+        tr = torch.empty((P, cfg.R, cfg.horizon), dtype=torch.int32, device=dev) if traj else None
+    else:
+        live, fit, tr = out
+    _check(LIB.gga_simulate_noalloc(ctypes.byref(_as_params(params)), ctypes.byref(cfg), _ptr(dose), _ptr(gap),
+                                    _ptr(nfrac), P, K, _ptr(live), _ptr(fit), _ptr(tr), _stream(stream)))
     return live, fit, tr
 
 

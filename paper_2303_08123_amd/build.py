@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgga.so")
-SOURCES = ["gga_host.cpp", "sim.hip", "sim_slab.hip", "quasi3d.hip", "population.hip", "ga.hip", "ga_slots.hip", "mlp.hip", "peaks.hip", "params_json.cpp"]
+SOURCES = ["gga_host.cpp", "sim.hip", "sim_slab.hip", "noalloc.hip", "quasi3d.hip", "population.hip", "ga.hip", "ga_slots.hip", "mlp.hip", "peaks.hip", "params_json.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -185,6 +185,7 @@ const char* gga_strerror(int code) {
         case GGA_E_HIP: return "HIP runtime error (see gga_last_hip_error)";
         case GGA_E_PARAM: return "model constant out of range";
         case GGA_E_ALPHABET: return "alphabet admits no protocol or exceeds the table limit";
+        case GGA_E_SCRATCH: return "batch needs more than the no-allocation entry point's fixed scratch";
         default: return "unknown error code";
     }
 }

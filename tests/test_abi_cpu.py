@@ -398,3 +398,21 @@ def test_simulate_workspace_sizes(gga):
     bad = gga.make_cfg(160, 10, 4)
     bad.struct_size = 3
     assert gga.workspace_bytes(bad, 10) == 0 and gga.workspace_bytes(gga.make_cfg(160, 10, 4), -1) == 0
+
+
+def test_noalloc_checks_its_scratch_before_any_launch(gga):
+    """gga_simulate_noalloc: a batch whose workspace exceeds the fixed scratch
+    is refused with GGA_E_SCRATCH, and a bad cfg with GGA_E_ABI / GGA_E_ARG,
+    before anything touches a device."""
+    p = gga.make_params(gga.load_model())
+    fake = ctypes.c_void_p(0x1000)
+    cfg = gga.make_cfg(256, 10, 1)
+    assert gga.workspace_bytes(cfg, 36) <= gga.NOALLOC_SCRATCH_BYTES < gga.workspace_bytes(cfg, 37)
+    rc = gga.LIB.gga_simulate_noalloc(ctypes.byref(p), ctypes.byref(cfg), fake, fake, fake, 37, 3, fake, fake,
+                                      None, None)
+    assert rc == gga.E_SCRATCH and "scratch" in gga.LIB.gga_strerror(rc).decode()
+    bad = gga.make_cfg(256, 10, 1)
+    bad.struct_size = 3
+    assert gga.LIB.gga_simulate_noalloc(ctypes.byref(p), ctypes.byref(bad), fake, fake, fake, 1, 3, fake, fake,
+                                        None, None) == -2
+    assert gga.LIB.gga_simulate_noalloc(ctypes.byref(p), None, fake, fake, fake, 1, 3, fake, fake, None, None) == -1

@@ -675,11 +675,27 @@ int gga_set_variant(int32_t L, int32_t v);
 
 /*
  * Device workspace of gga_simulate_uneven for these HOST arrays lattice_h[P]
- * (64, 96, .., 256) and horizon_h[P] (>= 0 steps) under the current variant
- * choices; 0 for invalid arguments.
+ * (64, 96, .., 256) and horizon_h[P] (>= 0 steps), R replicas and `substeps`
+ * diffusion sub-steps per step (cfg->substeps of the call) under the current
+ * variant choices and team setting; 0 for invalid arguments.
  */
 size_t gga_uneven_workspace_bytes(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, int32_t K,
-                                  int32_t R);
+                                  int32_t R, int32_t substeps);
+
+/*
+ * Slab groups (sides without a resident variant, in gga_simulate and
+ * gga_simulate_uneven) run as teams by default: the slabs of one instance are
+ * co-resident workgroups of a cooperative launch that keep their rows on the
+ * compute unit for the instance's whole horizon and exchange halo rows
+ * through device memory after every step, each waiting for its neighbours'
+ * step count with a bounded spin.  A wait that runs out leaves the instance's
+ * live count negative (so its fitness is NaN) and every workgroup exits.
+ * Test hook, process-wide: use_teams = 0 runs slab groups as one launch per
+ * step instead (bit-identical results, larger workspace); spin_limit bounds
+ * each wait (default 2^21 polls; negative: every wait fails).  Workspace
+ * sizes depend on use_teams.  Returns GGA_OK or GGA_E_ARG.
+ */
+int gga_set_team_options(int32_t use_teams, int32_t spin_limit);
 
 /*
  * gga_simulate for a batch whose protocol p runs on a lattice_h[p] x
@@ -717,7 +733,7 @@ int gga_state_run_variant(const gga_params* params, const gga_sim_cfg* cfg, int3
                           hipStream_t stream);
 
 /* Workspace of gga_autotune: the largest uneven workspace over L's variants. */
-size_t gga_autotune_workspace_bytes(int32_t L, int32_t P, int32_t K, int32_t R, int32_t horizon);
+size_t gga_autotune_workspace_bytes(int32_t L, int32_t P, int32_t K, int32_t R, int32_t horizon, int32_t substeps);
 
 /*
  * Autotuner: simulate the protocols on side cfg->L for cfg->horizon steps with

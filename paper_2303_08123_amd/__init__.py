@@ -140,13 +140,14 @@ def _load():
         "gga_variant_name": ([i32], ctypes.c_char_p),
         "gga_get_variant": ([i32, i32], ctypes.c_int),
         "gga_set_variant": ([i32, i32], ctypes.c_int),
-        "gga_uneven_workspace_bytes": ([vp, vp, i32, i32, i32], ctypes.c_size_t),
+        "gga_uneven_workspace_bytes": ([vp, vp, i32, i32, i32, i32], ctypes.c_size_t),
+        "gga_set_team_options": ([i32, i32], ctypes.c_int),
         "gga_simulate_uneven": ([vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, ctypes.c_size_t, vp, vp, vp],
                                 ctypes.c_int),
         "gga_event_table_bytes": ([i32, i32], ctypes.c_size_t),
         "gga_state_run_variant": ([vp, vp, i32, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp,
                                    ctypes.c_size_t, vp, vp], ctypes.c_int),
-        "gga_autotune_workspace_bytes": ([i32, i32, i32, i32, i32], ctypes.c_size_t),
+        "gga_autotune_workspace_bytes": ([i32, i32, i32, i32, i32, i32], ctypes.c_size_t),
         "gga_autotune": ([vp, vp, vp, vp, vp, i32, i32, vp, ctypes.c_size_t, vp, vp, vp, vp], ctypes.c_int),
         "gga_measure_peaks": ([vp, ctypes.c_size_t, vp, vp, vp, vp], ctypes.c_int),
         "gga_params_from_json": ([ctypes.c_char_p, vp], ctypes.c_int),
@@ -179,7 +180,7 @@ EXPORTS = ("gga_version", "gga_strerror", "gga_last_hip_error", "gga_validate",
            "gga_mlp_set_norm", "gga_mlp_predict", "gga_mlp_grad", "gga_mlp_train_step", "gga_mlp_gemm",
            "gga_sga_workspace_bytes", "gga_sga_init", "gga_sga_generation", "gga_sga_run",
            "gga_variant_count", "gga_variant_side", "gga_variant_is_slab", "gga_variant_name", "gga_get_variant",
-           "gga_set_variant", "gga_uneven_workspace_bytes", "gga_simulate_uneven", "gga_event_table_bytes",
+           "gga_set_variant", "gga_set_team_options", "gga_uneven_workspace_bytes", "gga_simulate_uneven", "gga_event_table_bytes",
            "gga_state_run_variant", "gga_autotune_workspace_bytes", "gga_autotune", "gga_simulate_library",
            "gga_measure_peaks", "gga_params_from_json", "gga_slots_breed", "gga_slots_decode",
            "gga_slots_encode", "gga_slots_workspace_bytes", "gga_slots_run", "gga_q3_workspace_bytes",
@@ -455,10 +456,16 @@ def _host_i32(x, P, what):
     return a
 
 
-def uneven_workspace(lattice, horizon, P, K, R, device="cuda"):
+def set_team_options(use_teams=True, spin_limit=1 << 21):
+    """Test hook: slab groups as teams (default) or one launch per step; the
+    teams' bounded wait in polls (negative: every wait fails)."""
+    _check(LIB.gga_set_team_options(int(bool(use_teams)), int(spin_limit)))
+
+
+def uneven_workspace(lattice, horizon, P, K, R, device="cuda", substeps=10):
     lat, hor = _host_i32(lattice, P, "lattice"), _host_i32(horizon, P, "horizon")
     n = LIB.gga_uneven_workspace_bytes(lat.ctypes.data_as(ctypes.c_void_p), hor.ctypes.data_as(ctypes.c_void_p),
-                                       P, K, R)
+                                       P, K, R, int(substeps))
     if n == 0 and P > 0:
         raise GGAError("no uneven plan: lattice sides must be multiples of 32 in 64 .. 256 and horizons >= 0")
     return torch.empty(int(n), dtype=torch.uint8, device=device)
@@ -471,7 +478,7 @@ def simulate_uneven(params, cfg, dose, gap, nfrac, lattice, horizon, ws=None, ou
     P, K = _protocols(dose, gap, nfrac)
     lat, hor = _host_i32(lattice, P, "lattice"), _host_i32(horizon, P, "horizon")
     if ws is None:
-        ws = uneven_workspace(lat, hor, P, K, cfg.R, dose.device)
+        ws = uneven_workspace(lat, hor, P, K, cfg.R, dose.device, substeps=cfg.substeps)
     if out is None:
         out = (torch.empty((P, cfg.R), dtype=torch.int32, device=dose.device),
                torch.empty((P,), dtype=torch.float32, device=dose.device))
@@ -500,7 +507,7 @@ def autotune(params, cfg, dose, gap, nfrac, stream=None):
     """Time every kernel variant for cfg.L on these protocols (cfg.horizon steps)
     and make the fastest the choice for cfg.L.  Returns (variant, {variant: ms})."""
     P, K = _protocols(dose, gap, nfrac)
-    n = LIB.gga_autotune_workspace_bytes(cfg.L, P, K, cfg.R, cfg.horizon)
+    n = LIB.gga_autotune_workspace_bytes(cfg.L, P, K, cfg.R, cfg.horizon, cfg.substeps)
     ws = torch.empty(max(int(n), 1), dtype=torch.uint8, device=dose.device)
     live = torch.empty((P, cfg.R), dtype=torch.int32, device=dose.device)
     fit = torch.empty((P,), dtype=torch.float32, device=dose.device)

@@ -225,6 +225,11 @@ __global__ void fill_kernel(int32_t* p, int n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+__global__ void iota_kernel(int32_t* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
+}
+
 __global__ void counter_kernel(int32_t* generation, int32_t value, int32_t add) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *generation = add ? *generation + value : value;
 }
@@ -273,6 +278,12 @@ hipError_t launch_random_keys(int n, const int32_t* generation, uint64_t seed, f
 hipError_t launch_fill(int32_t* p, int n, int32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t* p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <limits>
 #include <vector>
 
@@ -102,33 +103,120 @@ int slab_plan(int L, int RR, int H, gga::SimArgs* a);
 // gga_simulate's workspace for a side without a resident variant: the event
 // table (rows of GGA_KMAX fractions, so the size does not depend on K) and two
 // state buffers of P * R instances (one read, the other written each step).
+// Slab groups run as teams (the slabs of an instance co-resident, state kept
+// on the CU for the whole horizon, halo rows exchanged through device memory)
+// unless switched off by the test hook; the spin count bounds each wait.
+std::atomic<int> g_use_teams{1};
+std::atomic<int> g_spin_limit{1 << 21};
+
+// Export rows of a slab plan for the team form: slab s publishes its own rows
+// [i0, exA) (the slab above's bottom halo) and [exB, i1) (the slab below's top
+// halo).  False when a halo row is not an own row of the adjacent slab.
+bool team_plan(gga::SimArgs* a, int RR) {
+    const int S = a->n_slabs;
+    for (int s = 0; s < S; ++s) {
+        const int ys = a->slab_ys[s], i0 = a->slab_i0[s], i1 = a->slab_i1[s];
+        int exA = i0, exB = i1;
+        if (s > 0) {
+            const int lo = a->slab_ys[s - 1] + a->slab_i1[s - 1] - ys, hi = a->slab_ys[s - 1] + RR - ys;
+            if (lo < i0 || hi > i1) return false;
+            exA = hi;
+        }
+        if (s < S - 1) {
+            const int lo = a->slab_ys[s + 1] - ys, hi = a->slab_ys[s + 1] + a->slab_i0[s + 1] - ys;
+            if (lo < i0 || hi > i1) return false;
+            exB = lo;
+        }
+        a->slab_exA[s] = exA;
+        a->slab_exB[s] = exB;
+    }
+    return true;
+}
+
+// Whether slab variant v runs lattice side L with `substeps` sub-steps as teams.
+bool uses_teams(int v, int L, int substeps) {
+    if (!g_use_teams.load() || v < 0 || !gga::variant_is_slab(v)) return false;
+    gga::SimArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const int RR = gga::SIM_VARIANTS[v].rpt * gga::SIM_VARIANTS[v].nw;
+    return slab_plan(L, RR, substeps + 2, &a) > 0 && team_plan(&a, RR);
+}
+
+// Instances whose state buffers a slab group keeps: all of them one step per
+// launch, a team launch's worth as teams.
+int32_t state_rows(bool teams, int32_t n) { return teams ? std::min<int32_t>(n, gga::TEAM_MAX) : n; }
+
+// gga_simulate's workspace for a side without a resident variant: the event
+// table (rows of GGA_KMAX fractions, so the size does not depend on K), the
+// instance list, the teams' step counts and two state buffers (one per step
+// parity) of the instances held at once.
 struct SimWs {
-    size_t off_valid, off_count, off_step, off_frac, off_state, state_bytes, total;
+    size_t off_valid, off_count, off_step, off_frac, off_list, off_flags, off_state, state_bytes, total;
+    int32_t rows;
+    bool teams;
 };
-SimWs simulate_ws_layout(int L, int32_t P, int32_t R) {
+SimWs simulate_ws_layout(int L, int substeps, int32_t P, int32_t R) {
     SimWs w{};
+    w.teams = uses_teams(gga::variant_choice(L, false), L, substeps);
+    w.rows = state_rows(w.teams, P * R);
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t at = off; off += align256(bytes); return at; };
     w.off_valid = take(sizeof(int32_t) * (size_t)P);
     w.off_count = take(sizeof(int32_t) * (size_t)P);
     w.off_step = take(sizeof(int32_t) * (size_t)P * GGA_KMAX);
     w.off_frac = take(sizeof(gga::EventFraction) * (size_t)P * GGA_KMAX);
-    w.state_bytes = align256((size_t)L * L * (3 * sizeof(float) + sizeof(uint16_t)) * (size_t)P * R);
+    w.off_list = take(w.teams ? sizeof(int32_t) * (size_t)P * R : 0);
+    w.off_flags = take(w.teams ? sizeof(int32_t) * (size_t)gga::TEAM_MAX * gga::MAX_SLABS : 0);
+    w.state_bytes = align256((size_t)L * L * (3 * sizeof(float) + sizeof(uint16_t)) * (size_t)w.rows);
     w.off_state = take(2 * w.state_bytes);
     w.total = off;
     return w;
 }
 
+// The instances at list positions 0 .. n-1 of a.inst_list as teams of slab
+// variant v, in cooperative launches of as many teams as the device holds at
+// once (at most `rows`, the instances the state buffers hold), each for its
+// instances' whole horizons.  a carries the slab plan with its export rows.
+hipError_t enqueue_teams(gga::SimArgs a, int v, int n, int rows, char* state, size_t state_bytes, int L,
+                         int32_t* flags, hipStream_t stream) {
+    int cap = 0;
+    hipError_t e = gga::launch_team_variant(v, a, 0, &cap, stream);
+    if (e != hipSuccess) return e;
+    const int teams = std::min(8 * (cap / (8 * a.n_slabs)), rows);
+    if (teams < 1) return hipErrorInvalidConfiguration;
+    const size_t fbytes = (size_t)L * L * 3 * sizeof(float) * (size_t)rows;
+    a.fields = reinterpret_cast<float*>(state);
+    a.cells = reinterpret_cast<uint16_t*>(state + fbytes);
+    a.fields_out = reinterpret_cast<float*>(state + state_bytes);
+    a.cells_out = reinterpret_cast<uint16_t*>(state + state_bytes + fbytes);
+    a.team_flags = flags;
+    a.spin_limit = g_spin_limit.load();
+    a.mode = 0;
+    a.n0 = 0;
+    const int32_t* list = a.inst_list;
+    for (int k0 = 0; k0 < n && e == hipSuccess; k0 += teams) {
+        const int m = std::min(teams, n - k0);
+        a.inst_list = list + k0;
+        a.n_active = m;
+        e = gga::launch_fill(flags, m * a.n_slabs, 0, stream);
+        if (e == hipSuccess) e = gga::launch_team_variant(v, a, gga::slab_blocks(m, a.n_slabs), &cap, stream);
+    }
+    return e;
+}
+
 // Slab-form simulation of all P * R instances for cfg->horizon steps: event
-// table, initial state, then one launch per step alternating the two state
-// buffers; the live count of the last step (and of every step into traj) is
-// summed over the slabs.
+// table and live counts, then teams over whole horizons, or (teams off) the
+// initial state and one launch per step alternating the two state buffers;
+// the live count of the last step (and of every step into traj) is summed
+// over the slabs.
 hipError_t enqueue_simulate_slabs(gga::SimArgs a, const gga_sim_cfg* cfg, int32_t P, int32_t K, char* ws,
                                   const SimWs& w, hipStream_t stream) {
     const int v = gga::variant_choice(cfg->L, false);
     if (v < 0 || !gga::variant_is_slab(v)) return hipErrorInvalidValue;
     const gga::SimVariant& var = gga::SIM_VARIANTS[v];
-    if (slab_plan(cfg->L, var.rpt * var.nw, cfg->substeps + 2, &a) <= 0) return hipErrorInvalidValue;
+    const int RR = var.rpt * var.nw;
+    if (slab_plan(cfg->L, RR, cfg->substeps + 2, &a) <= 0) return hipErrorInvalidValue;
+    if (w.teams && !team_plan(&a, RR)) return hipErrorInvalidValue;
     int32_t* valid = reinterpret_cast<int32_t*>(ws + w.off_valid);
     int32_t* count = reinterpret_cast<int32_t*>(ws + w.off_count);
     int32_t* step = reinterpret_cast<int32_t*>(ws + w.off_step);
@@ -140,6 +228,19 @@ hipError_t enqueue_simulate_slabs(gga::SimArgs a, const gga_sim_cfg* cfg, int32_
     a.count_at = cfg->horizon;
     a.mode = 0;
     const int n = P * cfg->R;
+    hipError_t e = gga::launch_event_table(a, P, valid, count, step, frac, stream);
+    if (e == hipSuccess && a.traj) e = gga::launch_fill(a.traj, n * cfg->horizon, 0, stream);
+    if (w.teams) {
+        int32_t* list = reinterpret_cast<int32_t*>(ws + w.off_list);
+        if (e == hipSuccess) e = gga::launch_iota(list, n, stream);
+        a.inst_list = list;
+        a.nsteps = cfg->horizon;
+        if (e == hipSuccess) e = gga::launch_slab_live(a, n, stream);
+        if (e == hipSuccess)
+            e = enqueue_teams(a, v, n, w.rows, ws + w.off_state, w.state_bytes, cfg->L,
+                              reinterpret_cast<int32_t*>(ws + w.off_flags), stream);
+        return e;
+    }
     const size_t fbytes = (size_t)cfg->L * cfg->L * 3 * sizeof(float) * (size_t)n;
     char* s0 = ws + w.off_state;
     char* s1 = s0 + w.state_bytes;
@@ -147,8 +248,6 @@ hipError_t enqueue_simulate_slabs(gga::SimArgs a, const gga_sim_cfg* cfg, int32_
     uint16_t* ca = reinterpret_cast<uint16_t*>(s0 + fbytes);
     float* fb = reinterpret_cast<float*>(s1);
     uint16_t* cb = reinterpret_cast<uint16_t*>(s1 + fbytes);
-    hipError_t e = gga::launch_event_table(a, P, valid, count, step, frac, stream);
-    if (e == hipSuccess && a.traj) e = gga::launch_fill(a.traj, n * cfg->horizon, 0, stream);
     if (e == hipSuccess) e = gga::launch_slab_init(a, cfg->L, n, fa, ca, stream);
     for (int32_t t = 0; t < cfg->horizon && e == hipSuccess; ++t) {
         a.n0 = t;
@@ -263,7 +362,7 @@ int gga_population_random(const gga_alphabet* a, int32_t P, int32_t K, uint64_t 
 size_t gga_workspace_bytes(const gga_sim_cfg* cfg, int32_t P) {
     if (!cfg || cfg->struct_size != sizeof(gga_sim_cfg) || check_batch(P, 0, cfg->R) || cfg->R < 1) return 0;
     if (gga::side_index(cfg->L) < 0 || gga::sim_supported(cfg->L)) return 0;   // resident: state stays on the CU
-    return simulate_ws_layout(cfg->L, P, cfg->R).total;
+    return simulate_ws_layout(cfg->L, cfg->substeps, P, cfg->R).total;
 }
 
 int gga_simulate(const gga_params* params, const gga_sim_cfg* cfg, const float* dose_d,
@@ -294,7 +393,7 @@ int gga::simulate_checked(const gga_params* params, const gga_sim_cfg* cfg, cons
         a.mode = 0;
         e = gga::launch_simulation(a, cfg->L, P * cfg->R, stream);
     } else {                                         // slabs: state in the workspace, one launch per step
-        const SimWs w = simulate_ws_layout(cfg->L, P, cfg->R);
+        const SimWs w = simulate_ws_layout(cfg->L, cfg->substeps, P, cfg->R);
         if (!ws_d || misaligned16(ws_d) || ws_bytes < w.total) return GGA_E_ARG;
         if (traj_d && (long long)P * cfg->R * cfg->horizon > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;
         e = enqueue_simulate_slabs(a, cfg, P, K, static_cast<char*>(ws_d), w, stream);
@@ -1262,7 +1361,9 @@ size_t state_bytes(int L) { return (size_t)L * L * (3 * sizeof(float) + sizeof(u
 // One group of instances that share a lattice side (and so a kernel variant).
 struct Group {
     int L, variant, first, count, max_h;   // instances list[first .. first+count), horizon-descending
-    size_t state_off;                      // slab form: two state buffers of count instances
+    bool teams;                            // slab form as teams over whole horizons
+    int rows;                              // slab form: instances the state buffers hold
+    size_t state_off, flags_off;           // slab form: two state buffers of `rows` instances; team step counts
 };
 
 struct UnevenPlan {
@@ -1274,7 +1375,7 @@ struct UnevenPlan {
 // Group the P*R instances by lattice side, each group sorted by horizon
 // (longest first, then by index), and lay out the workspace.
 int plan_uneven(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, int32_t K, int32_t R,
-                const int* force, UnevenPlan* plan) {
+                int32_t substeps, const int* force, UnevenPlan* plan) {
     for (int32_t p = 0; p < P; ++p) {
         if (!side_ok(lattice_h[p])) return GGA_E_UNSUPPORTED;
         if (horizon_h[p] < 0 || horizon_h[p] > (1 << 30)) return GGA_E_ARG;
@@ -1292,7 +1393,9 @@ int plan_uneven(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, i
                          [&](int32_t x, int32_t y) { return horizon_h[x / R] > horizon_h[y / R]; });
         const int v = force && force[si] >= 0 ? force[si] : gga::variant_choice(L, false);
         if (v < 0) return GGA_E_UNSUPPORTED;
-        Group g{L, v, (int)plan->host.size(), (int)list.size(), horizon_h[list[0] / R], 0};
+        const bool teams = uses_teams(v, L, substeps);
+        Group g{L, v, (int)plan->host.size(), (int)list.size(), horizon_h[list[0] / R], teams,
+                state_rows(teams, (int32_t)list.size()), 0, 0};
         plan->groups.push_back(g);
         plan->host.insert(plan->host.end(), list.begin(), list.end());
     }
@@ -1307,7 +1410,10 @@ int plan_uneven(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, i
     plan->off_step = take(sizeof(int32_t) * (size_t)P * K);
     plan->off_frac = take(sizeof(gga::EventFraction) * (size_t)P * K);
     for (auto& g : plan->groups)
-        if (gga::variant_is_slab(g.variant)) g.state_off = take(2 * state_bytes(g.L) * (size_t)g.count);
+        if (gga::variant_is_slab(g.variant)) {
+            g.state_off = take(2 * align256(state_bytes(g.L) * (size_t)g.rows));
+            if (g.teams) g.flags_off = take(sizeof(int32_t) * (size_t)gga::TEAM_MAX * gga::MAX_SLABS);
+        }
     plan->total = off;
     return GGA_OK;
 }
@@ -1339,7 +1445,17 @@ hipError_t enqueue_uneven(const gga::SimArgs& base, const UnevenPlan& plan, char
         }
         const gga::SimVariant& v = gga::SIM_VARIANTS[g.variant];
         if (slab_plan(g.L, v.rpt * v.nw, a.substeps + 2, &a) <= 0) return hipErrorInvalidValue;
-        const size_t sb = state_bytes(g.L) * (size_t)g.count;
+        if (g.teams) {
+            if (!team_plan(&a, v.rpt * v.nw)) return hipErrorInvalidValue;
+            a.nsteps = 0;                          // steps come from horizon[]
+            e = gga::launch_slab_live(a, g.count, stream);
+            if (e == hipSuccess)
+                e = enqueue_teams(a, g.variant, g.count, g.rows, ws + g.state_off,
+                                  align256(state_bytes(g.L) * (size_t)g.rows), g.L,
+                                  reinterpret_cast<int32_t*>(ws + g.flags_off), stream);
+            continue;
+        }
+        const size_t sb = align256(state_bytes(g.L) * (size_t)g.count);
         float* fa = reinterpret_cast<float*>(ws + g.state_off);
         uint16_t* ca = reinterpret_cast<uint16_t*>(ws + g.state_off + (size_t)g.count * g.L * g.L * 3 * sizeof(float));
         float* fb = reinterpret_cast<float*>(ws + g.state_off + sb);
@@ -1395,6 +1511,13 @@ extern "C" {
 
 int gga_variant_count(void) { return gga::N_SIM_VARIANTS; }
 
+int gga_set_team_options(int32_t use_teams, int32_t spin_limit) {
+    if (use_teams != 0 && use_teams != 1) return GGA_E_ARG;
+    g_use_teams.store(use_teams);
+    g_spin_limit.store(spin_limit);
+    return GGA_OK;
+}
+
 int32_t gga_variant_side(int32_t v) { return (v >= 0 && v < gga::N_SIM_VARIANTS) ? gga::SIM_VARIANTS[v].L : -1; }
 
 int32_t gga_variant_is_slab(int32_t v) {
@@ -1413,10 +1536,11 @@ int gga_get_variant(int32_t L, int32_t resident_only) {
 int gga_set_variant(int32_t L, int32_t v) { return gga::set_variant_choice(L, v) == 0 ? GGA_OK : GGA_E_ARG; }
 
 size_t gga_uneven_workspace_bytes(const int32_t* lattice_h, const int32_t* horizon_h, int32_t P, int32_t K,
-                                  int32_t R) {
+                                  int32_t R, int32_t substeps) {
     if (check_batch(P, K, R) || R < 1 || (P > 0 && (!lattice_h || !horizon_h))) return 0;
+    if (substeps < 1 || substeps > 64) return 0;
     UnevenPlan plan;
-    if (plan_uneven(lattice_h, horizon_h, P, K, R, nullptr, &plan)) return 0;
+    if (plan_uneven(lattice_h, horizon_h, P, K, R, substeps, nullptr, &plan)) return 0;
     return plan.total;
 }
 
@@ -1433,7 +1557,7 @@ int gga_simulate_uneven(const gga_params* params, const gga_sim_cfg* cfg, const 
         (K > 0 && (!dose_d || !gap_h_d)))
         return GGA_E_ARG;
     UnevenPlan plan;
-    if ((rc = plan_uneven(lattice_h, horizon_h, P, K, cfg->R, nullptr, &plan))) return rc;
+    if ((rc = plan_uneven(lattice_h, horizon_h, P, K, cfg->R, cfg->substeps, nullptr, &plan))) return rc;
     if (ws_bytes < plan.total) return GGA_E_ARG;
     char* ws = static_cast<char*>(ws_d);
     if ((rc = upload_plan(plan, ws, P, stream))) return rc;
@@ -1510,8 +1634,9 @@ int gga_state_run_variant(const gga_params* params, const gga_sim_cfg* cfg, int3
     return e == hipSuccess ? GGA_OK : hip_fail(e);
 }
 
-size_t gga_autotune_workspace_bytes(int32_t L, int32_t P, int32_t K, int32_t R, int32_t horizon) {
+size_t gga_autotune_workspace_bytes(int32_t L, int32_t P, int32_t K, int32_t R, int32_t horizon, int32_t substeps) {
     if (!side_ok(L) || P < 1 || R < 1 || horizon < 0 || check_batch(P, K, R)) return 0;
+    if (substeps < 1 || substeps > 64) return 0;
     std::vector<int32_t> lat((size_t)P, L), hor((size_t)P, horizon);
     size_t most = 0;
     const int si = gga::side_index(L);
@@ -1520,7 +1645,8 @@ size_t gga_autotune_workspace_bytes(int32_t L, int32_t P, int32_t K, int32_t R, 
         int force[gga::N_SIDES] = {-1, -1, -1, -1, -1, -1, -1};
         force[si] = v;
         UnevenPlan plan;
-        if (plan_uneven(lat.data(), hor.data(), P, K, R, force, &plan) == GGA_OK) most = std::max(most, plan.total);
+        if (plan_uneven(lat.data(), hor.data(), P, K, R, substeps, force, &plan) == GGA_OK)
+            most = std::max(most, plan.total);
     }
     return most;
 }
@@ -1550,7 +1676,7 @@ int gga_autotune(const gga_params* params, const gga_sim_cfg* cfg, const float* 
         int force[gga::N_SIDES] = {-1, -1, -1, -1, -1, -1, -1};
         force[si] = v;
         UnevenPlan plan;
-        if (plan_uneven(lat.data(), hor.data(), P, K, cfg->R, force, &plan) != GGA_OK) continue;
+        if (plan_uneven(lat.data(), hor.data(), P, K, cfg->R, cfg->substeps, force, &plan) != GGA_OK) continue;
         if (ws_bytes < plan.total) { rc = GGA_E_ARG; break; }
         if ((rc = upload_plan(plan, ws, P, stream))) break;
         float ms = 0.0f;

@@ -54,6 +54,12 @@ struct SimArgs {
     int32_t count_at;         // slab form without horizon[]: the step whose end is counted (and the
                               // row length of traj, which then receives every slab's count per step)
     int32_t lib_n;            // resident form with MODE_LOAD: replica r loads state r mod lib_n (0: its own)
+    // Teams (slab form over whole horizons): per slab the own rows it publishes
+    // for its neighbours, [i0, exA) and [exB, i1); per list position and slab
+    // the published step count; the bounded wait's spin count (< 0: every wait fails)
+    int32_t slab_exA[16], slab_exB[16];
+    int32_t* team_flags;      // [n_active][n_slabs], zero before the launch
+    int32_t spin_limit;
 };
 constexpr int MAX_SLABS = 16;
 
@@ -106,6 +112,12 @@ hipError_t launch_simulation(const SimArgs& a, int L, int n_inst, hipStream_t st
 inline int slab_blocks(int n_active, int n_slabs) { return ((n_active + 7) / 8) * 8 * n_slabs; }
 hipError_t launch_variant(int v, const SimArgs& a, int n_blocks, hipStream_t stream);
 hipError_t launch_slab_variant(int v, const SimArgs& a, int n_blocks, hipStream_t stream);
+// team form of slab variant v (a cooperative launch of n_blocks workgroups; the
+// slab mapping of the kernel with n_active teams); n_blocks = 0 only reports in
+// *capacity how many workgroups of it the device holds at once
+hipError_t launch_team_variant(int v, const SimArgs& a, int n_blocks, int* capacity, hipStream_t stream);
+// instances per team launch at most (exchange buffers are sized for this many)
+constexpr int TEAM_MAX = 128;
 // process-wide variant choice per lattice side: resident (gga_simulate) and any (uneven batches)
 int variant_choice(int L, bool resident_only);
 int set_variant_choice(int L, int v);
@@ -173,5 +185,7 @@ hipError_t launch_gather(const float* sd, const int32_t* sg, const float* sf, co
                          float* dd, int32_t* dg, float* df, hipStream_t s);
 hipError_t launch_random_keys(int n, const int32_t* generation, uint64_t seed, float* key, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int n, int32_t v, hipStream_t s);
+// p[i] = i for i < n
+hipError_t launch_iota(int32_t* p, int n, hipStream_t s);
 
 }  // namespace gga

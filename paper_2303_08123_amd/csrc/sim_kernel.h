@@ -28,6 +28,15 @@
 // computed, not stored, and owned by the neighbouring slab.  Every site's
 // arithmetic is the resident form's, so both give identical results.
 //
+// Teams (TEAM): the slabs of one instance are a team of co-resident
+// workgroups (a cooperative launch) that keep their rows on the CU for the
+// whole horizon.  After each step a workgroup publishes the own rows its
+// neighbours hold as halo (into one of two exchange buffers, by step parity)
+// and a per-slab step count; before the next step it waits for both
+// neighbours' counts, with a bounded spin, and reloads only its halo rows.
+// A wait that runs out marks the instance's live count negative and the
+// workgroup leaves; its neighbours then run out too, so every workgroup exits.
+//
 // The method (Materials and Methods: nutrient and waste diffusion, cell
 // cycle, quiescence and death driven by the local environment, irradiation
 // damage; fitness from the final number of occupied sites, equation
@@ -216,11 +225,12 @@ struct Geo {
 // EXT: the extended radiobiology (the oxygen effect on radiosensitivity,
 // gga_params.oer_max > 1, and mitotic death, gga_params.mitotic_death), a
 // separate instantiation so that runs without them keep their register budget.
-template <int CPL, int RPT, int NW, int LW, bool EXT>
+template <int CPL, int RPT, int NW, int LW, bool EXT, bool TEAM = false>
 __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     using G = Geo<CPL, RPT, NW, LW>;
     constexpr int L = G::L;
     constexpr bool PAD = G::PAD;
+    static_assert(!TEAM || G::SLAB, "teams are made of slabs");
     constexpr int RR = G::RR;
     constexpr int NWAVE = G::NWAVE;
     constexpr bool SLAB = G::SLAB;
@@ -237,6 +247,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     __shared__ uint32_t s_oer_thr[EXT ? 4 : 1][EXT ? GGA_OER_BINS : 1];
     __shared__ int s_nev, s_valid, s_evj[2];
     __shared__ int s_count[2];
+    __shared__ int s_team_ok;
     __shared__ float s_react[4];               // reaction term per cell state
     __shared__ CellConst s_k;                  // cell-update constants, read where used
 
@@ -269,7 +280,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     const int ys = SLAB ? a.slab_ys[slab] : 0;
     const int iy0 = SLAB ? a.slab_i0[slab] : 0, iy1 = SLAB ? a.slab_i1[slab] : RR;
     const int lat0 = ys * LW;                        // lattice index of the slab's first site
-    const int nsteps = (!SLAB && a.horizon) ? a.horizon[p] : a.nsteps;
+    const int nsteps = ((!SLAB || TEAM) && a.horizon) ? a.horizon[p] : a.nsteps;
     const int y0 = wave * RPT;
     const int x0 = lane * CPL;
     const bool real = !PAD || x0 < LW;               // lanes past the lattice hold padding
@@ -288,7 +299,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     }
 
     // ---- protocol: validity and irradiation events ----
-    if constexpr (SLAB) {
+    if constexpr (SLAB && !TEAM) {
         // event table (times in half-hours; at most one fraction at the start of
         // step n0 and one at its middle): lane j of wave 0 checks fraction j
         if (wave == 0) {
@@ -317,7 +328,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         int nev = 0;
         double total = 0.0;
         long long t = 0;
-        for (int j = 0; !SLAB && valid && j < k; ++j) {
+        for (int j = 0; (!SLAB || TEAM) && valid && j < k; ++j) {
             const float d = a.dose[(size_t)p * a.K + j];
             const int g = a.gap[(size_t)p * a.K + j];
             if (!(d >= 0.0f) || !isfinite(d)) { valid = 0; break; }
@@ -335,7 +346,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             }
         }
         if (valid && total > a.dose_cap + 1e-6) valid = 0;
-        if (!SLAB) {
+        if (!SLAB || TEAM) {
             s_valid = valid;
             s_nev = nev;
         }
@@ -357,7 +368,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         return;                                   // uniform across the workgroup
     }
     const int nev = s_nev;
-    if constexpr (SLAB) {
+    if constexpr (SLAB && !TEAM) {
         if (tid < nev) {
             const EventFraction ef = a.ev_frac[(size_t)p * a.K + s_evj[tid]];
             s_ev_dose[tid] = ef.dose;
@@ -372,7 +383,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     // ---- state: fields in registers, cells in LDS ----
     float F[3][RPT + 1][CPL];                  // slot RPT: spare row for the rotating sub-steps
     const size_t plane = (size_t)LW * LW;      // device-memory state: [3][LW][LW] fields, [LW][LW] cells
-    if (SLAB || (a.mode & MODE_LOAD)) {
+    if ((SLAB && !TEAM) || (a.mode & MODE_LOAD)) {
         const float* src = a.fields + (size_t)slot * 3 * plane + lat0;
 #pragma unroll
         for (int f = 0; f < 3; ++f)
@@ -403,14 +414,14 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         for (int i = 0; i < RPT; ++i)
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                const int y = y0 + i, x = x0 + c;
+                const int y = ys + y0 + i, x = x0 + c;       // lattice row and column
                 uint16_t w = 0;
                 if (real && (x - ctr) * (x - ctr) + (y - ctr) * (y - ctr) <= rad2) {
                     const Block4 b = philox10(y * LW + x, INIT_STEP, r, p, seed_lo, seed_hi);
                     const uint32_t age = (uint32_t)(((uint64_t)b.w0 * (uint32_t)P.A0) >> 32);
                     w = (uint16_t)(PROLIF | (age << 2));
                 }
-                s_cell[y * L + x] = w;
+                s_cell[(y0 + i) * L + x] = w;
             }
     }
 
@@ -435,6 +446,55 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     __syncthreads();
 
     for (int n = a.n0; n < a.n0 + nsteps; ++n) {
+        if constexpr (TEAM) {
+            // the neighbouring slabs' rows of step n: wait for their step
+            // counts, then reload this slab's halo rows from the exchange
+            if (n > a.n0) {
+                const int t = n - a.n0;
+                // Polls are relaxed device-scope loads; one acquire fence
+                // follows the last (an acquire per poll would invalidate the
+                // caches on every iteration).  The compute unit's caches are
+                // shared by the workgroup's waves, and none of them reads the
+                // exchange rows before the barrier that follows the fence.
+                if (tid == 0) {
+                    int ok = a.spin_limit >= 0;
+                    for (int nb = slab - 1; ok && nb <= slab + 1; nb += 2) {
+                        if (nb < 0 || nb >= a.n_slabs) continue;
+                        const int32_t* f = a.team_flags + (size_t)slot * a.n_slabs + nb;
+                        int k = 0;
+                        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < t) {
+                            if (++k > a.spin_limit) { ok = 0; break; }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    s_team_ok = ok;
+                }
+                __syncthreads();
+                if (!s_team_ok) {                        // uniform: this workgroup leaves
+                    if (tid == 0 && a.live) atomicExch(&a.live[inst], (int)0x80000000);
+                    return;
+                }
+                const float* src = ((t & 1) ? a.fields_out : a.fields) + (size_t)slot * 3 * plane + lat0;
+                const uint16_t* cs = ((t & 1) ? a.cells_out : a.cells) + (size_t)slot * plane + lat0;
+                // per halo row: the cell words first (one load), then the
+                // fields, so that the LDS write waits for the words alone
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const int y = y0 + i;
+                    if (real && (y < iy0 || y >= iy1)) {
+                        uint32_t w[CPL];
+                        load_words<CPL>(cs + (size_t)y * LW + x0, w);
+#pragma unroll
+                        for (int f = 0; f < 3; ++f)
+#pragma unroll
+                            for (int c = 0; c < CPL; ++c) F[f][i][c] = src[f * plane + (size_t)y * LW + x0 + c];
+                        store_words<CPL>(s_cell + y * L + x0, w);
+                    }
+                }
+                __syncthreads();                          // halo cells in before anyone reads them
+            }
+        }
         // Every LDS access below addresses a row as base + constant offset.  The
         // base is opaque to the compiler at the top of each step, so per-row
         // addresses are not hoisted out of the loop into registers.
@@ -839,33 +899,64 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             count = s_count[n & 1];
             s_count[(n + 1) & 1] = 0;
             if (!SLAB && a.traj) a.traj[(size_t)inst * a.nsteps + (n - a.n0)] = count;
-            // slabs (one step per launch): this slab's share of step n's count
+            // slabs: this slab's share of step n's count
             if (SLAB && a.traj) atomicAdd(&a.traj[(size_t)inst * a.count_at + n], count);
+        }
+        if constexpr (TEAM) {
+            // publish the own rows the neighbours hold as halo, then the step count
+            if (n + 1 < a.n0 + nsteps) {
+                const int t1 = n + 1 - a.n0;
+                float* fd = ((t1 & 1) ? a.fields_out : a.fields) + (size_t)slot * 3 * plane + lat0;
+                uint16_t* cd = ((t1 & 1) ? a.cells_out : a.cells) + (size_t)slot * plane + lat0;
+                const int exA = a.slab_exA[slab], exB = a.slab_exB[slab];
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const int y = y0 + i;
+                    if (real && y >= iy0 && y < iy1 && (y < exA || y >= exB)) {
+#pragma unroll
+                        for (int f = 0; f < 3; ++f)
+#pragma unroll
+                            for (int c = 0; c < CPL; ++c) fd[f * plane + (size_t)y * LW + x0 + c] = F[f][i][c];
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c) cd[(size_t)y * LW + x0 + c] = s_cell[y * L + x0 + c];
+                    }
+                }
+                // every wave's rows have reached the cache hierarchy before the
+                // barrier; one device-scope release then publishes them all
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+                if (tid == 0)
+                    __hip_atomic_store(a.team_flags + (size_t)slot * a.n_slabs + slab, t1, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
 
-    if (!SLAB && nsteps == 0) {
+    if ((!SLAB || TEAM) && nsteps == 0) {
         int live = 0;
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int st = s_cell[(y0 + i) * L + x0 + c] & 3;
-                live += (st == PROLIF || st == QUIESC);
+                live += (st == PROLIF || st == QUIESC) && (!SLAB || (y0 + i >= iy0 && y0 + i < iy1));
             }
         live = wave_sum(live);
         if (lane == 0) atomicAdd(&s_count[0], live);
         __syncthreads();
         if (tid == 0) count = s_count[0];
     }
-    if constexpr (SLAB) {
+    if constexpr (TEAM) {
+        // the instance's last step (or its initial state): this slab's share
+        if (tid == 0 && a.live) atomicAdd(&a.live[inst], count);
+    } else if constexpr (SLAB) {
         // the instance's last step: add this slab's share of the live count
         if (tid == 0 && a.live && a.n0 + 1 == (a.horizon ? a.horizon[p] : a.count_at)) atomicAdd(&a.live[inst], count);
     } else {
         if (tid == 0 && a.live) a.live[inst] = count;
     }
 
-    if (SLAB || (a.mode & MODE_STORE)) {
+    if ((SLAB && !TEAM) || (a.mode & MODE_STORE)) {
         // slabs write their own rows into the other state buffer
         float* dst = (SLAB ? a.fields_out : a.fields) + (size_t)slot * 3 * plane + lat0;
 #pragma unroll

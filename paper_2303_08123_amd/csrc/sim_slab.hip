@@ -86,6 +86,30 @@ hipError_t launch_slab(const SimArgs& a, int n_blocks, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// The team form: every workgroup of the grid resident at once (a cooperative
+// launch), so each team's slabs can wait for one another.  With n_blocks = 0,
+// returns in *capacity the most workgroups of this kernel the device holds at
+// once instead of launching.
+template <int CPL, int RPT, int NW, int LW = 64 * CPL>
+hipError_t launch_team(const SimArgs& a, int n_blocks, int* capacity, hipStream_t stream) {
+    using G = Geo<CPL, RPT, NW, LW>;
+    static_assert(G::SLAB, "teams are made of slabs");
+    const bool ext = a.prm.oer_max > 1.0 || a.prm.mitotic_death;
+    const void* fn = ext ? reinterpret_cast<const void*>(&sim_kernel<CPL, RPT, NW, LW, true, true>)
+                         : reinterpret_cast<const void*>(&sim_kernel<CPL, RPT, NW, LW, false, true>);
+    if (n_blocks == 0) {
+        int dev = 0, per_cu = 0, cus = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, G::NT, 0);
+        *capacity = e == hipSuccess ? per_cu * cus : 0;
+        return e;
+    }
+    SimArgs arg = a;
+    void* params[] = {&arg};
+    return hipLaunchCooperativeKernel(fn, dim3(n_blocks), dim3(G::NT), params, 0, stream);
+}
+
 }  // namespace
 
 hipError_t launch_slab_variant(int v, const SimArgs& a, int n_blocks, hipStream_t stream) {
@@ -102,6 +126,23 @@ hipError_t launch_slab_variant(int v, const SimArgs& a, int n_blocks, hipStream_
         case 15: return launch_slab<4, 4, 16, 224>(a, n_blocks, stream);
         case 16: return launch_slab<4, 8, 8, 224>(a, n_blocks, stream);
         case 17: return launch_slab<2, 4, 16, 96>(a, n_blocks, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_team_variant(int v, const SimArgs& a, int n_blocks, int* capacity, hipStream_t stream) {
+    switch (v) {
+        case 1: return launch_team<1, 2, 16>(a, n_blocks, capacity, stream);
+        case 4: return launch_team<2, 4, 16>(a, n_blocks, capacity, stream);
+        case 5: return launch_team<4, 4, 16>(a, n_blocks, capacity, stream);
+        case 6: return launch_team<4, 8, 8>(a, n_blocks, capacity, stream);
+        case 11: return launch_team<4, 4, 16, 160>(a, n_blocks, capacity, stream);
+        case 12: return launch_team<4, 8, 8, 160>(a, n_blocks, capacity, stream);
+        case 13: return launch_team<4, 4, 16, 192>(a, n_blocks, capacity, stream);
+        case 14: return launch_team<4, 8, 8, 192>(a, n_blocks, capacity, stream);
+        case 15: return launch_team<4, 4, 16, 224>(a, n_blocks, capacity, stream);
+        case 16: return launch_team<4, 8, 8, 224>(a, n_blocks, capacity, stream);
+        case 17: return launch_team<2, 4, 16, 96>(a, n_blocks, capacity, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -176,7 +176,7 @@ def _uneven_bytes(gga, lattice, horizon, K, R):
     lat = np.ascontiguousarray(lattice, np.int32)
     hor = np.ascontiguousarray(horizon, np.int32)
     return gga.LIB.gga_uneven_workspace_bytes(lat.ctypes.data_as(ctypes.c_void_p), hor.ctypes.data_as(ctypes.c_void_p),
-                                              len(lat), K, R)
+                                              len(lat), K, R, 10)
 
 
 def test_uneven_workspace_holds_two_states_per_slab_instance(gga):
@@ -194,6 +194,14 @@ def test_uneven_workspace_holds_two_states_per_slab_instance(gga):
     assert _uneven_bytes(gga, [64, 96], [10, 10], 8, 1) > 0      # 96 is resident: lists and tables only
     assert _uneven_bytes(gga, [64, 96], [10, 10], 8, 1) < 1 << 20
     assert _uneven_bytes(gga, [64, 160], [10, 10], 8, 1) >= 2 * 160 * 160 * 14
+    # teams hold at most 128 instances of a slab side at once; one launch per step holds all
+    lat, hor = [256] * 50, [10] * 50
+    try:
+        assert 2 * 128 * 256 * 256 * 14 <= _uneven_bytes(gga, lat, hor, 8, 4) < 2 * 129 * 256 * 256 * 14
+        gga.set_team_options(False)
+        assert _uneven_bytes(gga, lat, hor, 8, 4) >= 2 * 200 * 256 * 256 * 14
+    finally:
+        gga.set_team_options(True)
     assert _uneven_bytes(gga, [64, 80], [10, 10], 8, 1) == 0     # unsupported side
     assert _uneven_bytes(gga, [64, 64], [10, -1], 8, 1) == 0     # negative horizon
 
@@ -385,16 +393,27 @@ def test_params_from_json_reads_the_model_file(gga, tmp_path):
 
 
 def test_simulate_workspace_sizes(gga):
-    """gga_workspace_bytes: none for the resident sides; the event table and
-    two state buffers per instance for the slab sides."""
+    """gga_workspace_bytes: none for the resident sides; for the slab sides the
+    event table and two state buffers, of at most 128 instances as teams (one
+    cooperative launch's worth, plus the instance list and step counts) or of
+    every instance with one launch per step."""
     for L in (64, 96, 128):
         assert gga.workspace_bytes(gga.make_cfg(L, 10, 4), 100) == 0
-    for L in (160, 192, 224, 256):
-        cfg = gga.make_cfg(L, 10, 4)
-        n = gga.workspace_bytes(cfg, 100)
-        state = 2 * 400 * L * L * 14
-        assert state <= n <= state + 100 * (8 + 20 * 64) + 6 * 256, (L, n)
-        assert gga.workspace_bytes(cfg, 0) < 1 << 12
+    table = 100 * (8 + 20 * 64)
+    try:
+        for teams, rows in ((True, 128), (False, 400)):
+            gga.set_team_options(teams)
+            for L in (160, 192, 224, 256):
+                cfg = gga.make_cfg(L, 10, 4)
+                n = gga.workspace_bytes(cfg, 100)
+                state = 2 * rows * L * L * 14
+                extra = table + (400 * 4 + 128 * 16 * 4 if teams else 0) + 8 * 256
+                assert state <= n <= state + extra, (teams, L, n)
+                assert gga.workspace_bytes(cfg, 0) < 1 << 14
+                small = gga.workspace_bytes(cfg, 2)                       # 8 instances either way
+                assert 2 * 8 * L * L * 14 <= small <= 2 * 8 * L * L * 14 + 2 * (1 << 14)
+    finally:
+        gga.set_team_options(True)
     bad = gga.make_cfg(160, 10, 4)
     bad.struct_size = 3
     assert gga.workspace_bytes(bad, 10) == 0 and gga.workspace_bytes(gga.make_cfg(160, 10, 4), -1) == 0

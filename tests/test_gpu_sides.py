@@ -184,3 +184,76 @@ def test_uneven_batch_of_all_seven_sides(gga, model_dict):
     assert np.allclose(fit, ref.mean(1))
     assert live[7, 0] == 113 and live[11, 1] == 113            # horizon 0: the seed disc
 
+
+
+@pytest.mark.parametrize("L", [160, 192, 224, 256])
+def test_teams_equal_one_launch_per_step(gga, model_dict, L):
+    """The team form (slabs co-resident for the whole horizon, halo rows
+    exchanged through device memory) gives the per-step slab form's results
+    bit for bit: live counts, fitness and every step's count."""
+    print(f"teams vs per-step L={L}", flush=True)
+    md = high_uptake(model_dict)
+    P, K, R = 5, 4, 3
+    dose, gap, nfrac = workloads.random_protocols(P, K, seed=L, kmin=1)
+    dd = _dev(dose, gap, nfrac)
+    cfg = gga.make_cfg(L, 40, R, seed=4, dose_cap=100.0)
+    out = {}
+    try:
+        for teams in (True, False):
+            gga.set_team_options(teams)
+            out[teams] = [x.cpu().numpy() for x in gga.simulate(md, cfg, *dd, traj=True)]
+    finally:
+        gga.set_team_options(True)
+    for a, b in zip(out[True], out[False]):
+        assert np.array_equal(a, b, equal_nan=True)
+    assert np.all(out[True][0] > 0)
+
+
+def test_team_uneven_batch_with_slab_choices_everywhere(gga, model_dict):
+    """With the slab variants chosen for every side (64, 96 and 128 too), an
+    uneven batch run as teams equals the same batch run one launch per step
+    and the resident runs of the resident sides."""
+    md = high_uptake(model_dict)
+    P, K, R, seed = 14, 5, 2, 41
+    dose, gap, nfrac = workloads.random_protocols(P, K, seed=8, kmin=1)
+    lattice = np.array([64, 96, 128, 160, 192, 224, 256] * 2, np.int32)
+    horizon = np.array([20, 18, 16, 14, 12, 10, 8, 0, 20, 1, 2, 14, 3, 9], np.int32)
+    cfg = gga.make_cfg(64, 0, R, seed=seed, dose_cap=100.0)
+    dd = _dev(dose, gap, nfrac)
+    resident = gga.simulate_uneven(md, cfg, *dd, lattice, horizon)[0].cpu().numpy()
+    runs = []
+    try:
+        for L, v in ((64, 1), (96, 17), (128, 4)):
+            gga.set_variant(L, v)
+        for teams in (True, False):
+            gga.set_team_options(teams)
+            runs.append(gga.simulate_uneven(md, cfg, *dd, lattice, horizon)[0].cpu().numpy())
+    finally:
+        gga.set_team_options(True)
+        for L, v in DEFAULTS:
+            gga.set_variant(L, v)
+    assert np.array_equal(runs[0], runs[1]) and np.array_equal(runs[0], resident)
+
+
+def test_team_wait_that_runs_out_is_reported_and_every_workgroup_exits(gga, model_dict):
+    """A team whose bounded wait fails (forced from the host: every wait fails)
+    leaves negative live counts and NaN fitness for instances that needed a
+    wait (horizon >= 2), correct results for those that did not, and the
+    device keeps working: the next call with the default limit is correct."""
+    P, K, R = 3, 3, 2
+    dose, gap, nfrac = workloads.random_protocols(P, K, seed=5, kmin=1)
+    dd = _dev(dose, gap, nfrac)
+    cfg = gga.make_cfg(64, 0, R, seed=2, dose_cap=100.0)
+    lattice = np.array([256, 224, 160], np.int32)
+    horizon = np.array([6, 1, 0], np.int32)
+    ref = gga.simulate_uneven(model_dict, cfg, *dd, lattice, horizon)
+    try:
+        gga.set_team_options(True, -1)
+        live, fit = gga.simulate_uneven(model_dict, cfg, *dd, lattice, horizon)
+        live, fit = live.cpu().numpy(), fit.cpu().numpy()
+    finally:
+        gga.set_team_options(True)
+    assert np.all(live[0] < 0) and np.isnan(fit[0])
+    assert np.array_equal(live[1:], ref[0].cpu().numpy()[1:])
+    again = gga.simulate_uneven(model_dict, cfg, *dd, lattice, horizon)
+    assert torch.equal(again[0], ref[0])

@@ -90,6 +90,11 @@ constexpr SimVariant SIM_VARIANTS[] = {
     {224, 4, 4, 16, "L224 slabs of 64 rows, 4x4 x16 waves (56 of 64 lanes)"},
     {224, 4, 8, 8, "L224 slabs of 64 rows, 8x4 x8 waves (56 of 64 lanes)"},
     {96, 2, 4, 16, "L96 slabs of 64 rows, 4x2 x16 waves (48 of 64 lanes)"},
+    // three columns per lane: 192 columns, no padding at 192, 160 of 192 at 160
+    {160, 3, 4, 16, "L160 slabs of 64 rows, 4x3 x16 waves (160 of 192 columns)"},
+    {160, 3, 8, 8, "L160 slabs of 64 rows, 8x3 x8 waves (160 of 192 columns)"},
+    {192, 3, 4, 16, "L192 slabs of 64 rows, 4x3 x16 waves"},
+    {192, 3, 8, 8, "L192 slabs of 64 rows, 8x3 x8 waves"},
 };
 constexpr int N_SIM_VARIANTS = sizeof(SIM_VARIANTS) / sizeof(SIM_VARIANTS[0]);
 constexpr bool variant_is_slab(int v) { return SIM_VARIANTS[v].rpt * SIM_VARIANTS[v].nw < SIM_VARIANTS[v].L; }

@@ -226,19 +226,24 @@ __global__ void __launch_bounds__(Q3_NT) q3_fraction_kernel(Q3Args a, const floa
 // square, which its inputs fully determine), and stores the owned sites.
 // Sites outside the lattice hold 0, the boundary value in field units, and
 // every site's arithmetic is the 2D kernels' (so C = 1 reproduces them).
-constexpr int Q3_TILE = 32, Q3_TILE_NT = 512, Q3_MAX_HALO = 16;
-__host__ __device__ inline unsigned q3_tiles_per_inst(int L) {
-    const unsigned t = ((unsigned)L + Q3_TILE - 1) / Q3_TILE;
+constexpr int Q3_MAX_HALO = 16;
+constexpr int Q3_BIG_TILE_MIN_L = 128;
+__host__ __device__ inline unsigned q3_tiles_per_inst(int L, int tile) {
+    const unsigned t = ((unsigned)L + tile - 1) / tile;
     return t * t;
 }
+// rows a thread walks in the widest sub-step (w = EMAX - 2 columns, NT / w threads per column)
+constexpr int q3_run(int EMAX, int NT) { return (EMAX - 2 + NT / (EMAX - 2) - 1) / (NT / (EMAX - 2)); }
 
-template <int EMAX>
+// Tiles of Q3_TILE x Q3_TILE owned sites, EMAX the loaded side for the
+// launch's largest halo, NT threads.
+template <int Q3_TILE, int Q3_TILE_NT, int EMAX>
 __global__ void __launch_bounds__(Q3_TILE_NT) q3_diffuse_tile_kernel(Q3Args a, const float* src, float* dst, int h) {
     __shared__ float s_f[3][EMAX * EMAX];
     __shared__ float s_r[EMAX * EMAX];
     const int L = a.L, L2 = L * L;
     const int tpr = (L + Q3_TILE - 1) / Q3_TILE;
-    const unsigned tiles = q3_tiles_per_inst(L);
+    const unsigned tiles = q3_tiles_per_inst(L, Q3_TILE);
     const unsigned total = (unsigned)a.n_inst * tiles, per = (total + 7u) / 8u;
     const unsigned lb = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);     // XCD-grouped, as q3_place
     if (lb >= total) return;
@@ -287,7 +292,7 @@ __global__ void __launch_bounds__(Q3_TILE_NT) q3_diffuse_tile_kernel(Q3Args a, c
     // reads per site and field: below, west, east); the new values wait in
     // registers until every thread has read the old ones, so one LDS copy of
     // the fields serves (more workgroups per CU).
-    constexpr int RUN = EMAX <= 52 ? 5 : 8;    // ceil(w / (Q3_TILE_NT / w)) for w <= EMAX - 2
+    constexpr int RUN = q3_run(EMAX, Q3_TILE_NT);    // ceil(w / (Q3_TILE_NT / w)) for w <= EMAX - 2
     for (int k = 0; k < h; ++k) {
         const int r0 = k + 1, w = E - 2 * (k + 1);
         const int nseg = Q3_TILE_NT / w, rows = (w + nseg - 1) / nseg;
@@ -570,15 +575,25 @@ hipError_t q3_run(const Q3Args& a, int n0, int nsteps, hipStream_t stream) {
     hipLaunchKernelGGL(q3_prepare_kernel, grid, block, 0, stream, a, nsteps == 0 ? 1 : 0);
     float* cur = a.fields;
     float* oth = a.fields2;
-    const dim3 tile_grid(((unsigned)a.n_inst * q3_tiles_per_inst(a.L) + 7u) / 8u * 8u);
+    // 64 x 64 owned sites per workgroup of 1,024 threads (one per CU, 113 KB of
+    // LDS at up to 10 sub-steps) once the lattice holds four such tiles, else
+    // 32 x 32 per 512 threads (three per CU)
+    const bool big = a.L >= Q3_BIG_TILE_MIN_L;
+    const dim3 tile_grid(((unsigned)a.n_inst * q3_tiles_per_inst(a.L, big ? 64 : 32) + 7u) / 8u * 8u);
     auto diffuse = [&](int k) {
         while (k > 0) {              // sub-steps fused in LDS tiles, Q3_MAX_HALO at most per launch
             const int h = k < Q3_MAX_HALO ? k : Q3_MAX_HALO;
-            if (h <= 10)
-                hipLaunchKernelGGL(q3_diffuse_tile_kernel<Q3_TILE + 20>, tile_grid, dim3(Q3_TILE_NT), 0, stream, a,
+            if (big && h <= 10)
+                hipLaunchKernelGGL((q3_diffuse_tile_kernel<64, 1024, 64 + 20>), tile_grid, dim3(1024), 0, stream, a,
+                                   (const float*)cur, oth, h);
+            else if (big)
+                hipLaunchKernelGGL((q3_diffuse_tile_kernel<64, 1024, 64 + 2 * Q3_MAX_HALO>), tile_grid, dim3(1024), 0,
+                                   stream, a, (const float*)cur, oth, h);
+            else if (h <= 10)
+                hipLaunchKernelGGL((q3_diffuse_tile_kernel<32, 512, 32 + 20>), tile_grid, dim3(512), 0, stream, a,
                                    (const float*)cur, oth, h);
             else
-                hipLaunchKernelGGL(q3_diffuse_tile_kernel<Q3_TILE + 2 * Q3_MAX_HALO>, tile_grid, dim3(Q3_TILE_NT), 0,
+                hipLaunchKernelGGL((q3_diffuse_tile_kernel<32, 512, 32 + 2 * Q3_MAX_HALO>), tile_grid, dim3(512), 0,
                                    stream, a, (const float*)cur, oth, h);
             std::swap(cur, oth);
             k -= h;

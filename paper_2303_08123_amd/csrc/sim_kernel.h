@@ -15,10 +15,12 @@
 // so the lane shifts' zero fill at lanes 0 and 63 is exactly the missing
 // neighbour outside the lattice (the Dirichlet value is 0 in field units).
 //
-// Padding.  When LW < L (sides 96, 160, 192, 224), the lanes past the lattice
-// hold padding sites: fields 0 with a diffusion number of 0, so they stay 0
-// and the last real lane reads the boundary value from its right neighbour as
-// at lane 63; cell words EMPTY, never free and never irradiated.  Philox
+// Padding.  When LW < L the columns past the lattice hold padding sites:
+// fields 0 with a diffusion number of 0 and no clamp, so they stay 0 and the
+// last lattice column reads the boundary value from its right neighbour as
+// lane 63 does; cell words EMPTY, never free and never irradiated.  Whole
+// lanes are padding when LW is a multiple of CPL; otherwise one lane holds
+// both kinds and keeps its diffusion numbers and clamps per column.  Philox
 // counters and device-memory state use lattice coordinates (row pitch LW).
 //
 // Slabs.  A slab edge that is not a lattice edge is treated as if it were
@@ -119,7 +121,8 @@ __device__ __forceinline__ int oxygen_bin(float o_hat, const gga_params& P) {
 #pragma clang fp contract(on)
 
 // CPL consecutive uint16 cell words of one row, read or written with one
-// LDS access (the address is 2*CPL-byte aligned: x0 = lane * CPL).
+// LDS access (the address is 2*CPL-byte aligned: x0 = lane * CPL; three
+// columns per lane take one access per word).
 template <int CPL>
 __device__ __forceinline__ void load_words(const uint16_t* p, uint32_t (&w)[CPL]) {
     if constexpr (CPL == 1) {
@@ -127,8 +130,10 @@ __device__ __forceinline__ void load_words(const uint16_t* p, uint32_t (&w)[CPL]
     } else if constexpr (CPL == 2) {
         const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
         w[0] = v & 0xFFFFu; w[1] = v >> 16;
+    } else if constexpr (CPL == 3) {
+        w[0] = p[0]; w[1] = p[1]; w[2] = p[2];
     } else {
-        static_assert(CPL == 4, "CPL must be 1, 2 or 4");
+        static_assert(CPL == 4, "CPL must be 1, 2, 3 or 4");
         const uint2 v = *reinterpret_cast<const uint2*>(p);
         w[0] = v.x & 0xFFFFu; w[1] = v.x >> 16; w[2] = v.y & 0xFFFFu; w[3] = v.y >> 16;
     }
@@ -139,6 +144,8 @@ __device__ __forceinline__ void store_words(uint16_t* p, const uint32_t (&w)[CPL
         p[0] = (uint16_t)w[0];
     } else if constexpr (CPL == 2) {
         *reinterpret_cast<uint32_t*>(p) = w[0] | (w[1] << 16);
+    } else if constexpr (CPL == 3) {
+        p[0] = (uint16_t)w[0]; p[1] = (uint16_t)w[1]; p[2] = (uint16_t)w[2];
     } else {
         *reinterpret_cast<uint2*>(p) = make_uint2(w[0] | (w[1] << 16), w[2] | (w[3] << 16));
     }
@@ -176,6 +183,8 @@ __device__ __forceinline__ void store_keys(uint32_t* p, const uint32_t (&k)[CPL]
         p[0] = k[0];
     } else if constexpr (CPL == 2) {
         *reinterpret_cast<uint2*>(p) = make_uint2(k[0], k[1]);
+    } else if constexpr (CPL == 3) {
+        p[0] = k[0]; p[1] = k[1]; p[2] = k[2];
     } else {
         *reinterpret_cast<uint4*>(p) = make_uint4(k[0], k[1], k[2], k[3]);
     }
@@ -193,8 +202,8 @@ template <int CPL, int RPT, int NW, int LW = 64 * CPL>
 struct Geo {
     static constexpr int L = 64 * CPL;                // row pitch on the CU
     static constexpr int SIDE = LW;                   // lattice side
-    static constexpr bool PAD = LW < L;               // lanes past the lattice hold padding
-    static constexpr int LOG2L = CPL == 1 ? 6 : CPL == 2 ? 7 : 8;
+    static constexpr bool PAD = LW < L;               // columns past the lattice hold padding
+    static constexpr bool PADC = PAD && LW % CPL != 0; // one lane holds lattice and padding columns
     static constexpr int NWAVE = NW;
     static constexpr int RR = NW * RPT;
     static constexpr bool SLAB = RR < LW;
@@ -209,7 +218,7 @@ struct Geo {
     static constexpr int AREA = area(NBUF);
     static constexpr int POOL = (AREA > RR * L) ? AREA : RR * L;
     static_assert(RR <= LW && NWAVE <= 16, "workgroup above 1024 threads");
-    static_assert(LW <= L && LW % CPL == 0 && (1 << LOG2L) == L, "padding is whole lanes");
+    static_assert(LW <= L && L % 32 == 0, "rows of whole claim words");
     static_assert(RPT * CPL <= 32, "per-thread site masks are 32 bits wide");
     static constexpr uint32_t ALL = (RPT * CPL == 32) ? 0xFFFFFFFFu : ((1u << (RPT * CPL)) - 1u);
     // mask bits of the first / last column of every row (bit idx = i * CPL + c)
@@ -229,7 +238,7 @@ template <int CPL, int RPT, int NW, int LW, bool EXT, bool TEAM = false>
 __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     using G = Geo<CPL, RPT, NW, LW>;
     constexpr int L = G::L;
-    constexpr bool PAD = G::PAD;
+    constexpr bool PAD = G::PAD, PADC = G::PADC;
     static_assert(!TEAM || G::SLAB, "teams are made of slabs");
     constexpr int RR = G::RR;
     constexpr int NWAVE = G::NWAVE;
@@ -238,7 +247,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 
     __shared__ __attribute__((aligned(16))) uint16_t s_cell[RR * L];
     __shared__ __attribute__((aligned(16))) uint32_t s_pool[G::POOL];   // halo buffer(s), then claim slots
-    __shared__ uint32_t s_claim[RR * L / 32];  // one "has a daughter" bit per site
+    __shared__ uint32_t s_claim[RR * L / 32 + 1];  // one "has a daughter" bit per site (and a spare word)
     __shared__ uint32_t s_ev_step[GGA_KMAX];   // half-hours since step n0 (2 (n - n0), + 1 at the half hour)
     __shared__ float s_ev_dose[GGA_KMAX];
     __shared__ double s_ev_prior[GGA_KMAX];    // unrepaired dose of the earlier fractions (incomplete repair)
@@ -283,11 +292,12 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     const int nsteps = ((!SLAB || TEAM) && a.horizon) ? a.horizon[p] : a.nsteps;
     const int y0 = wave * RPT;
     const int x0 = lane * CPL;
-    const bool real = !PAD || x0 < LW;               // lanes past the lattice hold padding
+    // columns past the lattice hold padding: column x0 + c is the lattice's
+    // when realc(c); real: the lane holds at least one lattice column
+    auto realc = [&](int c) { return !PAD || x0 + c < LW; };
+    const bool real = realc(0);
     // lattice index (the Philox site counter) of slab site index `site` (pitch L)
-    auto lat_id = [&](int site) {
-        return PAD ? (site >> G::LOG2L) * LW + (site & (L - 1)) + lat0 : site + lat0;
-    };
+    auto lat_id = [&](int site) { return PAD ? (site / L) * LW + site % L + lat0 : site + lat0; };
     const gga_params& P = a.prm;
     // Philox key; `a` itself stays unmodified (a written kernel argument would
     // be copied to scratch memory)
@@ -391,32 +401,32 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             for (int i = 0; i < RPT; ++i)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
-                    F[f][i][c] = real ? src[f * plane + (size_t)(y0 + i) * LW + x0 + c] : 0.0f;
+                    F[f][i][c] = realc(c) ? src[f * plane + (size_t)(y0 + i) * LW + x0 + c] : 0.0f;
         const uint16_t* cs = a.cells + (size_t)slot * plane + lat0;
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
 #pragma unroll
             for (int c = 0; c < CPL; ++c)
-                s_cell[(y0 + i) * L + x0 + c] = real ? cs[(size_t)(y0 + i) * LW + x0 + c] : (uint16_t)0;
+                s_cell[(y0 + i) * L + x0 + c] = realc(c) ? cs[(size_t)(y0 + i) * LW + x0 + c] : (uint16_t)0;
     } else {
         const int ctr = LW / 2;
         const int rad2 = P.seed_radius * P.seed_radius;
         float f0[3];
 #pragma unroll
-        for (int f = 0; f < 3; ++f) f0[f] = real ? to_field_units(P, f, P.init[f]) : 0.0f;
+        for (int f = 0; f < 3; ++f) f0[f] = to_field_units(P, f, P.init[f]);
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) F[f][i][c] = f0[f];
+                for (int c = 0; c < CPL; ++c) F[f][i][c] = realc(c) ? f0[f] : 0.0f;
 #pragma unroll
         for (int i = 0; i < RPT; ++i)
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int y = ys + y0 + i, x = x0 + c;       // lattice row and column
                 uint16_t w = 0;
-                if (real && (x - ctr) * (x - ctr) + (y - ctr) * (y - ctr) <= rad2) {
+                if (realc(c) && (x - ctr) * (x - ctr) + (y - ctr) * (y - ctr) <= rad2) {
                     const Block4 b = philox10(y * LW + x, INIT_STEP, r, p, seed_lo, seed_hi);
                     const uint32_t age = (uint32_t)(((uint64_t)b.w0 * (uint32_t)P.A0) >> 32);
                     w = (uint16_t)(PROLIF | (age << 2));
@@ -428,15 +438,20 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
     // Per-field constants (field units, see to_field_units): the update and the
     // lower clamp of O and G (c >= 0 reads c^ >= -g / rho, rho_O = 1 and
     // rho_G > 0); the one reaction rate kappa'_O enters through s_react.
-    // Padding lanes take lam = 0 and no clamp, so their fields stay 0.
-    float lam[3], cen[3], lo[2];
+    // Padding columns take lam = 0 and no clamp, so their fields stay 0 (per
+    // column when a lane holds both kinds, else per lane).
+    constexpr int NC = PADC ? CPL : 1;
+    float lam[3][NC], cen[3], lo[2][NC];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        lam[f] = real ? P.lambda[f] : 0.0f;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) lam[f][c] = realc(c) ? P.lambda[f] : 0.0f;
         cen[f] = 1.0f - 4.0f * P.lambda[f];
     }
 #pragma unroll
-    for (int f = 0; f < 2; ++f) lo[f] = real ? to_field_units(P, f, 0.0) : -INFINITY;
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) lo[f][c] = realc(c) ? to_field_units(P, f, 0.0) : -INFINITY;
     // reaction term per cell state, -kappa'_O a[state], looked up in LDS by
     // each site's state (one LDS read instead of a chain of selects)
     if (tid < 4) s_react[tid] = -P.kappa[0] * P.activity[tid];
@@ -484,11 +499,17 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                     const int y = y0 + i;
                     if (real && (y < iy0 || y >= iy1)) {
                         uint32_t w[CPL];
-                        load_words<CPL>(cs + (size_t)y * LW + x0, w);
+                        if constexpr (PADC) {
+#pragma unroll
+                            for (int c = 0; c < CPL; ++c) w[c] = realc(c) ? cs[(size_t)y * LW + x0 + c] : 0u;
+                        } else {
+                            load_words<CPL>(cs + (size_t)y * LW + x0, w);
+                        }
 #pragma unroll
                         for (int f = 0; f < 3; ++f)
 #pragma unroll
-                            for (int c = 0; c < CPL; ++c) F[f][i][c] = src[f * plane + (size_t)y * LW + x0 + c];
+                            for (int c = 0; c < CPL; ++c)
+                                if (realc(c)) F[f][i][c] = src[f * plane + (size_t)y * LW + x0 + c];
                         store_words<CPL>(s_cell + y * L + x0, w);
                     }
                 }
@@ -539,8 +560,8 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         };
         auto update = [&](int f, int i, int c, float up, float below, float west, float east, float cur) {
             const float sum = (up + below) + (west + east);
-            float v = fmaf(lam[f], sum, fmaf(cur, cen[f], Ro[i][c]));
-            if (f < 2) v = fmaxf(v, lo[f]);
+            float v = fmaf(lam[f][PADC ? c : 0], sum, fmaf(cur, cen[f], Ro[i][c]));
+            if (f < 2) v = fmaxf(v, lo[f][PADC ? c : 0]);
             return v;
         };
         auto rotating_substep = [&](auto KC, int par) {
@@ -698,7 +719,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 #pragma unroll
             for (int i = 0; i < RPT; ++i)
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) Ro[i][c] = real ? s_react[cellp[i * L + c] & 3] : 0.0f;
+                for (int c = 0; c < CPL; ++c) Ro[i][c] = realc(c) ? s_react[cellp[i * L + c] & 3] : 0.0f;
             // (3) the sub-steps up to a fraction at the half hour, or to the end of the hour
             const int stop = (half == 0 && ev < nev && s_ev_step[ev] == rel + 1) ? a.substeps / 2 : a.substeps;
             for (; s + 2 <= stop; s += 2) {
@@ -754,7 +775,14 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         __syncthreads();   // boundary rows read, claims reset: own rows may now be rewritten
         // Per site: lysis and environment transitions, written back row by row.
         // padding sites are never free
-        const uint32_t real_m = real ? ALL_SITES : 0u;
+        uint32_t real_m = real ? ALL_SITES : 0u;
+        if constexpr (PADC) {
+            real_m = 0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) real_m |= (uint32_t)realc(c) << (i * CPL + c);
+        }
         uint32_t empty_m = real_m, cyc_m = 0, old_m = 0, alive_m = 0, doom_m = 0;
         if (__builtin_amdgcn_ballot_w64(occupied != 0u) != 0) {   // wave-uniform; else all EMPTY
             // Environment flags of the thread's sites, from the fields after the
@@ -871,7 +899,13 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         uint32_t born_m = 0;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            born_m |= ((s_claim[(own >> 5) + i * (L / 32)] >> (x0 & 31)) & ((1u << CPL) - 1u)) << (i * CPL);
+            const int wi = (own >> 5) + i * (L / 32);
+            if constexpr (32 % CPL == 0) {
+                born_m |= ((s_claim[wi] >> (x0 & 31)) & ((1u << CPL) - 1u)) << (i * CPL);
+            } else {                             // a lane's bits may run into the next word
+                const uint64_t two = (uint64_t)s_claim[wi] | ((uint64_t)s_claim[wi + 1] << 32);
+                born_m |= ((uint32_t)(two >> (x0 & 31)) & ((1u << CPL) - 1u)) << (i * CPL);
+            }
         }
         born_m &= empty_m;
         {
@@ -916,9 +950,11 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
 #pragma unroll
                         for (int f = 0; f < 3; ++f)
 #pragma unroll
-                            for (int c = 0; c < CPL; ++c) fd[f * plane + (size_t)y * LW + x0 + c] = F[f][i][c];
+                            for (int c = 0; c < CPL; ++c)
+                                if (realc(c)) fd[f * plane + (size_t)y * LW + x0 + c] = F[f][i][c];
 #pragma unroll
-                        for (int c = 0; c < CPL; ++c) cd[(size_t)y * LW + x0 + c] = s_cell[y * L + x0 + c];
+                        for (int c = 0; c < CPL; ++c)
+                            if (realc(c)) cd[(size_t)y * LW + x0 + c] = s_cell[y * L + x0 + c];
                     }
                 }
                 // every wave's rows have reached the cache hierarchy before the
@@ -932,6 +968,10 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
         }
     }
 
+    // The lane and thread index again, from the lane count: keeping them live
+    // across the step loop for the uses below would take a register.
+    const int lane_end = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const int tid_end = wave * 64 + lane_end;
     if ((!SLAB || TEAM) && nsteps == 0) {
         int live = 0;
 #pragma unroll
@@ -942,18 +982,18 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                 live += (st == PROLIF || st == QUIESC) && (!SLAB || (y0 + i >= iy0 && y0 + i < iy1));
             }
         live = wave_sum(live);
-        if (lane == 0) atomicAdd(&s_count[0], live);
+        if (lane_end == 0) atomicAdd(&s_count[0], live);
         __syncthreads();
-        if (tid == 0) count = s_count[0];
+        if (tid_end == 0) count = s_count[0];
     }
     if constexpr (TEAM) {
         // the instance's last step (or its initial state): this slab's share
-        if (tid == 0 && a.live) atomicAdd(&a.live[inst], count);
+        if (tid_end == 0 && a.live) atomicAdd(&a.live[inst], count);
     } else if constexpr (SLAB) {
         // the instance's last step: add this slab's share of the live count
-        if (tid == 0 && a.live && a.n0 + 1 == (a.horizon ? a.horizon[p] : a.count_at)) atomicAdd(&a.live[inst], count);
+        if (tid_end == 0 && a.live && a.n0 + 1 == (a.horizon ? a.horizon[p] : a.count_at)) atomicAdd(&a.live[inst], count);
     } else {
-        if (tid == 0 && a.live) a.live[inst] = count;
+        if (tid_end == 0 && a.live) a.live[inst] = count;
     }
 
     if ((SLAB && !TEAM) || (a.mode & MODE_STORE)) {
@@ -966,7 +1006,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                 if (real && (!SLAB || (y0 + i >= iy0 && y0 + i < iy1)))
 #pragma unroll
                     for (int c = 0; c < CPL; ++c)
-                        dst[f * plane + (size_t)(y0 + i) * LW + x0 + c] = F[f][i][c];
+                        if (realc(c)) dst[f * plane + (size_t)(y0 + i) * LW + x0 + c] = F[f][i][c];
         __syncthreads();
         uint16_t* cd = (SLAB ? a.cells_out : a.cells) + (size_t)slot * plane + lat0;
 #pragma unroll
@@ -974,7 +1014,7 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             if (real && (!SLAB || (y0 + i >= iy0 && y0 + i < iy1)))
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
-                    cd[(size_t)(y0 + i) * LW + x0 + c] = s_cell[(y0 + i) * L + x0 + c];
+                    if (realc(c)) cd[(size_t)(y0 + i) * LW + x0 + c] = s_cell[(y0 + i) * L + x0 + c];
     }
 }
 

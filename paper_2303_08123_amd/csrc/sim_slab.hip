@@ -126,6 +126,10 @@ hipError_t launch_slab_variant(int v, const SimArgs& a, int n_blocks, hipStream_
         case 15: return launch_slab<4, 4, 16, 224>(a, n_blocks, stream);
         case 16: return launch_slab<4, 8, 8, 224>(a, n_blocks, stream);
         case 17: return launch_slab<2, 4, 16, 96>(a, n_blocks, stream);
+        case 18: return launch_slab<3, 4, 16, 160>(a, n_blocks, stream);
+        case 19: return launch_slab<3, 8, 8, 160>(a, n_blocks, stream);
+        case 20: return launch_slab<3, 4, 16, 192>(a, n_blocks, stream);
+        case 21: return launch_slab<3, 8, 8, 192>(a, n_blocks, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -143,6 +147,10 @@ hipError_t launch_team_variant(int v, const SimArgs& a, int n_blocks, int* capac
         case 15: return launch_team<4, 4, 16, 224>(a, n_blocks, capacity, stream);
         case 16: return launch_team<4, 8, 8, 224>(a, n_blocks, capacity, stream);
         case 17: return launch_team<2, 4, 16, 96>(a, n_blocks, capacity, stream);
+        case 18: return launch_team<3, 4, 16, 160>(a, n_blocks, capacity, stream);
+        case 19: return launch_team<3, 8, 8, 160>(a, n_blocks, capacity, stream);
+        case 20: return launch_team<3, 4, 16, 192>(a, n_blocks, capacity, stream);
+        case 21: return launch_team<3, 8, 8, 192>(a, n_blocks, capacity, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -22,7 +22,7 @@ def gga():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     import paper_2303_08123_amd as g
     yield g
-    for L, v in ((64, 0), (128, 2), (256, 5)):      # the library's defaults
+    for L, v in ((64, 0), (128, 2), (256, 6)):      # the library's defaults
         g.set_variant(L, v)
 
 

@@ -119,9 +119,10 @@ def test_variants_agree_bit_for_bit(gga, model_dict, L, variants):
     assert (st50 == 3).any() and (st200 == 2).any()
 
 
-@pytest.mark.parametrize("L", [96, 224])
+@pytest.mark.parametrize("L", [96, 160, 224])
 def test_trajectory_matches_oracle(gga, model_dict, L):
-    """gga_simulate (resident at 96, slabs through its workspace at 224): the
+    """gga_simulate (resident at 96, slabs through its workspace at 160, with
+    three columns per lane, and 224): the
     live count of every step agrees with the oracle's until the oracle first
     meets a near-threshold site."""
     print(f"trajectory L={L}", flush=True)
@@ -212,6 +213,45 @@ def test_teams_equal_one_launch_per_step(gga, model_dict, L, variant):
     for a, b in zip(out[True], out[False]):
         assert np.array_equal(a, b, equal_nan=True)
     assert np.all(out[True][0] > 0)
+
+
+@pytest.mark.parametrize("teams", [True, False])
+@pytest.mark.parametrize("L", [160, 256])
+def test_slab_sides_zero_horizon_empty_batch_and_no_fractions(gga, model_dict, L, teams):
+    """Degenerate calls on the slab sides, as teams and one launch per step:
+    an empty batch returns empty outputs; a zero-step horizon returns the
+    initial disc's count (113 sites within radius 6 of the centre) for valid
+    protocols and marks an invalid one (-1 live, NaN fitness); protocols with
+    no fraction equal the oracle's unirradiated trajectory."""
+    print(f"slab degenerate cases L={L} teams={teams}", flush=True)
+    try:
+        gga.set_team_options(teams)
+        cfg = gga.make_cfg(L, 10, 2, seed=0)
+        e = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+        live, fit, _ = gga.simulate(model_dict, cfg, e, e.int(), torch.zeros(0, dtype=torch.int32, device="cuda"))
+        assert live.numel() == 0 and fit.numel() == 0
+        dose = np.array([[2.0, 0.0], [0.0, 0.0], [30.0, 30.0]], np.float32)
+        gap = np.zeros((3, 2), np.int32)
+        nfrac = np.array([1, 0, 2], np.int32)                # the last breaks the 20 Gy cap
+        live, fit, _ = gga.simulate(model_dict, gga.make_cfg(L, 0, 2, seed=0, dose_cap=20.0), *_dev(dose, gap, nfrac))
+        live, fit = live.cpu().numpy(), fit.cpu().numpy()
+        assert np.all(live[:2] == 113) and np.all(live[2] == -1)
+        assert np.all(fit[:2] == 113.0) and np.isnan(fit[2])
+        H = 30
+        z = np.zeros((2, 0), np.float32)
+        live, fit, traj = gga.simulate(model_dict, gga.make_cfg(L, H, 2, seed=5), *_dev(z, z.astype(np.int32),
+                                                                                           np.zeros(2, np.int32)),
+                                       traj=True)
+        traj = traj.cpu().numpy()
+    finally:
+        gga.set_team_options(True)
+    prm = Params.from_dict(model_dict)
+    for p in range(2):
+        for r in range(2):
+            ref, certain = oracle_certain_prefix(prm, L, H, 10, [], p, r, 5)
+            assert certain == H, (p, r, certain)
+            assert np.array_equal(traj[p, r], ref), (p, r)
+
 
 
 def test_team_uneven_batch_with_slab_choices_everywhere(gga, model_dict):

@@ -15,7 +15,7 @@ from oracle import protocol, sim
 from oracle.model import Params
 from paper_2303_08123_amd import workloads
 from parity_helpers import (FIELD_RTOL, MAX_COUNTED_FRACTION, compare_cells, field_error, from_field_units,
-                            oracle_step_detail, to_field_units)
+                            oracle_certain_prefix, oracle_step_detail, to_field_units)
 
 pytestmark = pytest.mark.gpu
 
@@ -246,3 +246,44 @@ def test_autotune_picks_a_variant_of_the_side(gga, model_dict):
     assert np.array_equal(before, after)
     gga.set_variant(64, 0)
     assert gga.get_variant(64, resident_only=True) == 0
+
+
+def test_full_size_uneven_workload(gga, model_dict):
+    """The uneven bench configuration (8192 protocols x 8 replicas, sides 64,
+    96, .., 256, 10-40 days, 3-40 fractions) with the default variants:
+    properties of every output; for the first protocol of each side, every
+    replica's count equals a uniform gga_simulate of the same protocol index,
+    whose trajectory equals the oracle's step by step until its first
+    near-threshold site (the first 150 steps at most)."""
+    wl = dict(workloads.CONFIG3)
+    P, K, R = wl["P"], wl["K"], wl["R"]
+    print("full-size uneven batch", flush=True)
+    alpha = gga.make_alphabet(wl["dose_quantum"], wl["dose_q"], wl["gaps"], wl["kmin"], K, wl["dose_cap"])
+    dose, gap, nfrac = gga.population_random(alpha, P, K, seed=3)
+    lattice, horizon = workloads.config3_shapes(P, seed=wl["seed"], sides=wl["sides"], days=wl["days"])
+    cfg = gga.make_cfg(64, 0, R, seed=wl["seed"], substeps=wl["substeps"], dose_cap=wl["dose_cap"])
+    live, fit = gga.simulate_uneven(model_dict, cfg, dose, gap, nfrac, lattice, horizon)
+    live, fit = live.cpu().numpy(), fit.cpu().numpy()
+    assert live.shape == (P, R) and fit.shape == (P,)
+    assert np.all(live >= 0) and np.all(live <= lattice.astype(np.int64)[:, None] ** 2)
+    np.testing.assert_allclose(fit, live.mean(axis=1), rtol=1e-6)
+    prm = Params.from_dict(model_dict)
+    dh, gh, nh = (x.cpu().numpy() for x in (dose, gap, nfrac))
+    certain = []
+    for L in wl["sides"]:
+        p = int(np.nonzero(lattice == L)[0][0])
+        H = int(horizon[p])
+        print(f"sampled protocol {p}: L={L} H={H}", flush=True)
+        c1 = gga.make_cfg(L, H, R, seed=wl["seed"], substeps=wl["substeps"], dose_cap=wl["dose_cap"])
+        lv, _, tr = gga.simulate(model_dict, c1, dose[:p + 1].contiguous(), gap[:p + 1].contiguous(),
+                                 nfrac[:p + 1].contiguous(), traj=True)
+        lv, tr = lv.cpu().numpy(), tr.cpu().numpy()
+        assert np.array_equal(lv[p], live[p]), (L, p)
+        ev = protocol.events(dh[p], gh[p], int(nh[p]), H, prm)
+        n = min(H, 150)
+        for r in (0, R - 1):
+            ref, c = oracle_certain_prefix(prm, L, n, wl["substeps"], ev, p, r, wl["seed"])
+            assert np.array_equal(tr[p, r, :c], ref[:c]), (L, p, r, c)
+            certain.append(c)
+    print("certain prefixes", certain)
+    assert min(certain) >= 60

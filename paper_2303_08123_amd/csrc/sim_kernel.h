@@ -492,27 +492,33 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                 }
                 const float* src = ((t & 1) ? a.fields_out : a.fields) + (size_t)slot * 3 * plane + lat0;
                 const uint16_t* cs = ((t & 1) ? a.cells_out : a.cells) + (size_t)slot * plane + lat0;
-                // per halo row: the cell words first (one load), then the
-                // fields, so that the LDS write waits for the words alone
+                // Per halo row (wave-uniform): the cell words go from the
+                // exchange straight into the LDS row by LDS DMA (lane l moves
+                // the row's 32-bit word d0 + l; padding columns past LW are
+                // not touched and stay EMPTY), so no register holds them and
+                // no LDS write waits for its load: the rows' loads are all in
+                // flight together.  The fields load into F.
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
                     const int y = y0 + i;
-                    if (real && (y < iy0 || y >= iy1)) {
-                        uint32_t w[CPL];
-                        if constexpr (PADC) {
+                    if (y < iy0 || y >= iy1) {
+                        const uint32_t* gw = reinterpret_cast<const uint32_t*>(cs + (size_t)y * LW);
+                        uint32_t* lw = reinterpret_cast<uint32_t*>(s_cell + y * L);
 #pragma unroll
-                            for (int c = 0; c < CPL; ++c) w[c] = realc(c) ? cs[(size_t)y * LW + x0 + c] : 0u;
-                        } else {
-                            load_words<CPL>(cs + (size_t)y * LW + x0, w);
+                        for (int d0 = 0; d0 < LW / 2; d0 += 64)
+                            if (d0 + lane < LW / 2)
+                                __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(gw + d0 + lane),
+                                                                 (__attribute__((address_space(3))) void*)(lw + d0), 4, 0, 0);
+                        if (real) {
+#pragma unroll
+                            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                                for (int c = 0; c < CPL; ++c)
+                                    if (realc(c)) F[f][i][c] = src[f * plane + (size_t)y * LW + x0 + c];
                         }
-#pragma unroll
-                        for (int f = 0; f < 3; ++f)
-#pragma unroll
-                            for (int c = 0; c < CPL; ++c)
-                                if (realc(c)) F[f][i][c] = src[f * plane + (size_t)y * LW + x0 + c];
-                        store_words<CPL>(s_cell + y * L + x0, w);
                     }
                 }
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the DMA writes have landed in LDS
                 __syncthreads();                          // halo cells in before anyone reads them
             }
         }

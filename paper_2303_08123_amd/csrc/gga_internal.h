@@ -95,6 +95,10 @@ constexpr SimVariant SIM_VARIANTS[] = {
     {160, 3, 8, 8, "L160 slabs of 64 rows, 8x3 x8 waves (160 of 192 columns)"},
     {192, 3, 4, 16, "L192 slabs of 64 rows, 4x3 x16 waves"},
     {192, 3, 8, 8, "L192 slabs of 64 rows, 8x3 x8 waves"},
+    // taller slabs (fewer of them per instance, so less halo recomputed)
+    {160, 3, 9, 8, "L160 slabs of 72 rows, 9x3 x8 waves (160 of 192 columns)"},
+    {192, 3, 9, 8, "L192 slabs of 72 rows, 9x3 x8 waves"},
+    {192, 3, 10, 8, "L192 slabs of 80 rows, 10x3 x8 waves"},
 };
 constexpr int N_SIM_VARIANTS = sizeof(SIM_VARIANTS) / sizeof(SIM_VARIANTS[0]);
 constexpr bool variant_is_slab(int v) { return SIM_VARIANTS[v].rpt * SIM_VARIANTS[v].nw < SIM_VARIANTS[v].L; }

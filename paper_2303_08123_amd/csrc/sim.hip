@@ -44,7 +44,7 @@ hipError_t launch_sim(const SimArgs& a, int n_blocks, hipStream_t stream) {
 
 // chosen variant per lattice side 64, 96, .., 256 (index into SIM_VARIANTS):
 // [0] any form, [1] resident only (-1: the side has no resident variant)
-std::atomic<int> g_choice[2][N_SIDES] = {{{0}, {9}, {2}, {19}, {21}, {16}, {6}},
+std::atomic<int> g_choice[2][N_SIDES] = {{{0}, {9}, {2}, {22}, {24}, {16}, {6}},
                                          {{0}, {9}, {2}, {-1}, {-1}, {-1}, {-1}}};
 
 }  // namespace

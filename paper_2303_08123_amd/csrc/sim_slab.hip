@@ -130,6 +130,9 @@ hipError_t launch_slab_variant(int v, const SimArgs& a, int n_blocks, hipStream_
         case 19: return launch_slab<3, 8, 8, 160>(a, n_blocks, stream);
         case 20: return launch_slab<3, 4, 16, 192>(a, n_blocks, stream);
         case 21: return launch_slab<3, 8, 8, 192>(a, n_blocks, stream);
+        case 22: return launch_slab<3, 9, 8, 160>(a, n_blocks, stream);
+        case 23: return launch_slab<3, 9, 8, 192>(a, n_blocks, stream);
+        case 24: return launch_slab<3, 10, 8, 192>(a, n_blocks, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -151,6 +154,9 @@ hipError_t launch_team_variant(int v, const SimArgs& a, int n_blocks, int* capac
         case 19: return launch_team<3, 8, 8, 160>(a, n_blocks, capacity, stream);
         case 20: return launch_team<3, 4, 16, 192>(a, n_blocks, capacity, stream);
         case 21: return launch_team<3, 8, 8, 192>(a, n_blocks, capacity, stream);
+        case 22: return launch_team<3, 9, 8, 160>(a, n_blocks, capacity, stream);
+        case 23: return launch_team<3, 9, 8, 192>(a, n_blocks, capacity, stream);
+        case 24: return launch_team<3, 10, 8, 192>(a, n_blocks, capacity, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -152,11 +152,12 @@ def test_mlp_work_layout_fits_the_work_buffer(gga):
 def test_variant_table_and_choices(gga):
     vs = gga.variants()
     assert [v[1] for v in vs] == [64, 64, 128, 128, 128, 256, 256, 64, 64, 96, 96, 160, 160, 192, 192, 224, 224, 96,
-                                  160, 160, 192, 192]
+                                  160, 160, 192, 192, 160, 192, 192]
     assert [v[2] for v in vs] == [False, True, False, False, True, True, True, False, False,
-                                  False, False, True, True, True, True, True, True, True, True, True, True, True]
+                                  False, False, True, True, True, True, True, True, True, True, True, True, True,
+                                  True, True, True]
     assert gga.get_variant(64) == 0 and gga.get_variant(128) == 2 and gga.get_variant(256) == 6
-    assert [gga.get_variant(L) for L in (96, 160, 192, 224)] == [9, 19, 21, 16]
+    assert [gga.get_variant(L) for L in (96, 160, 192, 224)] == [9, 22, 24, 16]
     assert gga.get_variant(128, resident_only=True) == 2 and gga.get_variant(96, resident_only=True) == 9
     for L in (160, 192, 224, 256):
         with pytest.raises(gga.GGAError):

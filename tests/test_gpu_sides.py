@@ -16,7 +16,7 @@ from parity_helpers import (FIELD_RTOL, MAX_COUNTED_FRACTION, compare_cells, fie
 
 pytestmark = pytest.mark.gpu
 
-DEFAULTS = ((64, 0), (96, 9), (128, 2), (160, 19), (192, 21), (224, 16), (256, 6))
+DEFAULTS = ((64, 0), (96, 9), (128, 2), (160, 22), (192, 24), (224, 16), (256, 6))
 
 
 @pytest.fixture(scope="module")
@@ -57,6 +57,7 @@ PROTOS = (np.array([[2.0, 3.0, 1.0], [1.5, 0.0, 2.5]], np.float32),
     (96, 9, False), (96, 9, True), (96, 10, True), (96, 17, True),
     (160, 11, True), (192, 14, True), (224, 15, False), (224, 15, True), (224, 16, True),
     (160, 18, True), (160, 19, False), (160, 19, True), (192, 20, True), (192, 21, False), (192, 21, True),
+    (160, 22, True), (192, 23, True), (192, 24, False), (192, 24, True),
 ])
 def test_single_step_parity(gga, model_dict, L, variant, event):
     """One step from an identical grown state: fields within 1e-5 relative,
@@ -92,7 +93,7 @@ def test_single_step_parity(gga, model_dict, L, variant, event):
     assert ((cells & 3) == 2).any() and ((cells & 3) == 3).any()   # quiescent and dead cells took part
 
 
-@pytest.mark.parametrize("L,variants", [(96, (9, 10, 17)), (160, (11, 12, 18, 19)), (192, (13, 14, 20, 21)),
+@pytest.mark.parametrize("L,variants", [(96, (9, 10, 17)), (160, (11, 12, 18, 19, 22)), (192, (13, 14, 20, 21, 23, 24)),
                                         (224, (15, 16))])
 def test_variants_agree_bit_for_bit(gga, model_dict, L, variants):
     """Resident and slab variants of one side, from one state, over two
@@ -189,7 +190,8 @@ def test_uneven_batch_of_all_seven_sides(gga, model_dict):
 
 
 
-@pytest.mark.parametrize("L,variant", [(160, 12), (160, 19), (192, 14), (192, 21), (224, 16), (256, 6)])
+@pytest.mark.parametrize("L,variant", [(160, 12), (160, 19), (160, 22), (192, 14), (192, 21), (192, 23), (192, 24),
+                                       (224, 16), (256, 6)])
 def test_teams_equal_one_launch_per_step(gga, model_dict, L, variant):
     """The team form (slabs co-resident for the whole horizon, halo rows
     exchanged through device memory) gives the per-step slab form's results

@@ -25,7 +25,7 @@ def gga():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     import paper_2303_08123_amd as g
     yield g
-    for L, v in ((64, 0), (96, 9), (128, 2), (160, 19), (192, 21), (224, 16), (256, 6)):   # the library's defaults
+    for L, v in ((64, 0), (96, 9), (128, 2), (160, 22), (192, 24), (224, 16), (256, 6)):   # the library's defaults
         g.set_variant(L, v)
 
 

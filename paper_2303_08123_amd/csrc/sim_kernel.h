@@ -738,6 +738,28 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             }
             if (stop == a.substeps) break;
         }
+        if constexpr (TEAM) {
+            // The fields of the rows the neighbours hold as halo are final
+            // now (the cell update does not change them): their stores go out
+            // here and drain during the cell update; the cell words and the
+            // step count follow it.
+            if (n + 1 < a.n0 + nsteps) {
+                const int t1 = n + 1 - a.n0;
+                float* fd = ((t1 & 1) ? a.fields_out : a.fields) + (size_t)slot * 3 * plane + lat0;
+                const int exA = a.slab_exA[slab], exB = a.slab_exB[slab];
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const int y = y0 + i;
+                    if (real && y >= iy0 && y < iy1 && (y < exA || y >= exB)) {
+#pragma unroll
+                        for (int f = 0; f < 3; ++f)
+#pragma unroll
+                            for (int c = 0; c < CPL; ++c)
+                                if (realc(c)) fd[f * plane + (size_t)y * LW + x0 + c] = F[f][i][c];
+                    }
+                }
+            }
+        }
 
         // (4) cell update, bit-parallel over the thread's RPT x CPL sites
         // (bit idx = i * CPL + c of 32-bit masks).  Proposers claim an EMPTY
@@ -943,21 +965,17 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
             if (SLAB && a.traj) atomicAdd(&a.traj[(size_t)inst * a.count_at + n], count);
         }
         if constexpr (TEAM) {
-            // publish the own rows the neighbours hold as halo, then the step count
+            // publish the cell words of the own rows the neighbours hold as
+            // halo (their fields went out after the sub-steps), then the step
+            // count
             if (n + 1 < a.n0 + nsteps) {
                 const int t1 = n + 1 - a.n0;
-                float* fd = ((t1 & 1) ? a.fields_out : a.fields) + (size_t)slot * 3 * plane + lat0;
                 uint16_t* cd = ((t1 & 1) ? a.cells_out : a.cells) + (size_t)slot * plane + lat0;
                 const int exA = a.slab_exA[slab], exB = a.slab_exB[slab];
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
                     const int y = y0 + i;
                     if (real && y >= iy0 && y < iy1 && (y < exA || y >= exB)) {
-#pragma unroll
-                        for (int f = 0; f < 3; ++f)
-#pragma unroll
-                            for (int c = 0; c < CPL; ++c)
-                                if (realc(c)) fd[f * plane + (size_t)y * LW + x0 + c] = F[f][i][c];
 #pragma unroll
                         for (int c = 0; c < CPL; ++c)
                             if (realc(c)) cd[(size_t)y * LW + x0 + c] = s_cell[y * L + x0 + c];

@@ -221,9 +221,12 @@ size_t gga_workspace_bytes(const gga_sim_cfg* cfg, int32_t P);
  *   fitness_d[P]     mean of live over replicas (the fitness to minimise; the
  *                    paper's score is L*L - fitness)
  *   traj_d[P][R][horizon]  live count after every step, or NULL
- * Resident sides run one launch for the whole horizon; the other sides one
- * launch per step over slabs of rows (results bit-identical to a resident
- * run of the same lattice, see the kernel variants below).
+ * Resident sides run one launch for the whole horizon; the other sides run
+ * over slabs of rows, as teams of co-resident slab workgroups that keep their
+ * rows on the compute units for the whole horizon (or, with the team form
+ * switched off by gga_set_team_options, one launch per step); results are
+ * bit-identical to a resident run of the same lattice (see the kernel
+ * variants below).
  * A protocol that breaks a GGA_PROTO_* rule is not simulated: its live entries
  * are -1 and its fitness is NaN.
  * Errors: GGA_E_ARG (also a missing or small workspace), GGA_E_ABI,

@@ -704,8 +704,10 @@ int gga_set_team_options(int32_t use_teams, int32_t spin_limit);
  * gga_simulate for a batch whose protocol p runs on a lattice_h[p] x
  * lattice_h[p] lattice for horizon_h[p] steps (HOST arrays; cfg->L and
  * cfg->horizon are not used).  Instances are grouped by lattice side and
- * launched longest horizon first; slab-form groups take one launch per step
- * over the instances still running.  live_d[P][R], fitness_d[P] as
+ * launched longest horizon first; slab-form groups run as teams (cooperative
+ * launches of as many instances as the device holds at once, each instance's
+ * slabs resident for its whole horizon), or with the team form switched off
+ * take one launch per step over the instances still running.  live_d[P][R], fitness_d[P] as
  * gga_simulate (-1 / NaN for invalid protocols).  The instance order is
  * uploaded from host memory, and the call waits for that copy (and the work
  * already on `stream`) before enqueueing the kernels; it returns without

@@ -392,7 +392,7 @@ int gga::simulate_checked(const gga_params* params, const gga_sim_cfg* cfg, cons
         a.nsteps = cfg->horizon;
         a.mode = 0;
         e = gga::launch_simulation(a, cfg->L, P * cfg->R, stream);
-    } else {                                         // slabs: state in the workspace, one launch per step
+    } else {                                         // slabs: state in the workspace, as teams or per step
         const SimWs w = simulate_ws_layout(cfg->L, cfg->substeps, P, cfg->R);
         if (!ws_d || misaligned16(ws_d) || ws_bytes < w.total) return GGA_E_ARG;
         if (traj_d && (long long)P * cfg->R * cfg->horizon > std::numeric_limits<int32_t>::max()) return GGA_E_ARG;

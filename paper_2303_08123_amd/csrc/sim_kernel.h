@@ -471,16 +471,19 @@ __global__ __launch_bounds__(64 * NW) void sim_kernel(SimArgs a) {
                 // caches on every iteration).  The compute unit's caches are
                 // shared by the workgroup's waves, and none of them reads the
                 // exchange rows before the barrier that follows the fence.
+                // Both neighbours' counts are read in each poll, so a poll that
+                // finds both published costs one memory round trip.
                 if (tid == 0) {
                     int ok = a.spin_limit >= 0;
-                    for (int nb = slab - 1; ok && nb <= slab + 1; nb += 2) {
-                        if (nb < 0 || nb >= a.n_slabs) continue;
-                        const int32_t* f = a.team_flags + (size_t)slot * a.n_slabs + nb;
-                        int k = 0;
-                        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < t) {
-                            if (++k > a.spin_limit) { ok = 0; break; }
-                            __builtin_amdgcn_s_sleep(1);
-                        }
+                    const int32_t* flags = a.team_flags + (size_t)slot * a.n_slabs;
+                    const bool up = slab > 0, dn = slab + 1 < a.n_slabs;
+                    int k = 0;
+                    while (ok) {
+                        const int fu = up ? __hip_atomic_load(flags + slab - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : t;
+                        const int fd = dn ? __hip_atomic_load(flags + slab + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : t;
+                        if (fu >= t && fd >= t) break;
+                        if (++k > a.spin_limit) { ok = 0; break; }
+                        __builtin_amdgcn_s_sleep(1);
                     }
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     s_team_ok = ok;
